@@ -1,0 +1,214 @@
+/*
+ * tomo.h — C ABI of libtomo, a gfx950 (MI355X) implementation of the Toeplitz
+ * MBIR hot path of "Fast Large-Scale Model-Based Iterative Tomography via
+ * Exploiting Mathematical Structure, Hierarchical Optimization, Smart
+ * Initialization, and Distributed GPU Computing" (arXiv 2603.28756).
+ *
+ * Problem (Sec. 2, Eq. 5): minimise over the image f
+ *     F(f) = 1/2 || R f - g ||^2 + beta * Phi(f)
+ * for parallel-beam projections g, with R f evaluated through its Fourier
+ * form (Eqs. 3-4), R*R applied as a padded-FFT Toeplitz convolution with a
+ * precomputed point-spread function (Sec. 2.1, Eqs. 7-11), an edge-preserving
+ * qGGMRF prior Phi coupling each voxel to 8 (2D) or 26 (3D) neighbours
+ * (Sec. 2 and Sec. 2.4), an accelerated gradient method with restart
+ * (Sec. 2), a ramp-filtered back-projection start (Sec. 2.2) and a
+ * coarse-to-fine grid hierarchy with Lanczos prolongation (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units are pixels; a detector bin is one pixel wide.  Pixel (m_y, m_x) of an
+ * N x N slice has centre (m_x - N/2, m_y - N/2); detector bin j sits at
+ * t_j = j - c (c = rotation-centre bin); the projection at angle theta
+ * integrates along x cos(theta) + y sin(theta) = t.
+ *
+ * Device arrays are row-major, contiguous, float32, and at least 256-byte
+ * aligned:
+ *   image / volume   [n_slices][N][N]           (row = y, column = x)
+ *   sinogram         [n_slices][n_angles][n_det]
+ * The caller owns every device buffer, including the workspace (typically
+ * allocated with PyTorch).  The library never allocates or frees device
+ * memory.  Host arrays passed in are copied before the call returns.
+ *
+ * All work is enqueued on the plan's HIP stream and is asynchronous with
+ * respect to the host unless stated otherwise.  A plan is not thread-safe;
+ * distinct plans are independent.
+ *
+ * Errors are reported by status code only (no exceptions, no abort);
+ * tomo_last_error() returns a per-plan message for the last failure.
+ */
+#ifndef TOMO_H
+#define TOMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TOMO_OK = 0,
+  TOMO_ERR_INVALID_ARG = 1,        /* bad size, pointer, alignment or parameter       */
+  TOMO_ERR_NO_DEVICE = 2,          /* no HIP device visible                           */
+  TOMO_ERR_UNSUPPORTED_ARCH = 3,   /* current device is not gfx950                    */
+  TOMO_ERR_NO_WORKSPACE = 4,       /* tomo_plan_set_workspace() not called            */
+  TOMO_ERR_WORKSPACE_TOO_SMALL = 5,/* workspace smaller than tomo_plan_workspace_size */
+  TOMO_ERR_NOT_READY = 6,          /* call order: PSF not precomputed yet             */
+  TOMO_ERR_HIP = 7,                /* a HIP runtime call failed                       */
+  TOMO_ERR_NONFINITE = 8,          /* NaN/Inf met in the input or the iteration       */
+  TOMO_ERR_INTERNAL = 9
+} tomo_status;
+
+typedef struct tomo_plan_s* tomo_plan;
+
+/* Initial estimate of the coarsest level (tomo_recon_opts_t.init). */
+enum {
+  TOMO_INIT_FBP = 0,   /* ramp-filtered back-projection, Sec. 2.2                    */
+  TOMO_INIT_ZERO = 1,  /* constant zero image                                       */
+  TOMO_INIT_USER = 2   /* caller's image, read from x before iterating              */
+};
+
+/* Geometry, discretisation and prior of one reconstruction problem.  All
+ * fields are host values; the angle array is copied by tomo_plan_create(). */
+typedef struct {
+  int32_t n;              /* N: slice width in pixels, even, 16 <= N <= 2048               */
+  int32_t n_slices;       /* number of slices along the rotation axis, >= 1               */
+  int32_t n_angles;       /* projections per slice, >= 1                                  */
+  int32_t n_det;          /* detector bins per projection, even, >= 4                     */
+  const double* angles;   /* host [n_angles] radians; NULL -> theta_i = i*pi/n_angles      */
+  double center;          /* rotation-centre bin c; NaN -> n_det/2                         */
+  int32_t pad;            /* FFT size P of the Toeplitz product: 0 -> the smallest power of
+                             two >= 2N; otherwise a power of two >= 2N (Sec. 2.1 asks for
+                             >= 2N-1; every such P gives the same result)                 */
+  int32_t n_levels;       /* grid levels of the hierarchy (Sec. 2.3), 1..6; level l has
+                             N/2^(L-1-l) pixels and n_det/2^(L-1-l) bins; 0 -> 1          */
+  int32_t kb_width;       /* Kaiser-Bessel gridding kernel width W in grid cells, 2..16;
+                             0 -> 6                                                        */
+  double kb_oversamp;     /* gridding oversampling sigma >= 1.25 (the grid is the next
+                             power of two >= sigma*N); 0 -> 2                              */
+  double kb_beta;         /* KB shape; 0 -> pi*sqrt((W/s)^2 (s-1/2)^2 - 0.8) with s the
+                             effective oversampling (Beatty et al. 2005)                   */
+  double beta;            /* prior weight beta >= 0                                        */
+  double p, q;            /* qGGMRF exponents, 1 <= p <= q = 2                             */
+  double sigma;           /* qGGMRF scale sigma > 0                                        */
+  double T;               /* qGGMRF threshold T > 0                                        */
+  int32_t neighbours;     /* 8 (in-plane) or 26 (3D)                                       */
+  uint32_t flags;         /* reserved, must be 0                                           */
+} tomo_geometry_t;
+
+/* Options of tomo_reconstruct(). */
+typedef struct {
+  const int32_t* iters;   /* host [n_levels]: iterations per level, coarse -> fine, >= 0  */
+  int32_t init;           /* TOMO_INIT_*                                                   */
+  int32_t restart;        /* 1: gradient-mapping restart test on; 0: plain FISTA           */
+  double L_override;      /* > 0: use this step constant on every level instead of the
+                             computed one                                                  */
+  double* objective_dev;  /* nullable device float64[sum(iters)]: F(y_k) per iteration,
+                             the objective at the point where iteration k evaluates its
+                             gradient (computing it costs extra prior work)                */
+  int32_t* restart_dev;   /* nullable device int32[sum(iters)]: 1 where restart fired     */
+} tomo_recon_opts_t;
+
+/* Host-side summary filled by tomo_reconstruct() when non-NULL. */
+typedef struct {
+  double L[6];            /* step constant used on each level                               */
+  double lambda_pow[6];   /* power-iteration estimate of the largest eigenvalue of R*R     */
+  int32_t n_restarts;     /* restarts over all levels                                       */
+  int32_t nonfinite_iter; /* first global iteration with a non-finite value, or -1          */
+} tomo_recon_stats_t;
+
+/* Validate `geom`, bind the plan to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the default stream), and size its workspace.
+ * Sec. 2 (problem statement) and Sec. 2.3 (levels).  Nothing is enqueued.
+ * Errors: INVALID_ARG (any field out of range, NULL geom/out), NO_DEVICE,
+ * UNSUPPORTED_ARCH, HIP.  On error *out is set to NULL. */
+tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo_plan* out);
+
+/* Bytes of device workspace the plan needs (all levels, all buffers). */
+tomo_status tomo_plan_workspace_size(tomo_plan plan, size_t* bytes);
+
+/* Attach caller-owned device memory of `bytes` bytes (>= workspace size,
+ * 256-byte aligned).  The plan keeps the pointer until destroyed or re-attached;
+ * re-attaching invalidates precomputed data (call tomo_precompute_psf again).
+ * Errors: INVALID_ARG (NULL, misaligned), WORKSPACE_TOO_SMALL. */
+tomo_status tomo_plan_set_workspace(tomo_plan plan, void* dev, size_t bytes);
+
+/* Precompute, once per geometry and for every level, the spectrum F K of the
+ * point-spread function K = NUFFT1(1) (Sec. 2.1, Eqs. 8-9; the spreading of
+ * the all-ones function onto the oversampled grid, the grid FFT, the crop and
+ * deapodisation, and the padded FFT all run in float64), and the step constant
+ * L = 1.01 * lambda_pow + 2 beta rho''(0), lambda_pow from 30 power iterations
+ * of R*R from the all-ones image with float64 norms (Sec. 2, Eq. 6).
+ * Errors: NO_WORKSPACE, HIP. */
+tomo_status tomo_precompute_psf(tomo_plan plan);
+
+/* out = R* g (ramp = 0) or the ramp-filtered back-projection
+ * (pi/n_angles) R* h g (ramp = 1, Sec. 2.2, Eqs. 12-14) on the finest grid:
+ * radial DFT of each projection, optional |omega| ramp, Kaiser-Bessel gridding
+ * onto the oversampled grid (Eq. 4), inverse grid FFT, crop and deapodisation.
+ * sino: device [n_slices][n_angles][n_det]; out: device [n_slices][N][N].
+ * Errors: INVALID_ARG (NULL/misaligned), NO_WORKSPACE, HIP. */
+tomo_status tomo_backproject(tomo_plan plan, const float* sino, float* out, int ramp);
+
+/* out = R*R x = Res(F^-1(F K . F Pad x)) on the finest grid (Sec. 2.1, Eq. 9).
+ * x, out: device [n_slices][N][N], distinct.
+ * Errors: INVALID_ARG, NO_WORKSPACE, NOT_READY (PSF not precomputed), HIP. */
+tomo_status tomo_apply_normal(tomo_plan plan, const float* x, float* out);
+
+/* grad = R*R x - b + beta grad Phi(x) on the finest grid (Sec. 2.1, Eq. 11,
+ * plus the prior term of Eq. 5).  b is normally R* g from tomo_backproject.
+ * x, b, grad: device [n_slices][N][N]; grad must not alias x or b.
+ * obj_dev: nullable device float64[1] receiving
+ *   1/2 <x, R*R x> - <x, b> + beta Phi(x)
+ * (Eq. 10 without its constant 1/2 <g, g>).
+ * Errors: INVALID_ARG, NO_WORKSPACE, NOT_READY, HIP. */
+tomo_status tomo_gradient(tomo_plan plan, const float* x, const float* b, float* grad,
+                          double* obj_dev);
+
+/* Full reconstruction of `sino` into `x` through the grid hierarchy: per level
+ * (coarse to fine) the projections are subsampled (every s-th bin, divided by
+ * s), b = R* g is formed, the start is FBP / zero / the caller's image on the
+ * coarsest level and the Lanczos-3 prolongation of the previous level above
+ * it, and `iters[l]` accelerated gradient iterations with optional restart are
+ * run (Sec. 2, Sec. 2.2, Sec. 2.3).  Computes the PSF first if it is not ready.
+ * sino: device [n_slices][n_angles][n_det].
+ * x: device [n_slices][N][N] output; with TOMO_INIT_USER it is first read as
+ *    the coarsest-level start image [n_slices][N_0][N_0] (contiguous).
+ * stats_host: nullable; when given the call synchronises the plan's stream
+ *    and fills it.  Without it, a non-finite iteration is not detected.
+ * Errors: INVALID_ARG, NO_WORKSPACE, HIP, NONFINITE (only with stats_host). */
+tomo_status tomo_reconstruct(tomo_plan plan, const float* sino, float* x,
+                             const tomo_recon_opts_t* opts, tomo_recon_stats_t* stats_host);
+
+/* Copy level `level`'s PSF spectrum F K (float32, unnormalised) into the
+ * caller's device array [P_l][P_l/2 + 1] (row = vertical frequency v,
+ * column = horizontal frequency u = 0..P_l/2), and its step constants into
+ * host doubles (each nullable).  Errors: INVALID_ARG, NOT_READY, HIP. */
+tomo_status tomo_psf_info(tomo_plan plan, int32_t level, float* fk_dev, double* L_host,
+                          double* lambda_host);
+
+/* Level geometry: N_l, n_det_l and P_l of level `level` (host out-params). */
+tomo_status tomo_level_dims(tomo_plan plan, int32_t level, int32_t* n, int32_t* n_det,
+                            int32_t* pad);
+
+/* Plan-free utility: separable 2x Lanczos-3 prolongation of each slice
+ * (Sec. 2.3, Eqs. 16-17, normalised by the tap sum), enqueued on hip_stream.
+ * in: device [n_slices][n][n]; out: device [n_slices][2n][2n].
+ * Errors: INVALID_ARG, HIP. */
+tomo_status tomo_lanczos_prolong(const float* in, float* out, int32_t n, int32_t n_slices,
+                                 void* hip_stream);
+
+/* Destroy a plan (NULL is accepted).  Does not free the caller's workspace. */
+tomo_status tomo_plan_destroy(tomo_plan plan);
+
+/* Static description of a status code. */
+const char* tomo_status_string(tomo_status s);
+
+/* Message of the plan's last failure ("" if none; NULL plan -> last global error). */
+const char* tomo_last_error(tomo_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOMO_H */

@@ -1,0 +1,640 @@
+// Back-projection R* g and point-spread-function precompute on gfx950.
+//
+// Sec. 2, Eq. 4: R* g = NUFFT1( F g ) — a 1D DFT along each projection's radial
+// axis, then the adjoint non-uniform transform from the polar samples
+// k_il = (l / n_det)(cos theta_i, sin theta_i) to the image grid.
+// Sec. 2.1: K = NUFFT1(1) on the polar samples, needed on [-(N-1), N-1]^2, and
+// its padded spectrum F K, computed once before iterating.
+//
+// NUFFT1 is evaluated by Kaiser-Bessel gridding: each sample is spread onto an
+// oversampled M x M grid with the separable kernel
+// phi(u) = I0(beta sqrt(1 - (2u/W)^2)), |u| < W/2, the grid is inverse-FFT'd,
+// cropped, and divided by the kernel's Fourier transform
+// phi^(xi) = W sinh(sqrt(beta^2 - (pi W xi)^2)) / sqrt(beta^2 - (pi W xi)^2).
+//
+// Spreading is a deterministic gather with no atomics: the samples of one angle
+// lie on a line sorted by l, so each grid cell finds, per angle, the contiguous
+// range of l whose footprints can reach it, and tests exact membership against
+// the integer footprint origin stored per sample.  The per-sample 1D weights
+// are tabulated once per geometry (float64).
+#include "common.hpp"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace tomo {
+namespace {
+
+// Modified Bessel function I0 from its power series sum_k ((x/2)^k / k!)^2 (float64).
+__device__ double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+__device__ double kb_phi(double u, int W, double beta) {
+  const double h = 0.5 * W;
+  if (fabs(u) >= h) return 0.0;
+  const double r = 2.0 * u / W;
+  return bessel_i0(beta * sqrt(1.0 - r * r));
+}
+
+__device__ double kb_phihat(double xi, int W, double beta) {
+  const double a = M_PI * W * xi;
+  const double s2 = beta * beta - a * a;
+  if (s2 > 1e-12) {
+    const double s = sqrt(s2);
+    return W * sinh(s) / s;
+  }
+  if (s2 < -1e-12) {
+    const double s = sqrt(-s2);
+    return W * sin(s) / s;
+  }
+  return (double)W;
+}
+
+// ------------------------------------------------------------------------------- tables
+template <typename T>
+__global__ void twiddle_kernel(cpx<T>* tw, int P) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= P) return;
+  double s, c;
+  sincospi(2.0 * (double)m / (double)P, &s, &c);
+  tw[m] = mk((T)c, (T)(-s));
+}
+
+__global__ void fill_kernel(float* x, idx_t n, float v) {
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ void set_scalars_kernel(double* scal, int first, int count, const double* src,
+                                   double v) {
+  const int i = threadIdx.x;
+  if (i < count) scal[first + i] = src ? src[i] : v;
+}
+
+__global__ void angle_table_kernel(const double* ang, double* tab, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s, c;
+  sincos(ang[i], &s, &c);
+  tab[2 * i] = c;
+  tab[2 * i + 1] = s;
+}
+
+// DFT table tab[m] = exp(-2 pi i m / nd) and per-frequency factor
+// post[l] = (1/nd)(1/stride) exp(+2 pi i l c / nd) * (ramp ? pi |l| / (nd n_angles) : 1).
+__global__ void radial_tables_kernel(cpx<float>* tab, cpx<float>* post, int nd, double c,
+                                     int stride, int n_angles, int ramp) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < nd) {
+    double s, co;
+    sincospi(2.0 * (double)m / (double)nd, &s, &co);
+    tab[m] = mk((float)co, (float)(-s));
+  }
+  if (m < nd - 1) {
+    const int l = m - (nd / 2 - 1);
+    double s, co;
+    sincospi(2.0 * (double)l * c / (double)nd, &s, &co);
+    double f = 1.0 / ((double)nd * (double)stride);
+    if (ramp) f *= M_PI * fabs((double)l) / ((double)nd * (double)n_angles);
+    post[m] = mk((float)(co * f), (float)(s * f));
+  }
+}
+
+// G[row][l] = post[l] * sum_j g[row][j*stride] exp(-2 pi i l j / nd), rows = (slice, angle).
+constexpr int RD_ROWS = 16, RD_JC = 256;
+__global__ void __launch_bounds__(256)
+radial_dft_kernel(const float* __restrict__ sino, int nd_full, int nd, int stride, int rows,
+                  cpx<float>* __restrict__ ghat, const cpx<float>* __restrict__ tab,
+                  const cpx<float>* __restrict__ post) {
+  __shared__ float gt[RD_ROWS][RD_JC];
+  const int t = threadIdx.x;
+  const int nl = nd - 1;
+  const int lidx = blockIdx.x * 256 + t;
+  const int l = lidx - (nd / 2 - 1);
+  const int lpos = ((l % nd) + nd) % nd;
+  const int row0 = blockIdx.y * RD_ROWS;
+  float ar[RD_ROWS], ai[RD_ROWS];
+#pragma unroll
+  for (int r = 0; r < RD_ROWS; ++r) ar[r] = ai[r] = 0.f;
+  for (int j0 = 0; j0 < nd; j0 += RD_JC) {
+    for (int e = t; e < RD_ROWS * RD_JC; e += 256) {
+      const int rr = e / RD_JC, jj = e - rr * RD_JC;
+      const int row = row0 + rr, j = j0 + jj;
+      gt[rr][jj] = (row < rows && j < nd) ? sino[(idx_t)row * nd_full + (idx_t)j * stride] : 0.f;
+    }
+    __syncthreads();
+    int idx = (int)(((long long)lpos * (long long)j0) % nd);
+    const int jn = min(RD_JC, nd - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const cpx<float> w = tab[idx];
+      idx += lpos;
+      if (idx >= nd) idx -= nd;
+#pragma unroll
+      for (int r = 0; r < RD_ROWS; ++r) {
+        const float g = gt[r][jj];
+        ar[r] += g * w.re;
+        ai[r] += g * w.im;
+      }
+    }
+    __syncthreads();
+  }
+  if (lidx < nl) {
+    const cpx<float> f = post[lidx];
+#pragma unroll
+    for (int r = 0; r < RD_ROWS; ++r) {
+      const int row = row0 + r;
+      if (row < rows) ghat[(idx_t)row * nl + lidx] = cmul(mk(ar[r], ai[r]), f);
+    }
+  }
+}
+
+// Per-sample footprint origin and 1D kernel weights on an M-grid (grid units).
+template <typename T>
+__global__ void point_table_kernel(const double* __restrict__ atab, int2* __restrict__ g0,
+                                   T* __restrict__ wx, T* __restrict__ wy, int nd, int n_angles,
+                                   int M, int W, double beta) {
+  const int nl = nd - 1;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_angles * nl) return;
+  const int i = p / nl, lidx = p - i * nl;
+  const int l = lidx - (nd / 2 - 1);
+  const double d = (double)M / (double)nd;
+  const double kx = (double)l * d * atab[2 * i];
+  const double ky = (double)l * d * atab[2 * i + 1];
+  const int ox = (int)floor(kx - 0.5 * W) + 1;
+  const int oy = (int)floor(ky - 0.5 * W) + 1;
+  g0[p] = make_int2(ox, oy);
+  for (int a = 0; a < W; ++a) {
+    wx[(idx_t)p * W + a] = (T)kb_phi((double)(ox + a) - kx, W, beta);
+    wy[(idx_t)p * W + a] = (T)kb_phi((double)(oy + a) - ky, W, beta);
+  }
+}
+
+// Gather-spread: H[z][iy][ix] = sum over samples p whose footprint covers cell (ix, iy)
+// of wx[p][ix - g0x] wy[p][iy - g0y] c[z][p], grid index = frequency mod M.
+template <typename T, int ZB, bool CONST>
+__global__ void __launch_bounds__(256)
+spread_kernel(const cpx<T>* __restrict__ vals, cpx<T>* __restrict__ grid,
+              const double* __restrict__ atab, const int2* __restrict__ g0,
+              const T* __restrict__ wx, const T* __restrict__ wy, int M, int nd, int n_angles,
+              int W, int z0, int nzb, idx_t slice_pts, T const_val) {
+  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (idx_t)M * M) return;
+  const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
+  const int half = M / 2;
+  const int gx = ix < half ? ix : ix - M;
+  const int gy = iy < half ? iy : iy - M;
+  const int nl = nd - 1, lmax = nd / 2 - 1;
+  const float step = (float)M / (float)nd;
+  const float hw = 0.5f * (float)W + 1.5f;
+  const float reach = (float)half + hw;
+
+  T ar[ZB], ai[ZB];
+#pragma unroll
+  for (int z = 0; z < ZB; ++z) ar[z] = ai[z] = (T)0;
+
+  for (int sx = -1; sx <= 1; ++sx) {
+    const int gxp = gx + sx * M;
+    if (fabsf((float)gxp) > reach) continue;
+    for (int sy = -1; sy <= 1; ++sy) {
+      const int gyp = gy + sy * M;
+      if (fabsf((float)gyp) > reach) continue;
+      for (int i = 0; i < n_angles; ++i) {
+        const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
+        float lo = (float)(-lmax), hi = (float)lmax;
+        if (fabsf(cx) > 1e-6f) {
+          const float a = ((float)gxp - hw) / cx, b = ((float)gxp + hw) / cx;
+          lo = fmaxf(lo, fminf(a, b));
+          hi = fminf(hi, fmaxf(a, b));
+        } else if (fabsf((float)gxp) > hw) {
+          continue;
+        }
+        if (fabsf(cy) > 1e-6f) {
+          const float a = ((float)gyp - hw) / cy, b = ((float)gyp + hw) / cy;
+          lo = fmaxf(lo, fminf(a, b));
+          hi = fminf(hi, fmaxf(a, b));
+        } else if (fabsf((float)gyp) > hw) {
+          continue;
+        }
+        const int l0 = (int)ceilf(lo), l1 = (int)floorf(hi);
+        for (int l = l0; l <= l1; ++l) {
+          const int p = i * nl + (l + lmax);
+          const int2 o = g0[p];
+          const int ox = gxp - o.x, oy = gyp - o.y;
+          if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W) {
+            const T w = wx[(idx_t)p * W + ox] * wy[(idx_t)p * W + oy];
+            if constexpr (CONST) {
+              ar[0] += w * const_val;
+            } else {
+#pragma unroll
+              for (int z = 0; z < ZB; ++z) {
+                if (z < nzb) {
+                  const cpx<T> c = vals[(idx_t)(z0 + z) * slice_pts + p];
+                  ar[z] += w * c.re;
+                  ai[z] += w * c.im;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < ZB; ++z)
+    if (z < nzb) grid[(idx_t)z * M * M + cell] = mk(ar[z], ai[z]);
+}
+
+// ------------------------------------------------------------------- generic 2D C2C FFT
+template <typename T>
+constexpr int fftE() { return sizeof(T) == 8 ? 8 : 16; }
+
+template <typename T, int P, int ROWS, int DIR>
+__global__ void __launch_bounds__(ROWS * (P / fftE<T>()))
+fft_rows_kernel(cpx<T>* __restrict__ data, idx_t n_rows, const cpx<T>* __restrict__ tw) {
+  using PL = fft::Plan<P, fftE<T>()>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  constexpr int REG = fft::row_region<P>();
+  __shared__ cpx<T> lds[ROWS * REG];
+  const int t = threadIdx.x, rr = t / TPF, q = t - rr * TPF;
+  const idx_t row = (idx_t)blockIdx.x * ROWS + rr;
+  const bool active = row < n_rows;
+  cpx<T>* d = data + (active ? row : 0) * P;
+  cpx<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+    for (int r = 0; r < R0; ++r)
+      v[m * R0 + r] = active ? d[fft::reg_pos<P, TPF, R0>(q, m, r)] : mk((T)0, (T)0);
+  fft::LdsRow<T> L{lds + rr * REG};
+  fft::run_stages<PL, 0, DIR>(v, q, tw, L);
+  if (active)
+#pragma unroll
+    for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) d[fft::reg_pos<P, TPF, RL>(q, m, r)] = v[m * RL + r];
+}
+
+template <typename T, int P, int TC, int DIR>
+__global__ void __launch_bounds__(TC * (P / fftE<T>()))
+fft_cols_kernel(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ tw) {
+  using PL = fft::Plan<P, fftE<T>()>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  __shared__ cpx<T> lds[P * TC];
+  const int t = threadIdx.x, c = t % TC, q = t / TC;
+  cpx<T>* d = data + (idx_t)blockIdx.y * P * P + (idx_t)blockIdx.x * TC + c;
+  cpx<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[m * R0 + r] = d[(idx_t)fft::reg_pos<P, TPF, R0>(q, m, r) * P];
+  fft::LdsCols<T, TC> L{lds, c};
+  fft::run_stages<PL, 0, DIR>(v, q, tw, L);
+#pragma unroll
+  for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) d[(idx_t)fft::reg_pos<P, TPF, RL>(q, m, r) * P] = v[m * RL + r];
+}
+
+template <typename T>
+constexpr int rows_per_block(int P) {
+  const int tpf = P / fftE<T>();
+  int r = 256 / tpf;
+  return r < 1 ? 1 : r;
+}
+template <typename T>
+constexpr int cols_per_block(int P) {
+  int tc = (65536 / (int)sizeof(cpx<T>)) / P;
+  if (tc > 16) tc = 16;
+  return tc < 1 ? 1 : tc;
+}
+
+template <typename T, int P>
+hipError_t fft2d_p(cpx<T>* data, int batch, int dir, const cpx<T>* tw, hipStream_t st) {
+  constexpr int ROWS = rows_per_block<T>(P);
+  constexpr int TC = cols_per_block<T>(P);
+  constexpr int TPF = fft::Plan<P, fftE<T>()>::TPF;
+  const idx_t n_rows = (idx_t)batch * P;
+  const dim3 gr((unsigned)((n_rows + ROWS - 1) / ROWS));
+  const dim3 gc(P / TC, batch);
+  if (dir < 0) {
+    hipLaunchKernelGGL((fft_rows_kernel<T, P, ROWS, -1>), gr, dim3(ROWS * TPF), 0, st, data,
+                       n_rows, tw);
+    hipLaunchKernelGGL((fft_cols_kernel<T, P, TC, -1>), gc, dim3(TC * TPF), 0, st, data, tw);
+  } else {
+    hipLaunchKernelGGL((fft_rows_kernel<T, P, ROWS, +1>), gr, dim3(ROWS * TPF), 0, st, data,
+                       n_rows, tw);
+    hipLaunchKernelGGL((fft_cols_kernel<T, P, TC, +1>), gc, dim3(TC * TPF), 0, st, data, tw);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------- crop / deapodise
+// out[z][my][mx] = Re H[z][(my - N/2) mod M][(mx - N/2) mod M] / (phi^(x/M) phi^(y/M))
+__global__ void crop_deapod_kernel(const cpx<float>* __restrict__ grid, float* __restrict__ out,
+                                   int N, int M, int W, double beta, int nzb) {
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const idx_t tot = (idx_t)nzb * N * N;
+  if (i >= tot) return;
+  const int z = (int)(i / ((idx_t)N * N));
+  const int rem = (int)(i - (idx_t)z * N * N);
+  const int my = rem / N, mx = rem - my * N;
+  const int x = mx - N / 2, y = my - N / 2;
+  const int gx = (x + M) % M, gy = (y + M) % M;
+  const double d = kb_phihat((double)x / M, W, beta) * kb_phihat((double)y / M, W, beta);
+  out[i] = (float)((double)grid[(idx_t)z * M * M + (idx_t)gy * M + gx].re / d);
+}
+
+// Embedded PSF: emb[v][u] = K(dy, dx) for |dx|, |dy| <= N-1 (dy = v or v - P, dx likewise),
+// zero elsewhere; K(d) = Re Kgrid[d mod M] / (phi^(dx/M) phi^(dy/M)).
+__global__ void psf_embed_kernel(const cpx<double>* __restrict__ grid,
+                                 cpx<double>* __restrict__ emb, int N, int P, int M, int W,
+                                 double beta) {
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (idx_t)P * P) return;
+  const int v = (int)(i / P), u = (int)(i - (idx_t)v * P);
+  const int dy = v < P / 2 ? v : v - P;
+  const int dx = u < P / 2 ? u : u - P;
+  double k = 0.0;
+  if (abs(dx) <= N - 1 && abs(dy) <= N - 1) {
+    const int gx = (dx + M) % M, gy = (dy + M) % M;
+    const double d = kb_phihat((double)dx / M, W, beta) * kb_phihat((double)dy / M, W, beta);
+    k = grid[(idx_t)gy * M + gx].re / d;
+  }
+  emb[i] = mk(k, 0.0);
+}
+
+// fk[v][u] = Re S[v][u] / P^2 for u < P/2; fkn[v] = Re S[v][P/2] / P^2.
+__global__ void fk_store_kernel(const cpx<double>* __restrict__ spec, float* __restrict__ fk,
+                                float* __restrict__ fkn, int P) {
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int H = P / 2;
+  if (i >= (idx_t)P * (H + 1)) return;
+  const int v = (int)(i / (H + 1)), u = (int)(i - (idx_t)v * (H + 1));
+  const double inv = 1.0 / ((double)P * (double)P);
+  const double val = spec[(idx_t)v * P + u].re * inv;
+  if (u < H) fk[(idx_t)v * H + u] = (float)val;
+  else fkn[v] = (float)val;
+}
+
+__global__ void fk_export_kernel(const float* __restrict__ fk, const float* __restrict__ fkn,
+                                 float* __restrict__ out, int P) {
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int H = P / 2;
+  if (i >= (idx_t)P * (H + 1)) return;
+  const int v = (int)(i / (H + 1)), u = (int)(i - (idx_t)v * (H + 1));
+  const float s = (float)P * (float)P;
+  out[i] = (u < H ? fk[(idx_t)v * H + u] : fkn[v]) * s;
+}
+
+// sum of (scale * g[row][j*stride])^2 over rows x n_out samples; two-stage deterministic.
+__global__ void __launch_bounds__(256)
+sumsq_kernel(const float* __restrict__ g, idx_t rows, int n_out, int stride, int n_full,
+             double scale2, double* __restrict__ partials) {
+  __shared__ double sh[256];
+  const idx_t tot = rows * n_out;
+  double a = 0.0;
+  for (idx_t i = (idx_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (idx_t)gridDim.x * 256) {
+    const idx_t r = i / n_out;
+    const int j = (int)(i - r * n_out);
+    const double v = g[r * n_full + (idx_t)j * stride];
+    a += v * v;
+  }
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0] * scale2;
+}
+
+__global__ void __launch_bounds__(256) sum_partials_kernel(const double* __restrict__ partials,
+                                                           int n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += partials[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// ----------------------------------------------------------------- Lanczos-3 prolongation
+// Normalised taps sinc(x) sinc(x/3) / sum, at offsets m - i/2 for odd fine index i.
+__device__ float lanczos3(double x) {
+  if (x == 0.0) return 1.0f;
+  if (fabs(x) >= 3.0) return 0.0f;
+  const double a = sinpi(x) / (M_PI * x);
+  const double b = sinpi(x / 3.0) / (M_PI * x / 3.0);
+  return (float)(a * b);
+}
+
+__global__ void lanczos_prolong_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                       int n, int nz) {
+  const int n2 = 2 * n;
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (idx_t)nz * n2 * n2) return;
+  const int z = (int)(i / ((idx_t)n2 * n2));
+  const int rem = (int)(i - (idx_t)z * n2 * n2);
+  const int fy = rem / n2, fx = rem - fy * n2;
+  // 1D taps: even fine index copies the coarse sample; odd uses offsets m0-2..m0+3
+  float wyv[6], wxv[6];
+  int y0, x0, ny, nxx;
+  double norm = 0.0;
+  for (int a = -2; a <= 3; ++a) norm += (double)lanczos3(0.5 - (double)a);
+  if (fy & 1) {
+    y0 = fy / 2 - 2; ny = 6;
+    for (int a = 0; a < 6; ++a) wyv[a] = (float)((double)lanczos3(0.5 - (double)(a - 2)) / norm);
+  } else {
+    y0 = fy / 2; ny = 1; wyv[0] = 1.0f;
+  }
+  if (fx & 1) {
+    x0 = fx / 2 - 2; nxx = 6;
+    for (int a = 0; a < 6; ++a) wxv[a] = (float)((double)lanczos3(0.5 - (double)(a - 2)) / norm);
+  } else {
+    x0 = fx / 2; nxx = 1; wxv[0] = 1.0f;
+  }
+  const float* src = in + (idx_t)z * n * n;
+  float acc = 0.f;
+  for (int a = 0; a < ny; ++a) {
+    const int yy = y0 + a;
+    if (yy < 0 || yy >= n) continue;
+    float rowacc = 0.f;
+    for (int b = 0; b < nxx; ++b) {
+      const int xx = x0 + b;
+      if (xx < 0 || xx >= n) continue;
+      rowacc += wxv[b] * src[(idx_t)yy * n + xx];
+    }
+    acc += wyv[a] * rowacc;
+  }
+  out[i] = acc;
+}
+
+inline unsigned nblk(idx_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// =================================================================================== API
+hipError_t launch_twiddles_f32(cpx<float>* tw, int P, hipStream_t st) {
+  hipLaunchKernelGGL((twiddle_kernel<float>), dim3(nblk(P, 256)), dim3(256), 0, st, tw, P);
+  return hipGetLastError();
+}
+hipError_t launch_twiddles_f64(cpx<double>* tw, int P, hipStream_t st) {
+  hipLaunchKernelGGL((twiddle_kernel<double>), dim3(nblk(P, 256)), dim3(256), 0, st, tw, P);
+  return hipGetLastError();
+}
+hipError_t launch_fill(float* x, idx_t n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_set_scalars(double* scal, int first, int count, const double* src, double v,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, scal, first, count, src, v);
+  return hipGetLastError();
+}
+hipError_t launch_angle_table(const double* angles_dev, double* tab, int n, hipStream_t st) {
+  hipLaunchKernelGGL(angle_table_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, angles_dev, tab, n);
+  return hipGetLastError();
+}
+hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, const GridGeom& gg,
+                                int ramp, hipStream_t st) {
+  hipLaunchKernelGGL(radial_tables_kernel, dim3(nblk(gg.n_det, 256)), dim3(256), 0, st, dft_tab,
+                     post, gg.n_det, gg.c, gg.stride, gg.n_angles, ramp);
+  return hipGetLastError();
+}
+hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat,
+                             const cpx<float>* dft_tab, const cpx<float>* post,
+                             const GridGeom& gg, int nz, hipStream_t st) {
+  const int rows = nz * gg.n_angles;
+  const dim3 grid(nblk(gg.n_det - 1, 256), nblk(rows, RD_ROWS));
+  hipLaunchKernelGGL(radial_dft_kernel, grid, dim3(256), 0, st, sino, n_det_full, gg.n_det,
+                     gg.stride, rows, ghat, dft_tab, post);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_point_table(const double* atab, int2* g0, T* wx, T* wy, const GridGeom& gg,
+                              hipStream_t st) {
+  const int np = gg.n_angles * (gg.n_det - 1);
+  hipLaunchKernelGGL((point_table_kernel<T>), dim3(nblk(np, 128)), dim3(128), 0, st, atab, g0,
+                     wx, wy, gg.n_det, gg.n_angles, gg.M, gg.W, gg.beta);
+  return hipGetLastError();
+}
+template hipError_t launch_point_table<float>(const double*, int2*, float*, float*,
+                                              const GridGeom&, hipStream_t);
+template hipError_t launch_point_table<double>(const double*, int2*, double*, double*,
+                                               const GridGeom&, hipStream_t);
+
+hipError_t launch_spread_f32(const cpx<float>* ghat, cpx<float>* grid, const double* atab,
+                             const int2* g0, const float* wx, const float* wy,
+                             const GridGeom& gg, int z0, int nzb, int /*ghat_slices*/,
+                             hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  const idx_t spts = (idx_t)gg.n_angles * (gg.n_det - 1);
+  const dim3 blocks(nblk(cells, 256));
+  if (nzb <= 1)
+    hipLaunchKernelGGL((spread_kernel<float, 1, false>), blocks, dim3(256), 0, st, ghat, grid,
+                       atab, g0, wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W, z0, nzb, spts, 0.f);
+  else if (nzb <= 4)
+    hipLaunchKernelGGL((spread_kernel<float, 4, false>), blocks, dim3(256), 0, st, ghat, grid,
+                       atab, g0, wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W, z0, nzb, spts, 0.f);
+  else if (nzb <= 8)
+    hipLaunchKernelGGL((spread_kernel<float, 8, false>), blocks, dim3(256), 0, st, ghat, grid,
+                       atab, g0, wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W, z0, nzb, spts, 0.f);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* atab, const int2* g0,
+                                 const double* wx, const double* wy, const GridGeom& gg,
+                                 hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  const idx_t spts = (idx_t)gg.n_angles * (gg.n_det - 1);
+  const double cval = 1.0 / (double)gg.n_det;
+  hipLaunchKernelGGL((spread_kernel<double, 1, true>), dim3(nblk(cells, 256)), dim3(256), 0, st,
+                     (const cpx<double>*)nullptr, grid, atab, g0, wx, wy, gg.M, gg.n_det,
+                     gg.n_angles, gg.W, 0, 1, spts, cval);
+  return hipGetLastError();
+}
+
+#define TOMO_MSWITCH(T, CALL)         \
+  switch (M) {                        \
+    case 32: return CALL(T, 32);      \
+    case 64: return CALL(T, 64);      \
+    case 128: return CALL(T, 128);    \
+    case 256: return CALL(T, 256);    \
+    case 512: return CALL(T, 512);    \
+    case 1024: return CALL(T, 1024);  \
+    case 2048: return CALL(T, 2048);  \
+    case 4096: return CALL(T, 4096);  \
+    case 8192: return CALL(T, 8192);  \
+  }                                   \
+  return hipErrorInvalidValue;
+
+hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir, const cpx<float>* tw,
+                            hipStream_t st) {
+#define CALL(T, PP) fft2d_p<T, PP>(data, batch, dir, tw, st)
+  TOMO_MSWITCH(float, CALL)
+#undef CALL
+}
+hipError_t launch_fft2d_f64(cpx<double>* data, int M, int batch, int dir,
+                            const cpx<double>* tw, hipStream_t st) {
+#define CALL(T, PP) fft2d_p<T, PP>(data, batch, dir, tw, st)
+  TOMO_MSWITCH(double, CALL)
+#undef CALL
+}
+
+hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const GridGeom& gg, int nzb,
+                              hipStream_t st) {
+  const idx_t tot = (idx_t)nzb * gg.n * gg.n;
+  hipLaunchKernelGGL(crop_deapod_kernel, dim3(nblk(tot, 256)), dim3(256), 0, st, grid, out, gg.n,
+                     gg.M, gg.W, gg.beta, nzb);
+  return hipGetLastError();
+}
+hipError_t launch_psf_embed(const cpx<double>* grid, cpx<double>* emb, const GridGeom& gg, int N,
+                            int P, hipStream_t st) {
+  hipLaunchKernelGGL(psf_embed_kernel, dim3(nblk((idx_t)P * P, 256)), dim3(256), 0, st, grid, emb,
+                     N, P, gg.M, gg.W, gg.beta);
+  return hipGetLastError();
+}
+hipError_t launch_fk_store(const cpx<double>* spec, float* fk, float* fkn, int P,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(fk_store_kernel, dim3(nblk((idx_t)P * (P / 2 + 1), 256)), dim3(256), 0, st,
+                     spec, fk, fkn, P);
+  return hipGetLastError();
+}
+hipError_t launch_fk_export(const float* fk, const float* fkn, float* out, int P,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(fk_export_kernel, dim3(nblk((idx_t)P * (P / 2 + 1), 256)), dim3(256), 0, st,
+                     fk, fkn, out, P);
+  return hipGetLastError();
+}
+hipError_t launch_sumsq_strided(const float* g, idx_t rows, int n_out, int stride, double scale,
+                                double* partials, double* out, hipStream_t st) {
+  // rows of the full detector width n_out*stride; 512 blocks of partial sums
+  const int nb = 512;
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nb), dim3(256), 0, st, g, rows, n_out, stride,
+                     n_out * stride, scale * scale, partials);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partials, nb, out);
+  return hipGetLastError();
+}
+hipError_t launch_lanczos_prolong(const float* in, float* out, int n, int nz, hipStream_t st) {
+  const idx_t tot = (idx_t)nz * 4 * n * n;
+  hipLaunchKernelGGL(lanczos_prolong_kernel, dim3(nblk(tot, 256)), dim3(256), 0, st, in, out, n,
+                     nz);
+  return hipGetLastError();
+}
+
+}  // namespace tomo

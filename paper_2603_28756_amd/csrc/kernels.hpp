@@ -1,0 +1,106 @@
+// Internal launcher interface between the C-ABI layer (tomo_api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace tomo {
+
+// Device scalar block (float64 slots) shared by the iteration kernels.
+enum ScalarSlot {
+  SC_MU = 0,         // momentum coefficient: y_k = x_k + mu (x_k - x_{k-1})
+  SC_T = 1,          // FISTA t_k
+  SC_INVL = 2,       // 1 / L
+  SC_GG = 3,         // <g, g> of the current level's projections
+  SC_PSCALE = 4,     // power iteration: scale applied to the stored iterate
+  SC_LAMBDA = 5,     // power iteration: ||T v|| / ||v||
+  SC_VNORM = 6,      // power iteration: ||v|| of the current (scaled) iterate
+  SC_RESTART_ON = 7, // 1.0 when the restart test is enabled
+  SC_ITER = 8,       // global iteration counter (history index)
+  SC_NONFINITE = 9,  // first iteration with a non-finite reduction, -1 if none
+  SC_NRESTART = 10,  // restart count
+  SC_LASTOBJ = 11,   // last objective value
+  SC_BETA = 12,      // prior weight (objective assembly)
+  SC_GSUM = 13,      // generic reduction result
+  SC_COUNT = 16
+};
+
+enum Mode { MODE_FISTA = 0, MODE_GRAD = 1, MODE_POWER = 2 };
+
+// Launch geometry of the hot-path kernels for a padded size P (used for partials sizing).
+int rows_inv_rows_per_block(int P);
+int cols_tile_width(int P);
+
+// ---- hot path (float32 data, float64 reductions) --------------------------------------
+// Pass R: y = x_k + mu (x_k - x_{k-1}) (or scale * x_k in power mode) -> row R2C -> S1.
+hipError_t launch_rows_fwd(int P, int mode, const float* xk, const float* xkm1,
+                           const double* scal, cpx<float>* S1, const cpx<float>* tw,
+                           int N, int nz, hipStream_t st);
+// Pass C: column FFT, x FK, inverse column FFT, keep N rows: S1 -> S2.
+hipError_t launch_cols_conv(int P, const cpx<float>* S1, cpx<float>* S2, const float* fk,
+                            const float* fkn, const cpx<float>* tw, int N, int nz, hipStream_t st);
+// Pass R': inverse row C2R + crop + epilogue; writes partial sums [nblocks][4].
+hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj,
+                           const cpx<float>* S2, const float* xk, const float* xkm1,
+                           const float* b, float* out, double* partials, const double* scal,
+                           const cpx<float>* tw, int N, int nz, const PriorParams& pp,
+                           int* nblocks_out, hipStream_t st);
+// Deterministic float64 reduction of the partials + scalar update.
+hipError_t launch_finalize(int mode, const double* partials, int nblocks, double* scal,
+                           double* obj_hist, int32_t* restart_hist, double* obj_out,
+                           hipStream_t st);
+
+// ---- tables and utilities ---------------------------------------------------------------
+hipError_t launch_twiddles_f32(cpx<float>* tw, int P, hipStream_t st);
+hipError_t launch_twiddles_f64(cpx<double>* tw, int P, hipStream_t st);
+hipError_t launch_fill(float* x, idx_t n, float v, hipStream_t st);
+hipError_t launch_set_scalars(double* scal, int first, int count, const double* vals_dev_or_null,
+                              double v, hipStream_t st);
+hipError_t launch_sumsq_strided(const float* g, idx_t rows, int n_out, int stride, double scale,
+                                double* partials, double* out, hipStream_t st);
+hipError_t launch_lanczos_prolong(const float* in, float* out, int n, int nz, hipStream_t st);
+
+// ---- back-projection and PSF (gridding) ---------------------------------------------------
+struct GridGeom {
+  int n;          // output image width N_l (back-projection) or 2 N_l (PSF region)
+  int n_det;      // detector bins of the level
+  int n_angles;
+  int M;          // oversampled grid size
+  int W;          // kernel width
+  double beta;    // KB shape
+  double c;       // rotation-centre bin of the level
+  int stride;     // detector subsampling stride of the level (1 = finest)
+};
+
+hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, const GridGeom& gg,
+                                int ramp, hipStream_t st);
+hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat,
+                             const cpx<float>* dft_tab, const cpx<float>* post,
+                             const GridGeom& gg, int nz, hipStream_t st);
+template <typename T>
+hipError_t launch_point_table(const double* angle_tab /* [n_angles][2] cos,sin */, int2* g0, T* wx,
+                              T* wy, const GridGeom& gg, hipStream_t st);
+hipError_t launch_angle_table(const double* angles_dev, double* tab, int n_angles, hipStream_t st);
+hipError_t launch_spread_f32(const cpx<float>* ghat, cpx<float>* grid, const double* angle_tab,
+                             const int2* g0, const float* wx, const float* wy,
+                             const GridGeom& gg, int z0, int nzb, int ghat_slices,
+                             hipStream_t st);
+hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* angle_tab, const int2* g0,
+                                 const double* wx, const double* wy, const GridGeom& gg,
+                                 hipStream_t st);
+hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir,
+                            const cpx<float>* tw, hipStream_t st);
+hipError_t launch_fft2d_f64(cpx<double>* data, int M, int batch, int dir,
+                            const cpx<double>* tw, hipStream_t st);
+hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const GridGeom& gg, int nzb,
+                              hipStream_t st);
+hipError_t launch_psf_embed(const cpx<double>* grid, cpx<double>* emb, const GridGeom& gg,
+                            int N, int P, hipStream_t st);
+hipError_t launch_fk_store(const cpx<double>* spec, float* fk, float* fkn, int P,
+                           hipStream_t st);
+hipError_t launch_fk_export(const float* fk, const float* fkn, float* out, int P,
+                            hipStream_t st);
+
+}  // namespace tomo

@@ -1,0 +1,584 @@
+// Hot path of the Toeplitz MBIR iteration on gfx950 (Sec. 2.1, Eqs. 9-11; Sec. 2, Eqs. 5-6).
+//
+// R*R y = Res_{NxN} F^-1(F K . F Pad y) is evaluated in three passes over a
+// half spectrum S[z][row][u] (u = 0..P/2-1, complex64, the u = 0 slot packing
+// the real DC column in its real part and the real Nyquist column u = P/2 in
+// its imaginary part):
+//   pass R  : rows of y (two real rows per complex transform) -> forward FFT of
+//             length P (second half zero) -> Hermitian split -> S1
+//   pass C  : per column u: forward FFT of length P (rows >= N zero), multiply
+//             by F K / P^2, inverse FFT, keep rows < N -> S2
+//   pass R' : rows of S2 -> inverse FFT of length P (two rows per complex
+//             transform) -> keep columns < N -> T y, then the fused epilogue:
+//             grad = T y - b + beta grad Phi(y) over 8 or 26 neighbours, the
+//             gradient step, and float64 partial sums for the objective and
+//             the restart test.
+// A single-block float64 finalize turns the partial sums into the next momentum
+// coefficient, so no host synchronisation is needed between iterations.
+#include "common.hpp"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace tomo {
+namespace {
+
+constexpr int kE = 16;  // elements per thread in the float32 transforms
+
+// ----------------------------------------------------------------------------------- prior
+// qGGMRF derivative (and value) for q = 2 in the factored form
+//   rho'(d) = c_grad d (q/p + w) / (1 + w)^2,  rho(d) = c_val t^2 / (1 + w),
+//   t = |d| / (T sigma), w = t^(q - p).
+template <bool VAL>
+TOMO_DEV void qggmrf(float d, const PriorParams& pp, float& rp, float& rv) {
+  const float t = fabsf(d) * pp.inv_Tsigma;
+  float w = 1.f;
+  if (!pp.quadratic) w = __builtin_amdgcn_exp2f(pp.qmp * __builtin_amdgcn_logf(t));
+  const float r = __builtin_amdgcn_rcpf(1.f + w);
+  rp = pp.c_grad * d * (pp.q_over_p + w) * r * r;
+  if constexpr (VAL) rv = pp.c_val * t * t * r;
+}
+
+template <int NT>
+TOMO_DEV void block_sum4(double a0, double a1, double a2, double a3, double* out, double* sbuf) {
+  double a[4] = {a0, a1, a2, a3};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+      if (off < NT) a[i] += __shfl_xor(a[i], off, 64);  // blocks narrower than a wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sbuf[wave * 4 + i] = a[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    constexpr int NW = (NT + 63) / 64;
+    double s[4] = {0, 0, 0, 0};
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s[i] += sbuf[w * 4 + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = s[i];
+  }
+}
+
+// ---------------------------------------------------------------------------------- pass R
+template <int P, int PAIRS, int MODE>
+__global__ void __launch_bounds__(PAIRS * (P / kE))
+rows_fwd_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
+                const double* __restrict__ scal, cpx<float>* __restrict__ S1,
+                const cpx<float>* __restrict__ tw, int N, int n_pairs) {
+  using PL = fft::Plan<P, kE>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  constexpr int REG = fft::row_region<P>();
+  constexpr int H = P / 2;
+  __shared__ cpx<float> lds[PAIRS * REG];
+
+  const int t = threadIdx.x, pr = t / TPF, q = t - pr * TPF;
+  const int gp = blockIdx.x * PAIRS + pr;
+  const bool active = gp < n_pairs;
+  const int halfN = N >> 1;
+  const int z = active ? gp / halfN : 0;
+  const int r1 = active ? 2 * (gp - z * halfN) : 0;
+  const idx_t row1 = ((idx_t)z * N + r1) * N;
+  const idx_t row2 = row1 + N;
+
+  float mu = 0.f, s = 1.f;
+  if constexpr (MODE == MODE_POWER) s = (float)scal[SC_PSCALE];
+  else mu = (float)scal[SC_MU];
+
+  cpx<float> v[E];
+#pragma unroll
+  for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
+      cpx<float> zz = mk(0.f, 0.f);
+      if (active && n < N) {
+        const float a1 = xk[row1 + n], a2 = xk[row2 + n];
+        if constexpr (MODE == MODE_POWER) {
+          zz = mk(s * a1, s * a2);
+        } else {
+          const float b1 = xkm1[row1 + n], b2 = xkm1[row2 + n];
+          zz = mk(a1 + mu * (a1 - b1), a2 + mu * (a2 - b2));
+        }
+      }
+      v[m * R0 + r] = zz;
+    }
+
+  fft::LdsRow<float> L{lds + pr * REG};
+  fft::run_stages<PL, 0, -1>(v, q, tw, L);
+#pragma unroll
+  for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) L.st(fft::reg_pos<P, TPF, RL>(q, m, r), v[m * RL + r]);
+  __syncthreads();
+
+  if (active) {
+    cpx<float>* o1 = S1 + ((idx_t)z * N + r1) * H;
+    cpx<float>* o2 = o1 + H;
+    for (int u = q; u < H; u += TPF) {
+      const cpx<float> zu = L.ld(u);
+      if (u == 0) {
+        const cpx<float> zn = L.ld(H);
+        o1[0] = mk(zu.re, zn.re);
+        o2[0] = mk(zu.im, zn.im);
+      } else {
+        const cpx<float> zm = L.ld(P - u);
+        // X1 = (Z[u] + conj Z[P-u]) / 2,  X2 = (Z[u] - conj Z[P-u]) / (2i)
+        o1[u] = mk(0.5f * (zu.re + zm.re), 0.5f * (zu.im - zm.im));
+        o2[u] = mk(0.5f * (zu.im + zm.im), -0.5f * (zu.re - zm.re));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------- pass C
+template <int P, int TC>
+__global__ void __launch_bounds__(TC * (P / kE))
+cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
+                 const float* __restrict__ fk, const float* __restrict__ fkn,
+                 const cpx<float>* __restrict__ tw, int N) {
+  using PL = fft::Plan<P, kE>;
+  using IPL = fft::RevPlan<PL>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  constexpr int H = P / 2;
+  __shared__ cpx<float> lds[P * TC];
+
+  const int t = threadIdx.x, c = t % TC, q = t / TC;
+  const int u = blockIdx.x * TC + c;
+  const int z = blockIdx.y;
+  const cpx<float>* in = S1 + (idx_t)z * N * H + u;
+
+  cpx<float> v[E];
+#pragma unroll
+  for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
+      v[m * R0 + r] = n < N ? in[(idx_t)n * H] : mk(0.f, 0.f);
+    }
+
+  fft::LdsCols<float, TC> L{lds, c};
+  fft::run_stages<PL, 0, -1>(v, q, tw, L);
+
+  if (blockIdx.x == 0) {
+    // Column 0 carries the DC column (real part) and the Nyquist column (imag part); both
+    // are real, so their spectra C0, CN are Hermitian and C0 FK0 + i CN FKN is recovered
+    // from Z[v] and conj Z[-v].
+#pragma unroll
+    for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) L.st(fft::reg_pos<P, TPF, RL>(q, m, r), v[m * RL + r]);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int n = fft::reg_pos<P, TPF, RL>(q, m, r);
+        const cpx<float> zv = v[m * RL + r];
+        if (c == 0) {
+          const cpx<float> zm = conj(L.ld((P - n) & (P - 1)));
+          const float f0 = fk[(idx_t)n * H], fN = fkn[n];
+          const float a = 0.5f * (f0 + fN), b = 0.5f * (f0 - fN);
+          v[m * RL + r] = mk(a * zv.re + b * zm.re, a * zv.im + b * zm.im);
+        } else {
+          v[m * RL + r] = scale(zv, fk[(idx_t)n * H + u]);
+        }
+      }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int n = fft::reg_pos<P, TPF, RL>(q, m, r);
+        v[m * RL + r] = scale(v[m * RL + r], fk[(idx_t)n * H + u]);
+      }
+  }
+
+  fft::run_stages<IPL, 0, +1>(v, q, tw, L);
+
+  cpx<float>* out = S2 + (idx_t)z * N * H + u;
+#pragma unroll
+  for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
+      if (n < N) out[(idx_t)n * H] = v[m * R0 + r];
+    }
+}
+
+// --------------------------------------------------------------------------------- pass R'
+template <int P, int PAIRS, int MODE, int NB, bool OBJ>
+__global__ void __launch_bounds__(PAIRS * (P / kE))
+rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
+                const float* __restrict__ xkm1, const float* __restrict__ bvec,
+                float* __restrict__ out, double* __restrict__ partials,
+                const double* __restrict__ scal, const cpx<float>* __restrict__ tw, int N,
+                int nz, PriorParams pp) {
+  using PL = fft::Plan<P, kE>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  constexpr int NT = PAIRS * TPF, RB = 2 * PAIRS, H = P / 2;
+  constexpr int REG = fft::row_region<P>();
+  constexpr int CW = 64;
+  constexpr int ZD = (NB == 26) ? 3 : 1;
+  constexpr int YT = ZD * (RB + 2) * (CW + 2);
+  constexpr int FFT_BYTES = PAIRS * REG * 8;
+  constexpr int YT_BYTES = YT * 4;
+  constexpr int A_BYTES = FFT_BYTES > YT_BYTES ? FFT_BYTES : YT_BYTES;
+  constexpr int TY_BYTES = RB * H * 4;
+  __shared__ __align__(16) unsigned char smem[A_BYTES + TY_BYTES];
+  __shared__ double sred[((NT + 63) / 64) * 4];
+  cpx<float>* fl = reinterpret_cast<cpx<float>*>(smem);
+  float* ytile = reinterpret_cast<float*>(smem);
+  float* tyt = reinterpret_cast<float*>(smem + A_BYTES);
+
+  const int bps = (N + RB - 1) / RB;
+  const int z = blockIdx.x / bps;
+  const int r0 = (blockIdx.x - z * bps) * RB;
+  const int t = threadIdx.x, pr = t / TPF, q = t - pr * TPF;
+  const int r1 = r0 + 2 * pr;
+  const bool active = r1 < N;
+
+  // ---- C2R of rows r1, r1+1 packed as Z = X1 + i X2 over the full length P
+  {
+    const cpx<float>* s1 = S2 + ((idx_t)z * N + (active ? r1 : 0)) * H;
+    const cpx<float>* s2 = s1 + H;
+    cpx<float> v[E];
+#pragma unroll
+    for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
+        cpx<float> zz = mk(0.f, 0.f);
+        if (active) {
+          if (n == 0) {
+            const cpx<float> a = s1[0], b = s2[0];
+            zz = mk(a.re, b.re);
+          } else if (n == H) {
+            const cpx<float> a = s1[0], b = s2[0];
+            zz = mk(a.im, b.im);
+          } else if (n < H) {
+            const cpx<float> a = s1[n], b = s2[n];
+            zz = mk(a.re - b.im, a.im + b.re);
+          } else {
+            const cpx<float> a = s1[P - n], b = s2[P - n];
+            zz = mk(a.re + b.im, b.re - a.im);
+          }
+        }
+        v[m * R0 + r] = zz;
+      }
+    fft::LdsRow<float> L{fl + pr * REG};
+    fft::run_stages<PL, 0, +1>(v, q, tw, L);
+#pragma unroll
+    for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int n = fft::reg_pos<P, TPF, RL>(q, m, r);
+        if (n < N) {
+          tyt[(2 * pr) * H + n] = v[m * RL + r].re;
+          tyt[(2 * pr + 1) * H + n] = v[m * RL + r].im;
+        }
+      }
+  }
+  __syncthreads();
+
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  if constexpr (MODE == MODE_POWER) {
+    for (int e = t; e < RB * N; e += NT) {
+      const int ry = e / N, col = e - ry * N, row = r0 + ry;
+      if (row < N) {
+        const float ty = tyt[ry * H + col];
+        out[((idx_t)z * N + row) * N + col] = ty;
+        acc0 += (double)ty * (double)ty;
+      }
+    }
+  } else {
+    const float mu = (MODE == MODE_FISTA) ? (float)scal[SC_MU] : 0.f;
+    const float invL = (MODE == MODE_FISTA) ? (float)scal[SC_INVL] : 0.f;
+    for (int c0 = 0; c0 < N; c0 += CW) {
+      for (int e = t; e < YT; e += NT) {
+        const int dzi = e / ((RB + 2) * (CW + 2));
+        const int rem = e - dzi * (RB + 2) * (CW + 2);
+        const int ry = rem / (CW + 2), cx = rem - ry * (CW + 2);
+        const int zz = z + dzi - ZD / 2;
+        const int row = r0 - 1 + ry, col = c0 - 1 + cx;
+        float yv = 0.f;
+        if (zz >= 0 && zz < nz && row >= 0 && row < N && col >= 0 && col < N) {
+          const idx_t o = ((idx_t)zz * N + row) * N + col;
+          const float a = xk[o];
+          yv = (MODE == MODE_FISTA) ? a + mu * (a - xkm1[o]) : a;
+        }
+        ytile[e] = yv;
+      }
+      __syncthreads();
+      for (int e = t; e < RB * CW; e += NT) {
+        const int ry = e / CW, cx = e - ry * CW;
+        const int row = r0 + ry, col = c0 + cx;
+        if (row < N && col < N) {
+          const int cidx = ((ZD / 2) * (RB + 2) + ry + 1) * (CW + 2) + cx + 1;
+          const float ys = ytile[cidx];
+          const bool vz[3] = {z > 0, true, z + 1 < nz};
+          const bool vy[3] = {row > 0, true, row + 1 < N};
+          const bool vx[3] = {col > 0, true, col + 1 < N};
+          float gsum = 0.f, phi = 0.f;
+#pragma unroll
+          for (int dz = -1; dz <= 1; ++dz) {
+            if (NB == 8 && dz != 0) continue;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+              for (int dx = -1; dx <= 1; ++dx) {
+                if (dz == 0 && dy == 0 && dx == 0) continue;
+                if (!(vz[dz + 1] && vy[dy + 1] && vx[dx + 1])) continue;
+                const float yn = ytile[cidx + (dz * (RB + 2) + dy) * (CW + 2) + dx];
+                const float wgt = pp.wts[(dz != 0) + (dy != 0) + (dx != 0)];
+                float rp, rv = 0.f;
+                qggmrf<OBJ>(ys - yn, pp, rp, rv);
+                gsum += wgt * rp;
+                if constexpr (OBJ) {
+                  // each unordered pair once: the lexicographically positive offset
+                  const bool half = dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0)));
+                  if (half) phi += wgt * rv;
+                }
+              }
+          }
+          const idx_t o = ((idx_t)z * N + row) * N + col;
+          const float ty = tyt[ry * H + col];
+          const float bs = bvec[o];
+          const float g = ty - bs + pp.beta * gsum;
+          if constexpr (MODE == MODE_FISTA) {
+            const float xn = ys - g * invL;
+            out[o] = xn;
+            const float xo = xk[o];
+            acc3 += (double)(ys - xn) * (double)(xn - xo);
+          } else {
+            out[o] = g;
+          }
+          acc0 += (double)ys * (double)ty;
+          acc1 += (double)ys * (double)bs;
+          if constexpr (OBJ) acc2 += (double)phi;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  block_sum4<NT>(acc0, acc1, acc2, acc3, partials + (idx_t)blockIdx.x * 4, sred);
+}
+
+// -------------------------------------------------------------------------------- finalize
+template <int MODE>
+__global__ void __launch_bounds__(256)
+finalize_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ scal,
+                double* __restrict__ hist, int32_t* __restrict__ rhist,
+                double* __restrict__ obj_out) {
+  __shared__ double sh[4][256];
+  const int t = threadIdx.x;
+  double a[4] = {0, 0, 0, 0};
+  for (int b = t; b < nblocks; b += 256)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] += partials[(idx_t)b * 4 + i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) sh[i][t] = a[i];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sh[i][t] += sh[i][t + s];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double s0 = sh[0][0], s1 = sh[1][0], s2 = sh[2][0], s3 = sh[3][0];
+  if constexpr (MODE == MODE_POWER) {
+    const double wn = sqrt(s0);
+    scal[SC_LAMBDA] = wn / scal[SC_VNORM];
+    scal[SC_PSCALE] = wn > 0.0 ? 1.0 / wn : 0.0;
+    scal[SC_VNORM] = 1.0;
+    scal[SC_GSUM] = s0;
+  } else if constexpr (MODE == MODE_GRAD) {
+    const double obj = 0.5 * s0 - s1 + scal[SC_BETA] * s2;
+    if (obj_out) obj_out[0] = obj;
+    scal[SC_LASTOBJ] = obj;
+  } else {
+    const int k = (int)scal[SC_ITER];
+    const double obj = 0.5 * s0 - s1 + 0.5 * scal[SC_GG] + scal[SC_BETA] * s2;
+    if (hist) hist[k] = obj;
+    scal[SC_LASTOBJ] = obj;
+    const double tk = scal[SC_T];
+    double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+    const bool restart = scal[SC_RESTART_ON] != 0.0 && s3 > 0.0;
+    double mu;
+    if (restart) {
+      tn = 1.0;
+      mu = 0.0;
+      scal[SC_NRESTART] += 1.0;
+    } else {
+      mu = (tk - 1.0) / tn;
+    }
+    if (rhist) rhist[k] = restart ? 1 : 0;
+    const bool bad = !isfinite(s3) || !isfinite(s0) || !isfinite(s1) || (hist && !isfinite(obj));
+    if (bad && scal[SC_NONFINITE] < 0.0) scal[SC_NONFINITE] = (double)k;
+    scal[SC_T] = tn;
+    scal[SC_MU] = mu;
+    scal[SC_ITER] = (double)(k + 1);
+  }
+}
+
+// ------------------------------------------------------------------- launch configuration
+constexpr int fwd_pairs(int P) {
+  const int tpf = P / kE;
+  int pairs = 256 / tpf;
+  if (pairs < 1) pairs = 1;
+  if (pairs > 64) pairs = 64;
+  return pairs;
+}
+constexpr int inv_pairs(int P) {
+  const int tpf = P / kE;
+  int pairs = 256 / tpf;
+  if (pairs < 1) pairs = 1;
+  if (pairs > 8) pairs = 8;
+  return pairs;
+}
+constexpr int col_tc(int P) {
+  int tc = 8192 / P;  // 64 KiB of LDS per block
+  if (tc > 16) tc = 16;
+  if (tc < 1) tc = 1;
+  return tc;
+}
+
+template <int P>
+hipError_t rows_fwd_p(int mode, const float* xk, const float* xkm1, const double* scal,
+                      cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st) {
+  constexpr int PAIRS = fwd_pairs(P);
+  constexpr int NT = PAIRS * fft::Plan<P, kE>::TPF;
+  const int n_pairs = nz * (N / 2);
+  const dim3 grid((n_pairs + PAIRS - 1) / PAIRS);
+  if (mode == MODE_POWER)
+    hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_POWER>), grid, dim3(NT), 0, st, xk, xkm1,
+                       scal, S1, tw, N, n_pairs);
+  else
+    hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_FISTA>), grid, dim3(NT), 0, st, xk, xkm1,
+                       scal, S1, tw, N, n_pairs);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t cols_conv_p(const cpx<float>* S1, cpx<float>* S2, const float* fk, const float* fkn,
+                       const cpx<float>* tw, int N, int nz, hipStream_t st) {
+  constexpr int TC = col_tc(P);
+  constexpr int NT = TC * fft::Plan<P, kE>::TPF;
+  const dim3 grid((P / 2) / TC, nz);
+  hipLaunchKernelGGL((cols_conv_kernel<P, TC>), grid, dim3(NT), 0, st, S1, S2, fk, fkn, tw, N);
+  return hipGetLastError();
+}
+
+template <int P, int MODE, int NB, bool OBJ>
+hipError_t rows_inv_launch(const cpx<float>* S2, const float* xk, const float* xkm1,
+                           const float* b, float* out, double* partials, const double* scal,
+                           const cpx<float>* tw, int N, int nz, const PriorParams& pp,
+                           int* nblocks, hipStream_t st) {
+  constexpr int PAIRS = inv_pairs(P);
+  constexpr int NT = PAIRS * fft::Plan<P, kE>::TPF;
+  constexpr int RB = 2 * PAIRS;
+  const int nb = nz * ((N + RB - 1) / RB);
+  *nblocks = nb;
+  hipLaunchKernelGGL((rows_inv_kernel<P, PAIRS, MODE, NB, OBJ>), dim3(nb), dim3(NT), 0, st, S2,
+                     xk, xkm1, b, out, partials, scal, tw, N, nz, pp);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t rows_inv_p(int mode, int nbh, bool obj, const cpx<float>* S2, const float* xk,
+                      const float* xkm1, const float* b, float* out, double* partials,
+                      const double* scal, const cpx<float>* tw, int N, int nz,
+                      const PriorParams& pp, int* nblocks, hipStream_t st) {
+#define TOMO_INV(MODE, NB, OBJ)                                                              \
+  return rows_inv_launch<P, MODE, NB, OBJ>(S2, xk, xkm1, b, out, partials, scal, tw, N, nz, \
+                                           pp, nblocks, st)
+  if (mode == MODE_POWER) TOMO_INV(MODE_POWER, 8, false);
+  if (mode == MODE_GRAD) {
+    if (nbh == 26) { if (obj) TOMO_INV(MODE_GRAD, 26, true); TOMO_INV(MODE_GRAD, 26, false); }
+    if (obj) TOMO_INV(MODE_GRAD, 8, true);
+    TOMO_INV(MODE_GRAD, 8, false);
+  }
+  if (nbh == 26) { if (obj) TOMO_INV(MODE_FISTA, 26, true); TOMO_INV(MODE_FISTA, 26, false); }
+  if (obj) TOMO_INV(MODE_FISTA, 8, true);
+  TOMO_INV(MODE_FISTA, 8, false);
+#undef TOMO_INV
+}
+
+}  // namespace
+
+int rows_inv_rows_per_block(int P) {
+  switch (P) {
+    case 32: return 2 * inv_pairs(32);
+    case 64: return 2 * inv_pairs(64);
+    case 128: return 2 * inv_pairs(128);
+    case 256: return 2 * inv_pairs(256);
+    case 512: return 2 * inv_pairs(512);
+    case 1024: return 2 * inv_pairs(1024);
+    case 2048: return 2 * inv_pairs(2048);
+    case 4096: return 2 * inv_pairs(4096);
+  }
+  return 2;
+}
+
+int cols_tile_width(int P) { return col_tc(P); }
+
+#define TOMO_PSWITCH(CALL)          \
+  switch (P) {                      \
+    case 32: return CALL(32);       \
+    case 64: return CALL(64);       \
+    case 128: return CALL(128);     \
+    case 256: return CALL(256);     \
+    case 512: return CALL(512);     \
+    case 1024: return CALL(1024);   \
+    case 2048: return CALL(2048);   \
+    case 4096: return CALL(4096);   \
+  }                                 \
+  return hipErrorInvalidValue;
+
+hipError_t launch_rows_fwd(int P, int mode, const float* xk, const float* xkm1,
+                           const double* scal, cpx<float>* S1, const cpx<float>* tw, int N,
+                           int nz, hipStream_t st) {
+#define CALL(PP) rows_fwd_p<PP>(mode, xk, xkm1, scal, S1, tw, N, nz, st)
+  TOMO_PSWITCH(CALL)
+#undef CALL
+}
+
+hipError_t launch_cols_conv(int P, const cpx<float>* S1, cpx<float>* S2, const float* fk,
+                            const float* fkn, const cpx<float>* tw, int N, int nz,
+                            hipStream_t st) {
+#define CALL(PP) cols_conv_p<PP>(S1, S2, fk, fkn, tw, N, nz, st)
+  TOMO_PSWITCH(CALL)
+#undef CALL
+}
+
+hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj, const cpx<float>* S2,
+                           const float* xk, const float* xkm1, const float* b, float* out,
+                           double* partials, const double* scal, const cpx<float>* tw, int N,
+                           int nz, const PriorParams& pp, int* nblocks_out, hipStream_t st) {
+#define CALL(PP)                                                                         \
+  rows_inv_p<PP>(mode, neighbours, with_obj, S2, xk, xkm1, b, out, partials, scal, tw, N, \
+                 nz, pp, nblocks_out, st)
+  TOMO_PSWITCH(CALL)
+#undef CALL
+}
+
+hipError_t launch_finalize(int mode, const double* partials, int nblocks, double* scal,
+                           double* obj_hist, int32_t* restart_hist, double* obj_out,
+                           hipStream_t st) {
+  if (mode == MODE_POWER)
+    hipLaunchKernelGGL((finalize_kernel<MODE_POWER>), dim3(1), dim3(256), 0, st, partials,
+                       nblocks, scal, obj_hist, restart_hist, obj_out);
+  else if (mode == MODE_GRAD)
+    hipLaunchKernelGGL((finalize_kernel<MODE_GRAD>), dim3(1), dim3(256), 0, st, partials,
+                       nblocks, scal, obj_hist, restart_hist, obj_out);
+  else
+    hipLaunchKernelGGL((finalize_kernel<MODE_FISTA>), dim3(1), dim3(256), 0, st, partials,
+                       nblocks, scal, obj_hist, restart_hist, obj_out);
+  return hipGetLastError();
+}
+
+}  // namespace tomo

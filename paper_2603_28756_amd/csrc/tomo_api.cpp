@@ -1,0 +1,647 @@
+// C-ABI layer of libtomo: plan lifecycle, validation, workspace carving and the
+// orchestration of the HIP kernels.  Host code only; every numerical step runs in
+// the kernels of toeplitz_kernels.hip and gridding_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tomo.h"
+#include "kernels.hpp"
+
+using namespace tomo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxLevels = 6;
+constexpr int kPowerIters = 30;
+constexpr int kMinFft = 32, kMaxHot = 4096, kMaxGrid = 8192;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int next_pow2(long long x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2i(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+struct Level {
+  int n = 0, nd = 0, P = 0, M = 0, Mpsf = 0, stride = 1;
+  double c = 0.0;
+  double beta_bp = 0.0, beta_psf = 0.0;
+  double L = 0.0, lambda = 0.0;
+  size_t off_fk = 0, off_fkn = 0, off_b = 0;
+};
+
+}  // namespace
+
+struct tomo_plan_s {
+  tomo_geometry_t g{};
+  std::vector<double> angles;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int nz = 0, n_levels = 1;
+  std::vector<Level> lv;
+  PriorParams pp{};
+  double rho2_0 = 0.0;  // rho''(0)
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0, need = 0;
+  size_t off_scal = 0, off_partials = 0, n_partials = 0;
+  size_t off_tw32[14] = {}, off_tw64[14] = {};
+  size_t off_angles = 0, off_atab = 0;
+  size_t off_x[3] = {};
+  size_t off_ghat = 0, off_dfttab = 0, off_post = 0;
+  size_t off_g0 = 0, off_wx = 0, off_wy = 0;
+  size_t off_scratch = 0, scratch_bytes = 0;
+  bool tables_ready = false, psf_ready = false;
+  std::string err;
+
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  double* scal() const { return at<double>(off_scal); }
+  double* partials() const { return at<double>(off_partials); }
+  cpx<float>* tw32(int P) const { return at<cpx<float>>(off_tw32[ilog2i(P)]); }
+  cpx<double>* tw64(int P) const { return at<cpx<double>>(off_tw64[ilog2i(P)]); }
+  float* xbuf(int i) const { return at<float>(off_x[i]); }
+  cpx<float>* S1() const { return at<cpx<float>>(off_scratch); }
+  cpx<float>* S2(const Level& l) const {
+    return at<cpx<float>>(off_scratch + align_up((size_t)nz * l.n * (l.P / 2) * 8));
+  }
+};
+
+namespace {
+
+tomo_status fail(tomo_plan p, tomo_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (p) p->err = buf;
+  g_last_error = buf;
+  return s;
+}
+
+#define HIPCHK(plan, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(plan, TOMO_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+double beatty_beta(int W, double s) {
+  const double v = (W / s) * (W / s) * (s - 0.5) * (s - 0.5) - 0.8;
+  return M_PI * std::sqrt(v > 0.0 ? v : 0.0);
+}
+
+// Carve the workspace: every region 256-byte aligned, offsets relative to the base.
+void layout(tomo_plan p) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const Level& fin = p->lv.back();
+  p->off_scal = take(SC_COUNT * sizeof(double));
+  size_t maxblocks = 512;
+  for (const Level& l : p->lv) {
+    const int rb = rows_inv_rows_per_block(l.P);
+    const size_t nb = (size_t)p->nz * ((l.n + rb - 1) / rb);
+    if (nb > maxblocks) maxblocks = nb;
+  }
+  p->n_partials = maxblocks;
+  p->off_partials = take(maxblocks * 4 * sizeof(double));
+  for (int k = ilog2i(kMinFft); k <= ilog2i(kMaxGrid); ++k) {
+    p->off_tw32[k] = take((size_t(1) << k) * sizeof(cpx<float>));
+    p->off_tw64[k] = take((size_t(1) << k) * sizeof(cpx<double>));
+  }
+  const int na = p->g.n_angles;
+  p->off_angles = take(na * sizeof(double));
+  p->off_atab = take(2 * na * sizeof(double));
+  for (Level& l : p->lv) {
+    l.off_fk = take((size_t)l.P * (l.P / 2) * sizeof(float));
+    l.off_fkn = take((size_t)l.P * sizeof(float));
+    l.off_b = take((size_t)p->nz * l.n * l.n * sizeof(float));
+  }
+  for (int i = 0; i < 3; ++i) p->off_x[i] = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
+  const size_t npts_max = (size_t)na * (fin.nd - 1);
+  p->off_ghat = take((size_t)p->nz * npts_max * sizeof(cpx<float>));
+  p->off_dfttab = take((size_t)fin.nd * sizeof(cpx<float>));
+  p->off_post = take((size_t)fin.nd * sizeof(cpx<float>));
+  const int W = p->g.kb_width;
+  p->off_g0 = take(npts_max * sizeof(int2));
+  p->off_wx = take(npts_max * W * sizeof(float));
+  p->off_wy = take(npts_max * W * sizeof(float));
+  size_t scratch = 0;
+  for (const Level& l : p->lv) {
+    const size_t s1 = align_up((size_t)p->nz * l.n * (l.P / 2) * 8);
+    const size_t hot = 2 * s1;
+    const size_t bp = (size_t)l.M * l.M * sizeof(cpx<float>);
+    const size_t npts = (size_t)na * (l.nd - 1);
+    const size_t psf = align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>)) +
+                       align_up((size_t)l.P * l.P * sizeof(cpx<double>)) +
+                       align_up(npts * sizeof(int2)) + 2 * align_up(npts * W * sizeof(double));
+    scratch = std::max(scratch, std::max(hot, std::max(bp, psf)));
+  }
+  p->scratch_bytes = scratch;
+  p->off_scratch = take(scratch);
+  p->need = off;
+}
+
+tomo_status check_ws(tomo_plan p) {
+  if (!p->ws) return fail(p, TOMO_ERR_NO_WORKSPACE, "no workspace attached");
+  return TOMO_OK;
+}
+
+tomo_status ensure_tables(tomo_plan p) {
+  if (p->tables_ready) return TOMO_OK;
+  hipStream_t st = p->stream;
+  for (int k = ilog2i(kMinFft); k <= ilog2i(kMaxGrid); ++k) {
+    HIPCHK(p, launch_twiddles_f32(p->at<cpx<float>>(p->off_tw32[k]), 1 << k, st));
+    HIPCHK(p, launch_twiddles_f64(p->at<cpx<double>>(p->off_tw64[k]), 1 << k, st));
+  }
+  HIPCHK(p, hipMemcpyAsync(p->at<double>(p->off_angles), p->angles.data(),
+                           p->angles.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(p, launch_angle_table(p->at<double>(p->off_angles), p->at<double>(p->off_atab),
+                               p->g.n_angles, st));
+  HIPCHK(p, launch_set_scalars(p->scal(), 0, SC_COUNT, nullptr, 0.0, st));
+  HIPCHK(p, launch_set_scalars(p->scal(), SC_BETA, 1, nullptr, p->g.beta, st));
+  HIPCHK(p, launch_set_scalars(p->scal(), SC_NONFINITE, 1, nullptr, -1.0, st));
+  p->tables_ready = true;
+  return TOMO_OK;
+}
+
+GridGeom bp_geom(tomo_plan p, const Level& l) {
+  GridGeom gg;
+  gg.n = l.n;
+  gg.n_det = l.nd;
+  gg.n_angles = p->g.n_angles;
+  gg.M = l.M;
+  gg.W = p->g.kb_width;
+  gg.beta = l.beta_bp;
+  gg.c = l.c;
+  gg.stride = l.stride;
+  return gg;
+}
+
+// out[nz][N_l][N_l] = R*_l g_l (ramp = 0) or FBP (ramp = 1) of level l.
+tomo_status backproject_level(tomo_plan p, const Level& l, const float* sino, float* out,
+                              int ramp) {
+  hipStream_t st = p->stream;
+  const GridGeom gg = bp_geom(p, l);
+  cpx<float>* ghat = p->at<cpx<float>>(p->off_ghat);
+  cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
+  cpx<float>* post = p->at<cpx<float>>(p->off_post);
+  HIPCHK(p, launch_radial_tables(tab, post, gg, ramp, st));
+  HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
+  int2* g0 = p->at<int2>(p->off_g0);
+  float* wx = p->at<float>(p->off_wx);
+  float* wy = p->at<float>(p->off_wy);
+  HIPCHK(p, launch_point_table<float>(p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+  const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
+  int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / slice_grid);
+  if (chunk < 1) return fail(p, TOMO_ERR_INTERNAL, "scratch too small for one grid slice");
+  cpx<float>* grid = p->at<cpx<float>>(p->off_scratch);
+  for (int z0 = 0; z0 < p->nz; z0 += chunk) {
+    const int zc = std::min(chunk, p->nz - z0);
+    for (int zb = 0; zb < zc; zb += 8) {
+      const int nzb = std::min(8, zc - zb);
+      HIPCHK(p, launch_spread_f32(ghat, grid + (size_t)zb * l.M * l.M, p->at<double>(p->off_atab),
+                                  g0, wx, wy, gg, z0 + zb, nzb, p->nz, st));
+    }
+    HIPCHK(p, launch_fft2d_f32(grid, l.M, zc, +1, p->tw32(l.M), st));
+    HIPCHK(p, launch_crop_deapod(grid, out + (size_t)z0 * l.n * l.n, gg, zc, st));
+  }
+  return TOMO_OK;
+}
+
+// One application of the Toeplitz passes on level l.
+tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const float* xk,
+                            const float* xkm1, const float* b, float* out, bool obj,
+                            int* nblocks) {
+  hipStream_t st = p->stream;
+  cpx<float>* S1 = p->S1();
+  cpx<float>* S2 = p->S2(l);
+  HIPCHK(p, launch_rows_fwd(l.P, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz, st));
+  HIPCHK(p, launch_cols_conv(l.P, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
+                             p->tw32(l.P), l.n, nz, st));
+  HIPCHK(p, launch_rows_inv(l.P, mode, p->g.neighbours, obj, S2, xk, xkm1, b, out, p->partials(),
+                            p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks, st));
+  return TOMO_OK;
+}
+
+tomo_status psf_level(tomo_plan p, Level& l) {
+  hipStream_t st = p->stream;
+  GridGeom gg;
+  gg.n = 2 * l.n;
+  gg.n_det = l.nd;
+  gg.n_angles = p->g.n_angles;
+  gg.M = l.Mpsf;
+  gg.W = p->g.kb_width;
+  gg.beta = l.beta_psf;
+  gg.c = l.c;
+  gg.stride = 1;
+  const size_t npts = (size_t)p->g.n_angles * (l.nd - 1);
+  size_t off = p->off_scratch;
+  cpx<double>* grid = p->at<cpx<double>>(off);
+  off += align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>));
+  cpx<double>* emb = p->at<cpx<double>>(off);
+  off += align_up((size_t)l.P * l.P * sizeof(cpx<double>));
+  int2* g0 = p->at<int2>(off);
+  off += align_up(npts * sizeof(int2));
+  double* wx = p->at<double>(off);
+  off += align_up(npts * gg.W * sizeof(double));
+  double* wy = p->at<double>(off);
+  HIPCHK(p, launch_point_table<double>(p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+  HIPCHK(p, launch_spread_psf_f64(grid, p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+  HIPCHK(p, launch_fft2d_f64(grid, l.Mpsf, 1, +1, p->tw64(l.Mpsf), st));
+  HIPCHK(p, launch_psf_embed(grid, emb, gg, l.n, l.P, st));
+  HIPCHK(p, launch_fft2d_f64(emb, l.P, 1, -1, p->tw64(l.P), st));
+  HIPCHK(p, launch_fk_store(emb, p->at<float>(l.off_fk), p->at<float>(l.off_fkn), l.P, st));
+
+  // Power iteration on one slice: v0 = 1, lambda = ||T v|| / ||v||.
+  float* v = p->xbuf(0);
+  float* w = p->xbuf(1);
+  HIPCHK(p, launch_fill(v, (idx_t)l.n * l.n, 1.0f, st));
+  HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, st));
+  HIPCHK(p, launch_set_scalars(p->scal(), SC_VNORM, 1, nullptr, (double)l.n, st));
+  for (int it = 0; it < kPowerIters; ++it) {
+    int nb = 0;
+    tomo_status s = toeplitz_passes(p, l, MODE_POWER, 1, v, v, nullptr, w, false, &nb);
+    if (s != TOMO_OK) return s;
+    HIPCHK(p, launch_finalize(MODE_POWER, p->partials(), nb, p->scal(), nullptr, nullptr,
+                              nullptr, st));
+    std::swap(v, w);
+  }
+  double lam = 0.0;
+  HIPCHK(p, hipMemcpyAsync(&lam, p->scal() + SC_LAMBDA, sizeof(double), hipMemcpyDeviceToHost,
+                           st));
+  HIPCHK(p, hipStreamSynchronize(st));
+  if (!std::isfinite(lam) || lam <= 0.0)
+    return fail(p, TOMO_ERR_NONFINITE, "power iteration gave lambda = %g", lam);
+  l.lambda = lam;
+  l.L = 1.01 * lam + 2.0 * p->g.beta * p->rho2_0;
+  return TOMO_OK;
+}
+
+tomo_status validate_geom(const tomo_geometry_t* g) {
+  if (!g) return fail(nullptr, TOMO_ERR_INVALID_ARG, "geometry is NULL");
+  if (g->n < 16 || g->n > 2048 || (g->n & 1))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "n = %d must be even and in [16, 2048]", g->n);
+  if (g->n_slices < 1) return fail(nullptr, TOMO_ERR_INVALID_ARG, "n_slices must be >= 1");
+  if (g->n_angles < 1) return fail(nullptr, TOMO_ERR_INVALID_ARG, "n_angles must be >= 1");
+  if (g->n_det < 4 || (g->n_det & 1))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "n_det = %d must be even and >= 4", g->n_det);
+  if (g->n_det > 16384) return fail(nullptr, TOMO_ERR_INVALID_ARG, "n_det too large");
+  const int L = g->n_levels == 0 ? 1 : g->n_levels;
+  if (L < 1 || L > kMaxLevels)
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "n_levels must be in [1, %d]", kMaxLevels);
+  const int s = 1 << (L - 1);
+  if (g->n % s || (g->n / s) < 16 || ((g->n / s) & 1))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG,
+                "n must be divisible by 2^(n_levels-1) with an even coarsest width >= 16");
+  if (g->n_det % (2 * s))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG,
+                "n_det must be divisible by 2^n_levels (even bins on every level)");
+  if (g->pad != 0 && (!is_pow2(g->pad) || g->pad < 2 * g->n || g->pad > kMaxHot))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "pad must be 0 or a power of two in [2N, %d]",
+                kMaxHot);
+  const int W = g->kb_width == 0 ? 6 : g->kb_width;
+  if (W < 2 || W > 16) return fail(nullptr, TOMO_ERR_INVALID_ARG, "kb_width must be in [2, 16]");
+  const double sg = g->kb_oversamp == 0.0 ? 2.0 : g->kb_oversamp;
+  if (!(sg >= 1.25 && sg <= 4.0))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "kb_oversamp must be in [1.25, 4]");
+  if (!(g->kb_beta >= 0.0) || !std::isfinite(g->kb_beta))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "kb_beta must be >= 0");
+  if (!(g->beta >= 0.0) || !std::isfinite(g->beta))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "beta must be >= 0");
+  if (!(g->p >= 1.0 && g->p <= 2.0)) return fail(nullptr, TOMO_ERR_INVALID_ARG, "p must be in [1, 2]");
+  if (g->q != 2.0) return fail(nullptr, TOMO_ERR_INVALID_ARG, "q must be 2");
+  if (!(g->sigma > 0.0) || !std::isfinite(g->sigma))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "sigma must be > 0");
+  if (!(g->T > 0.0) || !std::isfinite(g->T)) return fail(nullptr, TOMO_ERR_INVALID_ARG, "T must be > 0");
+  if (g->neighbours != 8 && g->neighbours != 26)
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "neighbours must be 8 or 26");
+  if (g->flags != 0) return fail(nullptr, TOMO_ERR_INVALID_ARG, "flags must be 0");
+  if (g->angles)
+    for (int i = 0; i < g->n_angles; ++i)
+      if (!std::isfinite(g->angles[i]))
+        return fail(nullptr, TOMO_ERR_INVALID_ARG, "angle %d is not finite", i);
+  if (!std::isnan(g->center) && !std::isfinite(g->center))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "center must be finite or NaN");
+  return TOMO_OK;
+}
+
+}  // namespace
+
+// ===================================================================================== ABI
+extern "C" {
+
+tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo_plan* out) {
+  if (!out) return fail(nullptr, TOMO_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  tomo_status s = validate_geom(geom);
+  if (s != TOMO_OK) return s;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return fail(nullptr, TOMO_ERR_NO_DEVICE, "no HIP device visible");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, TOMO_ERR_NO_DEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(nullptr, TOMO_ERR_HIP, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, TOMO_ERR_UNSUPPORTED_ARCH, "device arch %s is not gfx950", prop.gcnArchName);
+
+  tomo_plan p = new tomo_plan_s();
+  p->g = *geom;
+  p->device = dev;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->nz = geom->n_slices;
+  p->n_levels = geom->n_levels == 0 ? 1 : geom->n_levels;
+  if (p->g.kb_width == 0) p->g.kb_width = 6;
+  if (p->g.kb_oversamp == 0.0) p->g.kb_oversamp = 2.0;
+  p->angles.resize(geom->n_angles);
+  for (int i = 0; i < geom->n_angles; ++i)
+    p->angles[i] = geom->angles ? geom->angles[i] : i * M_PI / geom->n_angles;
+  p->g.angles = nullptr;
+  const double center = std::isnan(geom->center) ? geom->n_det / 2.0 : geom->center;
+
+  const int L = p->n_levels;
+  p->lv.resize(L);
+  for (int l = 0; l < L; ++l) {
+    Level& lv = p->lv[l];
+    const int s = 1 << (L - 1 - l);
+    lv.stride = s;
+    lv.n = geom->n / s;
+    lv.nd = geom->n_det / s;
+    lv.c = center / s;
+    lv.P = geom->pad ? geom->pad / s : next_pow2(2LL * lv.n);
+    if (lv.P < kMinFft) lv.P = kMinFft;
+    lv.M = next_pow2((long long)std::ceil(p->g.kb_oversamp * lv.n - 1e-9));
+    if (lv.M < kMinFft) lv.M = kMinFft;
+    lv.Mpsf = next_pow2((long long)std::ceil(p->g.kb_oversamp * 2 * lv.n - 1e-9));
+    if (lv.Mpsf < kMinFft) lv.Mpsf = kMinFft;
+    if (lv.P > kMaxHot || lv.M > kMaxGrid || lv.Mpsf > kMaxGrid) {
+      delete p;
+      return fail(nullptr, TOMO_ERR_INVALID_ARG, "sizes exceed the supported FFT range");
+    }
+    lv.beta_bp = geom->kb_beta > 0.0 ? geom->kb_beta
+                                     : beatty_beta(p->g.kb_width, (double)lv.M / lv.n);
+    lv.beta_psf = geom->kb_beta > 0.0 ? geom->kb_beta
+                                      : beatty_beta(p->g.kb_width, (double)lv.Mpsf / (2.0 * lv.n));
+  }
+
+  // qGGMRF constants (q = 2)
+  const double pe = geom->p, q = geom->q, sg = geom->sigma, T = geom->T;
+  PriorParams& pp = p->pp;
+  pp.beta = (float)geom->beta;
+  pp.p = (float)pe;
+  pp.qmp = (float)(q - pe);
+  pp.q_over_p = (float)(q / pe);
+  pp.inv_Tsigma = (float)(1.0 / (T * sg));
+  pp.c_grad = (float)(std::pow(T * sg, pe - q) / std::pow(sg, pe));
+  pp.c_val = (float)(std::pow(T * sg, pe) / (pe * std::pow(sg, pe)));
+  pp.qm1 = (float)(q - 1.0);
+  const double r1 = 1.0, r2 = 1.0 / std::sqrt(2.0), r3 = 1.0 / std::sqrt(3.0);
+  const double sum = geom->neighbours == 26 ? 6 * r1 + 12 * r2 + 8 * r3 : 4 * r1 + 4 * r2;
+  pp.wts[0] = 0.f;
+  pp.wts[1] = (float)(r1 / sum);
+  pp.wts[2] = (float)(r2 / sum);
+  pp.wts[3] = (float)(r3 / sum);
+  pp.neighbours = geom->neighbours;
+  pp.quadratic = pe == q ? 1 : 0;
+  p->rho2_0 = pe == q ? 1.0 / (2.0 * sg * sg) : 2.0 / (pe * std::pow(T, 2.0 - pe) * sg * sg);
+
+  layout(p);
+  *out = p;
+  return TOMO_OK;
+}
+
+tomo_status tomo_plan_workspace_size(tomo_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  *bytes = p->need;
+  return TOMO_OK;
+}
+
+tomo_status tomo_plan_set_workspace(tomo_plan p, void* dev, size_t bytes) {
+  if (!p || !dev) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(dev)) return fail(p, TOMO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < p->need)
+    return fail(p, TOMO_ERR_WORKSPACE_TOO_SMALL, "workspace %zu B < required %zu B", bytes, p->need);
+  p->ws = static_cast<char*>(dev);
+  p->ws_bytes = bytes;
+  p->tables_ready = false;
+  p->psf_ready = false;
+  return TOMO_OK;
+}
+
+tomo_status tomo_precompute_psf(tomo_plan p) {
+  if (!p) return fail(nullptr, TOMO_ERR_INVALID_ARG, "plan is NULL");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  HIPCHK(p, hipSetDevice(p->device));
+  if ((s = ensure_tables(p)) != TOMO_OK) return s;
+  for (Level& l : p->lv)
+    if ((s = psf_level(p, l)) != TOMO_OK) return s;
+  p->psf_ready = true;
+  return TOMO_OK;
+}
+
+tomo_status tomo_backproject(tomo_plan p, const float* sino, float* out, int ramp) {
+  if (!p || !sino || !out) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(sino) || !aligned(out)) return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  HIPCHK(p, hipSetDevice(p->device));
+  if ((s = ensure_tables(p)) != TOMO_OK) return s;
+  return backproject_level(p, p->lv.back(), sino, out, ramp ? 1 : 0);
+}
+
+tomo_status tomo_apply_normal(tomo_plan p, const float* x, float* out) {
+  if (!p || !x || !out) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(x) || !aligned(out)) return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
+  if (x == out) return fail(p, TOMO_ERR_INVALID_ARG, "x and out must be distinct");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
+  HIPCHK(p, hipSetDevice(p->device));
+  HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, p->stream));
+  int nb = 0;
+  return toeplitz_passes(p, p->lv.back(), MODE_POWER, p->nz, x, x, nullptr, out, false, &nb);
+}
+
+tomo_status tomo_gradient(tomo_plan p, const float* x, const float* b, float* grad,
+                          double* obj_dev) {
+  if (!p || !x || !b || !grad) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(x) || !aligned(b) || !aligned(grad))
+    return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
+  if (grad == x || grad == b) return fail(p, TOMO_ERR_INVALID_ARG, "grad must not alias x or b");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
+  HIPCHK(p, hipSetDevice(p->device));
+  int nb = 0;
+  if ((s = toeplitz_passes(p, p->lv.back(), MODE_GRAD, p->nz, x, x, b, grad, obj_dev != nullptr,
+                           &nb)) != TOMO_OK)
+    return s;
+  HIPCHK(p, launch_finalize(MODE_GRAD, p->partials(), nb, p->scal(), nullptr, nullptr, obj_dev,
+                            p->stream));
+  return TOMO_OK;
+}
+
+tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
+                             const tomo_recon_opts_t* opts, tomo_recon_stats_t* stats) {
+  if (!p || !sino || !x || !opts || !opts->iters) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(sino) || !aligned(x)) return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
+  if (opts->init < TOMO_INIT_FBP || opts->init > TOMO_INIT_USER)
+    return fail(p, TOMO_ERR_INVALID_ARG, "unknown init");
+  if (opts->L_override < 0.0 || !std::isfinite(opts->L_override))
+    return fail(p, TOMO_ERR_INVALID_ARG, "L_override must be >= 0");
+  for (int l = 0; l < p->n_levels; ++l)
+    if (opts->iters[l] < 0) return fail(p, TOMO_ERR_INVALID_ARG, "iters must be >= 0");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  HIPCHK(p, hipSetDevice(p->device));
+  if ((s = ensure_tables(p)) != TOMO_OK) return s;
+  if (!p->psf_ready && (s = tomo_precompute_psf(p)) != TOMO_OK) return s;
+  hipStream_t st = p->stream;
+  double* sc = p->scal();
+  HIPCHK(p, launch_set_scalars(sc, SC_ITER, 1, nullptr, 0.0, st));
+  HIPCHK(p, launch_set_scalars(sc, SC_NRESTART, 1, nullptr, 0.0, st));
+  HIPCHK(p, launch_set_scalars(sc, SC_NONFINITE, 1, nullptr, -1.0, st));
+  HIPCHK(p, launch_set_scalars(sc, SC_BETA, 1, nullptr, p->g.beta, st));
+  HIPCHK(p, launch_set_scalars(sc, SC_RESTART_ON, 1, nullptr, opts->restart ? 1.0 : 0.0, st));
+
+  int cur = 0;  // buffer holding the current iterate
+  for (int li = 0; li < p->n_levels; ++li) {
+    const Level& l = p->lv[li];
+    const size_t vol = (size_t)p->nz * l.n * l.n;
+    float* b = p->at<float>(l.off_b);
+    if ((s = backproject_level(p, l, sino, b, 0)) != TOMO_OK) return s;
+    HIPCHK(p, launch_sumsq_strided(sino, (idx_t)p->nz * p->g.n_angles, l.nd, l.stride,
+                                   1.0 / l.stride, p->partials(), sc + SC_GG, st));
+    if (li == 0) {
+      if (opts->init == TOMO_INIT_FBP) {
+        if ((s = backproject_level(p, l, sino, p->xbuf(cur), 1)) != TOMO_OK) return s;
+      } else if (opts->init == TOMO_INIT_ZERO) {
+        HIPCHK(p, launch_fill(p->xbuf(cur), (idx_t)vol, 0.0f, st));
+      } else {
+        HIPCHK(p, hipMemcpyAsync(p->xbuf(cur), x, vol * sizeof(float), hipMemcpyDeviceToDevice, st));
+      }
+    } else {
+      const int nxt = (cur + 1) % 3;
+      HIPCHK(p, launch_lanczos_prolong(p->xbuf(cur), p->xbuf(nxt), p->lv[li - 1].n, p->nz, st));
+      cur = nxt;
+    }
+    const double L = opts->L_override > 0.0 ? opts->L_override : l.L;
+    HIPCHK(p, launch_set_scalars(sc, SC_MU, 1, nullptr, 0.0, st));
+    HIPCHK(p, launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st));
+    HIPCHK(p, launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / L, st));
+    int ik = cur, ikm1 = cur, inext = (cur + 1) % 3;
+    for (int k = 0; k < opts->iters[li]; ++k) {
+      int nb = 0;
+      if ((s = toeplitz_passes(p, l, MODE_FISTA, p->nz, p->xbuf(ik), p->xbuf(ikm1), b,
+                               p->xbuf(inext), opts->objective_dev != nullptr, &nb)) != TOMO_OK)
+        return s;
+      HIPCHK(p, launch_finalize(MODE_FISTA, p->partials(), nb, sc, opts->objective_dev,
+                                opts->restart_dev, nullptr, st));
+      // x_{k-1} <- x_k, x_k <- x_{k+1}; the freed buffer receives the next iterate
+      ikm1 = ik;
+      ik = inext;
+      inext = 3 - ik - ikm1;
+    }
+    cur = ik;
+  }
+  const size_t vol = (size_t)p->nz * p->lv.back().n * p->lv.back().n;
+  HIPCHK(p, hipMemcpyAsync(x, p->xbuf(cur), vol * sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (stats) {
+    double sv[SC_COUNT];
+    HIPCHK(p, hipMemcpyAsync(sv, sc, sizeof sv, hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    std::memset(stats, 0, sizeof *stats);
+    for (int l = 0; l < p->n_levels && l < 6; ++l) {
+      stats->L[l] = opts->L_override > 0.0 ? opts->L_override : p->lv[l].L;
+      stats->lambda_pow[l] = p->lv[l].lambda;
+    }
+    stats->n_restarts = (int32_t)sv[SC_NRESTART];
+    stats->nonfinite_iter = (int32_t)sv[SC_NONFINITE];
+    if (stats->nonfinite_iter >= 0)
+      return fail(p, TOMO_ERR_NONFINITE, "non-finite value at iteration %d", stats->nonfinite_iter);
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_psf_info(tomo_plan p, int32_t level, float* fk_dev, double* L_host,
+                          double* lambda_host) {
+  if (!p || level < 0 || level >= p->n_levels) return fail(p, TOMO_ERR_INVALID_ARG, "bad level");
+  if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
+  const Level& l = p->lv[level];
+  if (fk_dev) {
+    HIPCHK(p, hipSetDevice(p->device));
+    HIPCHK(p, launch_fk_export(p->at<float>(l.off_fk), p->at<float>(l.off_fkn), fk_dev, l.P,
+                               p->stream));
+  }
+  if (L_host) *L_host = l.L;
+  if (lambda_host) *lambda_host = l.lambda;
+  return TOMO_OK;
+}
+
+tomo_status tomo_level_dims(tomo_plan p, int32_t level, int32_t* n, int32_t* n_det, int32_t* pad) {
+  if (!p || level < 0 || level >= p->n_levels) return fail(p, TOMO_ERR_INVALID_ARG, "bad level");
+  const Level& l = p->lv[level];
+  if (n) *n = l.n;
+  if (n_det) *n_det = l.nd;
+  if (pad) *pad = l.P;
+  return TOMO_OK;
+}
+
+tomo_status tomo_lanczos_prolong(const float* in, float* out, int32_t n, int32_t n_slices,
+                                 void* hip_stream) {
+  if (!in || !out || n < 1 || n_slices < 1) return fail(nullptr, TOMO_ERR_INVALID_ARG, "bad argument");
+  hipError_t e = launch_lanczos_prolong(in, out, n, n_slices, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(nullptr, TOMO_ERR_HIP, "prolongation launch: %s", hipGetErrorString(e));
+  return TOMO_OK;
+}
+
+tomo_status tomo_plan_destroy(tomo_plan p) {
+  delete p;
+  return TOMO_OK;
+}
+
+const char* tomo_status_string(tomo_status s) {
+  switch (s) {
+    case TOMO_OK: return "ok";
+    case TOMO_ERR_INVALID_ARG: return "invalid argument";
+    case TOMO_ERR_NO_DEVICE: return "no HIP device";
+    case TOMO_ERR_UNSUPPORTED_ARCH: return "unsupported GPU architecture (needs gfx950)";
+    case TOMO_ERR_NO_WORKSPACE: return "no workspace attached";
+    case TOMO_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case TOMO_ERR_NOT_READY: return "PSF not precomputed";
+    case TOMO_ERR_HIP: return "HIP runtime error";
+    case TOMO_ERR_NONFINITE: return "non-finite value";
+    case TOMO_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* tomo_last_error(tomo_plan p) { return p ? p->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

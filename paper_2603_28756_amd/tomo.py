@@ -1,0 +1,235 @@
+"""ctypes binding of libtomo (the C ABI declared in include/tomo.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors, the workspace) and the HIP
+stream.  If the shared library has not been built, importing the binding's
+functions raises; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libtomo.so")
+
+TOMO_OK = 0
+STATUS_NAMES = {
+    0: "OK", 1: "INVALID_ARG", 2: "NO_DEVICE", 3: "UNSUPPORTED_ARCH", 4: "NO_WORKSPACE",
+    5: "WORKSPACE_TOO_SMALL", 6: "NOT_READY", 7: "HIP", 8: "NONFINITE", 9: "INTERNAL",
+}
+INIT_FBP, INIT_ZERO, INIT_USER = 0, 1, 2
+
+
+class TomoError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"tomo status {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("n_angles", ctypes.c_int32),
+        ("n_det", ctypes.c_int32), ("angles", ctypes.POINTER(ctypes.c_double)),
+        ("center", ctypes.c_double), ("pad", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+        ("kb_width", ctypes.c_int32), ("kb_oversamp", ctypes.c_double), ("kb_beta", ctypes.c_double),
+        ("beta", ctypes.c_double), ("p", ctypes.c_double), ("q", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("T", ctypes.c_double), ("neighbours", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class ReconOpts(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.POINTER(ctypes.c_int32)), ("init", ctypes.c_int32),
+        ("restart", ctypes.c_int32), ("L_override", ctypes.c_double),
+        ("objective_dev", ctypes.c_void_p), ("restart_dev", ctypes.c_void_p),
+    ]
+
+
+class ReconStats(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_double * 6), ("lambda_pow", ctypes.c_double * 6),
+        ("n_restarts", ctypes.c_int32), ("nonfinite_iter", ctypes.c_int32),
+    ]
+
+
+EXPORTS = {
+    "tomo_plan_create": ([ctypes.POINTER(Geometry), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "tomo_plan_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tomo_plan_set_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "tomo_precompute_psf": ([ctypes.c_void_p], ctypes.c_int),
+    "tomo_backproject": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "tomo_apply_normal": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_gradient": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_reconstruct": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ReconOpts),
+                          ctypes.POINTER(ReconStats)], ctypes.c_int),
+    "tomo_psf_info": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "tomo_level_dims": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "tomo_lanczos_prolong": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
+                             ctypes.c_int),
+    "tomo_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "tomo_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "tomo_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libtomo.so from the package's lib/ directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2603_28756_amd.build` "
+            "(there is no non-HIP implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (argt, rest) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argt
+        fn.restype = rest
+    _lib = lib
+    return lib
+
+
+def _check(status: int, plan=None):
+    if status != TOMO_OK:
+        lib = load_library()
+        msg = lib.tomo_last_error(plan).decode()
+        raise TomoError(status, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """One geometry/prior configuration bound to a device stream and a workspace tensor."""
+
+    def __init__(self, n: int, n_slices: int, n_angles: int, n_det: int,
+                 angles: Optional[Sequence[float]] = None, center: Optional[float] = None,
+                 pad: int = 0, n_levels: int = 1, kb_width: int = 6, kb_oversamp: float = 2.0,
+                 kb_beta: float = 0.0, beta: float = 0.01, p: float = 1.2, q: float = 2.0,
+                 sigma: float = 0.1, T: float = 1.0, neighbours: int = 26, stream=None,
+                 device: Optional[torch.device] = None):
+        lib = load_library()
+        self._lib = lib
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._angles = None
+        g = Geometry()
+        g.n, g.n_slices, g.n_angles, g.n_det = n, n_slices, n_angles, n_det
+        if angles is not None:
+            self._angles = (ctypes.c_double * n_angles)(*[float(a) for a in angles])
+            g.angles = ctypes.cast(self._angles, ctypes.POINTER(ctypes.c_double))
+        g.center = math.nan if center is None else float(center)
+        g.pad, g.n_levels, g.kb_width = pad, n_levels, kb_width
+        g.kb_oversamp, g.kb_beta = kb_oversamp, kb_beta
+        g.beta, g.p, g.q, g.sigma, g.T = beta, p, q, sigma, T
+        g.neighbours, g.flags = neighbours, 0
+        self.geometry = g
+        self.n, self.n_slices, self.n_angles, self.n_det = n, n_slices, n_angles, n_det
+        self.n_levels = n_levels
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.tomo_plan_create(ctypes.byref(g), _stream_ptr(self.stream), ctypes.byref(h)))
+        self._h = h
+        sz = ctypes.c_size_t()
+        _check(lib.tomo_plan_workspace_size(self._h, ctypes.byref(sz)), self._h)
+        self.workspace_bytes = sz.value
+        # 256-byte aligned caller-owned workspace
+        self._ws = torch.empty(sz.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        _check(lib.tomo_plan_set_workspace(self._h, ctypes.c_void_p(base + off), sz.value), self._h)
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tomo_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ calls
+    def precompute_psf(self):
+        _check(self._lib.tomo_precompute_psf(self._h), self._h)
+
+    def backproject(self, sino: torch.Tensor, out: torch.Tensor, ramp: bool = False):
+        _check(self._lib.tomo_backproject(self._h, _ptr(sino), _ptr(out), int(ramp)), self._h)
+
+    def apply_normal(self, x: torch.Tensor, out: torch.Tensor):
+        _check(self._lib.tomo_apply_normal(self._h, _ptr(x), _ptr(out)), self._h)
+
+    def gradient(self, x: torch.Tensor, b: torch.Tensor, grad: torch.Tensor,
+                 obj: Optional[torch.Tensor] = None):
+        _check(self._lib.tomo_gradient(self._h, _ptr(x), _ptr(b), _ptr(grad), _ptr(obj)), self._h)
+
+    def reconstruct(self, sino: torch.Tensor, x: torch.Tensor, iters: Sequence[int],
+                    init: int = INIT_FBP, restart: bool = True, L_override: float = 0.0,
+                    objective: Optional[torch.Tensor] = None,
+                    restarts: Optional[torch.Tensor] = None, stats: bool = True):
+        it = (ctypes.c_int32 * len(iters))(*[int(i) for i in iters])
+        o = ReconOpts()
+        o.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+        o.init, o.restart, o.L_override = init, int(restart), float(L_override)
+        o.objective_dev = _ptr(objective)
+        o.restart_dev = _ptr(restarts)
+        st = ReconStats() if stats else None
+        status = self._lib.tomo_reconstruct(self._h, _ptr(sino), _ptr(x), ctypes.byref(o),
+                                            ctypes.byref(st) if st is not None else None)
+        _check(status, self._h)
+        if st is None:
+            return None
+        return {"L": list(st.L)[: self.n_levels], "lambda_pow": list(st.lambda_pow)[: self.n_levels],
+                "n_restarts": st.n_restarts, "nonfinite_iter": st.nonfinite_iter}
+
+    def psf_info(self, level: int = -1, with_spectrum: bool = True):
+        level = self.n_levels - 1 if level < 0 else level
+        n, nd, pad = self.level_dims(level)
+        fk = torch.empty((pad, pad // 2 + 1), dtype=torch.float32, device=self.device) if with_spectrum else None
+        L = ctypes.c_double()
+        lam = ctypes.c_double()
+        _check(self._lib.tomo_psf_info(self._h, level, _ptr(fk), ctypes.byref(L), ctypes.byref(lam)), self._h)
+        return fk, L.value, lam.value
+
+    def level_dims(self, level: int):
+        n, nd, pad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.tomo_level_dims(self._h, level, ctypes.byref(n), ctypes.byref(nd), ctypes.byref(pad)),
+               self._h)
+        return n.value, nd.value, pad.value
+
+
+def lanczos_prolong(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """2x Lanczos-3 prolongation of each slice of x [n_z, n, n] (HIP kernel)."""
+    lib = load_library()
+    nz, n, n2 = x.shape
+    assert n == n2
+    if out is None:
+        out = torch.empty((nz, 2 * n, 2 * n), dtype=torch.float32, device=x.device)
+    _check(lib.tomo_lanczos_prolong(_ptr(x), _ptr(out), n, nz, _stream_ptr(stream)))
+    return out
