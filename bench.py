@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the Toeplitz MBIR path on one MI355X, as one JSON line.
+
+A step is one whole reconstruction of the 64 x 512^2 volume workload (180
+angles x 724 bins, 1% noise, Kaiser-Bessel width 6 and oversampling 2, PSF
+spectrum 1024^2, 100 accelerated-gradient iterations with the 26-neighbour
+qGGMRF prior): the float64 PSF-spectrum and step-constant precompute, the
+back-projection R* g, the FBP start and the 100 iterations.  Inputs are resident
+in device memory before the timed region starts.
+
+value = N^2 * n_slices * iterations / (seconds per step)   [gradient voxel-updates/s]
+
+roofline: the kernel class with the largest share of the step is timed live with
+HIP events on the plan's stream over the timed region; its algorithmic bytes per
+launch divided by its mean launch time is compared with the 8 TB/s HBM peak.
+cpu_baseline: the FP64 oracle's own iteration (Toeplitz product by numpy FFTs,
+prior, update) timed on a bounded slab of the same volume on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CLASS_NAMES = ["rows_fwd", "cols_conv", "rows_inv", "finalize", "backproject", "psf", "prior"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_volume_64x512.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_28756_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(cls: str, n: int, nz: int, P: int) -> float:
+    """Bytes each kernel class must move per launch (compulsory reads + writes)."""
+    H = P // 2
+    spec = 8.0 * nz * n * H          # one half spectrum S1 or S2 (complex64)
+    vol = 4.0 * nz * n * n           # one float32 volume
+    fk = 4.0 * P * (H + 1)           # PSF spectrum (float32)
+    if cls == "rows_fwd":            # read x_k, x_{k-1}; write S1
+        return 2 * vol + spec
+    if cls == "cols_conv":           # read S1 and F K; write S2
+        return 2 * spec + fk
+    if cls == "rows_inv":            # read S2, x_k, x_{k-1}, b, prior gradient; write x_{k+1}
+        return spec + 5 * vol
+    if cls == "prior":               # read x_k, x_{k-1}; write the prior gradient
+        return 3 * vol
+    return float("nan")
+
+
+def cpu_baseline(wl, prob_np, iters: int = 3, slices: int = 4) -> dict:
+    """Oracle FISTA on a contiguous slab of `slices` slices, `iters` iterations."""
+    import numpy as np
+    from oracle import geometry as G
+    from oracle import prior as qg
+    from oracle import radon, solver, toeplitz
+    geom = G.Geometry(wl.n, prob_np["angles"], wl.n_det)
+    z0 = wl.n_slices // 2 - slices // 2
+    sino = prob_np["sino32"][z0:z0 + slices].astype(np.float64)
+    pr = qg.QGGMRF(p=wl.p, q=wl.q, sigma=wl.sigma, T=wl.T, neighbours=wl.neighbours)
+    P = solver.pad_size(wl.n)
+    t0 = time.perf_counter()
+    fk = toeplitz.psf_spectrum(geom, P)
+    b = radon.adjoint(sino, geom)
+    t_pre = time.perf_counter() - t0
+    prob = solver.Problem(geom, fk, b, float(np.vdot(sino, sino)), pr, wl.beta)
+    x0 = b * 0.0
+    L = solver.lipschitz(prob)
+    t0 = time.perf_counter()
+    solver.fista(prob, x0, iters, L=L)
+    t_it = time.perf_counter() - t0
+    vox = slices * wl.n * wl.n * iters
+    return {"value": vox / t_it, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{slices} of {wl.n_slices} slices (z {z0}..{z0 + slices - 1}), {iters} FISTA "
+                       f"iterations of the float64 oracle (numpy FFT Toeplitz product, 26-neighbour "
+                       f"prior, update), {t_it:.1f} s; oracle PSF spectrum + R*g precompute of the "
+                       f"slab took {t_pre:.1f} s and the step constant is not in the rate either"),
+            "host_cpus": os.cpu_count()}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="volume_64x512")
+    ap.add_argument("--iters", type=int, default=0, help="override the workload's iteration count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fused-prior", action="store_true",
+                    help="evaluate the prior inside the epilogue (comparison variant)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard along the slice axis, see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+
+    if args.copy_calib:
+        n = 256 * 1024 * 1024 // 4   # 256 MiB read + 256 MiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": 4 * n, "copy_calib_bytes_written": 4 * n}))
+        return 0
+
+    import synth
+    from paper_2603_28756_amd import tomo
+
+    wl = synth.WORKLOADS[args.workload]
+    iters = list(wl.iterations) if not args.iters else [args.iters] * wl.levels
+    pr = synth.make_problem(wl.n, wl.n_slices, wl.n_angles, wl.n_det, wl.noise, wl.seed, wl.n_objects)
+    sino32 = pr["sino"].astype(np.float32)
+    prob_np = {"angles": pr["angles"], "sino32": sino32}
+    sino = torch.from_numpy(sino32).to(dev)
+    plan = tomo.Plan(wl.n, wl.n_slices, wl.n_angles, wl.n_det, angles=list(pr["angles"]),
+                     n_levels=wl.levels, kb_width=wl.kb_width, kb_oversamp=wl.kb_oversamp,
+                     beta=wl.beta, p=wl.p, q=wl.q, sigma=wl.sigma, T=wl.T,
+                     neighbours=wl.neighbours, device=dev, fused_prior=args.fused_prior)
+    x = torch.empty((wl.n_slices, wl.n, wl.n), dtype=torch.float32, device=dev)
+    _, _, P = plan.level_dims(wl.levels - 1)
+
+    def step():
+        plan.precompute_psf()
+        plan.reconstruct(sino, x, iters, init=tomo.INIT_FBP, stats=False)
+
+    for _ in range(args.warmup):
+        step()
+    # one step with every class timed: the breakdown, and which class dominates
+    plan.timing_enable(range(tomo.T_COUNT))
+    step()
+    ms_all, cnt_all = plan.timing_read()
+    breakdown = {CLASS_NAMES[i]: {"total_ms": ms_all[i], "launches": cnt_all[i],
+                                  "mean_ms": ms_all[i] / cnt_all[i] if cnt_all[i] else None}
+                 for i in range(tomo.T_COUNT)}
+    iter_classes = [tomo.T_ROWS_FWD, tomo.T_COLS_CONV, tomo.T_ROWS_INV, tomo.T_PRIOR]
+    hot = max(iter_classes, key=lambda i: ms_all[i])
+
+    # timed region: only the dominant class carries events
+    plan.timing_enable([hot])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    ms_hot, cnt_hot = plan.timing_read()
+    mean_hot_ms = ms_hot[hot] / max(cnt_hot[hot], 1)
+
+    total_iters = sum(iters)
+    vox = wl.n * wl.n * wl.n_slices * total_iters
+    value = vox / (ms_per_step * 1e-3)
+    iter_ms = sum(breakdown[CLASS_NAMES[i]]["total_ms"]
+                  for i in iter_classes + [tomo.T_FINALIZE]) / total_iters
+    name = CLASS_NAMES[hot]
+    alg = algorithmic_bytes(name, wl.n, wl.n_slices, P)
+    achieved = alg / (mean_hot_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash() and name in tr.get("kernels", {}):
+            traffic = tr["kernels"][name]["bytes_per_launch"]
+    out = {
+        "metric": "gradient voxel-updates/s",
+        "value": value,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "n": wl.n, "n_slices": wl.n_slices, "n_angles": wl.n_angles,
+            "n_det": wl.n_det, "iterations": iters, "pad": P, "kb_width": wl.kb_width,
+            "kb_oversamp": wl.kb_oversamp, "neighbours": wl.neighbours, "noise": wl.noise,
+            "step": "PSF spectrum + step constant precompute, R*g, FBP start, iterations",
+            "prior": "fused epilogue" if args.fused_prior else "pair-shared kernel",
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg, "mean_launch_ms": mean_hot_ms,
+            "launches_timed": cnt_hot[hot],
+        },
+        "iteration_ms": iter_ms,
+        "iteration_voxel_updates_per_s": wl.n * wl.n * wl.n_slices / (iter_ms * 1e-3),
+        "effective_hbm_frac_20B": 20.0 * wl.n * wl.n * wl.n_slices / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "breakdown_one_step": breakdown,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, prob_np)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

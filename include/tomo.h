@@ -93,8 +93,17 @@ typedef struct {
   double sigma;           /* qGGMRF scale sigma > 0                                        */
   double T;               /* qGGMRF threshold T > 0                                        */
   int32_t neighbours;     /* 8 (in-plane) or 26 (3D)                                       */
-  uint32_t flags;         /* reserved, must be 0                                           */
+  uint32_t flags;         /* TOMO_FLAG_* bits; other bits must be 0                        */
 } tomo_geometry_t;
+
+/* tomo_geometry_t.flags: run every iteration with direct launches instead of replaying
+ * captured three-iteration HIP graphs (which tomo_reconstruct uses for levels with at
+ * least 7 iterations, on an internal stream ordered after the plan's stream). */
+#define TOMO_FLAG_NO_GRAPH 1u
+/* tomo_geometry_t.flags: evaluate the qGGMRF gradient inside the inverse-row epilogue over a
+ * neighbour tile (each pair evaluated from both of its voxels) instead of the separate
+ * z-marching prior kernel that evaluates each pair once.  Same results to rounding. */
+#define TOMO_FLAG_FUSED_PRIOR 2u
 
 /* Options of tomo_reconstruct(). */
 typedef struct {
@@ -197,6 +206,31 @@ tomo_status tomo_level_dims(tomo_plan plan, int32_t level, int32_t* n, int32_t* 
  * Errors: INVALID_ARG, HIP. */
 tomo_status tomo_lanczos_prolong(const float* in, float* out, int32_t n, int32_t n_slices,
                                  void* hip_stream);
+
+/* Kernel classes timed by tomo_timing_enable(). */
+enum {
+  TOMO_T_ROWS_FWD = 0,     /* Toeplitz pass R: row FFTs of the padded iterate            */
+  TOMO_T_COLS_CONV = 1,    /* pass C: column FFT, PSF-spectrum multiply, inverse FFT     */
+  TOMO_T_ROWS_INV = 2,     /* pass R': inverse row FFTs, crop, prior, update epilogue    */
+  TOMO_T_FINALIZE = 3,     /* float64 reduction and momentum/restart update              */
+  TOMO_T_BACKPROJECT = 4,  /* one whole back-projection / FBP                            */
+  TOMO_T_PSF = 5,          /* one whole PSF spectrum + step-constant precompute          */
+  TOMO_T_PRIOR = 6,        /* qGGMRF gradient kernel (pair-shared, z-marching)           */
+  TOMO_T_COUNT = 7
+};
+
+/* Diagnostics: record a pair of HIP events on the plan's stream around every
+ * launch of the kernel classes set in `class_mask` (bit i = class i; 0 turns
+ * timing off) and reset the accumulators.  Event recording adds a few
+ * microseconds of stream overhead per timed launch and nothing else.
+ * Errors: INVALID_ARG, HIP. */
+tomo_status tomo_timing_enable(tomo_plan plan, uint32_t class_mask);
+
+/* Synchronise the plan's stream and return, per class, the summed event time
+ * in milliseconds (host float64[TOMO_T_COUNT]) and the number of timed launches
+ * (host int64[TOMO_T_COUNT]); either pointer may be NULL.  Accumulators keep
+ * running.  Errors: INVALID_ARG, HIP. */
+tomo_status tomo_timing_read(tomo_plan plan, double* total_ms, int64_t* counts);
 
 /* Destroy a plan (NULL is accepted).  Does not free the caller's workspace. */
 tomo_status tomo_plan_destroy(tomo_plan plan);

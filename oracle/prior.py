@@ -125,3 +125,19 @@ def gradient(f: np.ndarray, pr: QGGMRF) -> np.ndarray:
         s, r = _pair_views(f, o)
         g[s] += w[o] * rho_prime(f[s] - f[r], pr)
     return g
+
+
+def gradient_at(f: np.ndarray, pr: QGGMRF, voxels) -> np.ndarray:
+    """dPhi/df_s at the listed voxels (z, y, x), summing over in-volume neighbours."""
+    f = np.asarray(f, dtype=np.float64)
+    w = weights(pr.neighbours)
+    nz, ny, nx = f.shape
+    out = np.zeros(len(voxels), dtype=np.float64)
+    for m, (z, y, x) in enumerate(voxels):
+        acc = 0.0
+        for (dz, dy, dx), b in w.items():
+            zz, yy, xx = z + dz, y + dy, x + dx
+            if 0 <= zz < nz and 0 <= yy < ny and 0 <= xx < nx:
+                acc += b * float(rho_prime(np.array([f[z, y, x] - f[zz, yy, xx]]), pr)[0])
+        out[m] = acc
+    return out

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .geometry import Geometry, pixel_coords, radial_indices, radial_freqs
+from .geometry import Geometry, pixel_coords, polar_points, radial_indices, radial_freqs
 
 
 def _angle_factors(geom: Geometry, i: int, sign: float):
@@ -87,3 +87,14 @@ def adjoint(g: np.ndarray, geom: Geometry) -> np.ndarray:
     if g.ndim == 3:
         return np.stack([adjoint(s, geom) for s in g])
     return polar_to_image(sino_spectrum(g, geom), geom)
+
+
+def polar_to_pixels(gh: np.ndarray, geom: Geometry, ys, xs) -> np.ndarray:
+    """The same sum as ``polar_to_image`` evaluated only at pixels (ys[m], xs[m])."""
+    k = polar_points(geom)
+    c = pixel_coords(geom.n)
+    out = np.empty(len(ys), dtype=np.float64)
+    for m, (iy, ix) in enumerate(zip(ys, xs)):
+        phase = 2.0 * np.pi * (k[..., 0] * c[ix] + k[..., 1] * c[iy])
+        out[m] = float(np.sum((gh * np.exp(1j * phase)).real))
+    return out

@@ -42,13 +42,21 @@ hipError_t launch_rows_fwd(int P, int mode, const float* xk, const float* xkm1,
 hipError_t launch_cols_conv(int P, const cpx<float>* S1, cpx<float>* S2, const float* fk,
                             const float* fkn, const cpx<float>* tw, int N, int nz, hipStream_t st);
 // Pass R': inverse row C2R + crop + epilogue; writes partial sums [nblocks][4].
+// gpv: prior gradient beta grad Phi(y) from launch_prior, or NULL to evaluate the prior
+// inside the epilogue over a neighbour tile.
 hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj,
                            const cpx<float>* S2, const float* xk, const float* xkm1,
-                           const float* b, float* out, double* partials, const double* scal,
-                           const cpx<float>* tw, int N, int nz, const PriorParams& pp,
-                           int* nblocks_out, hipStream_t st);
+                           const float* b, const float* gpv, float* out, double* partials,
+                           const double* scal, const cpx<float>* tw, int N, int nz,
+                           const PriorParams& pp, int* nblocks_out, hipStream_t st);
+// Prior gradient (and Phi partial sums [blocks][4], slot 0, when with_obj) over z-marching tiles.
+int prior_blocks(int N, int nz);
+hipError_t launch_prior(int mode, int neighbours, bool with_obj, const float* xk,
+                        const float* xkm1, const double* scal, float* gp, double* partials,
+                        int N, int nz, const PriorParams& pp, hipStream_t st);
 // Deterministic float64 reduction of the partials + scalar update.
-hipError_t launch_finalize(int mode, const double* partials, int nblocks, double* scal,
+hipError_t launch_finalize(int mode, const double* partials, int nblocks,
+                           const double* prior_partials, int nprior, double* scal,
                            double* obj_hist, int32_t* restart_hist, double* obj_out,
                            hipStream_t st);
 

@@ -209,21 +209,175 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
     }
 }
 
+// ---------------------------------------------------------------------------- prior (3D)
+// gp = beta grad Phi(y) with y = x_k + mu (x_k - x_{k-1}), evaluated once per neighbour pair.
+// A block owns a TR x TCc column of voxels and marches through ZC slices, keeping three
+// y planes (with a one-voxel halo) in LDS.  Per plane it evaluates rho' once for each
+// in-plane pair (4 lexicographically positive offsets) and for each pair crossing to the
+// next plane (9 offsets); a pair's value enters its first voxel with + and its second with -
+// (rho' is odd), so every pair inside the tile is evaluated once instead of twice.
+// With OBJ the block also sums rho over the pairs whose first voxel it owns.
+constexpr int PR_TR = 16, PR_TC = 32, PR_ZC = 16, PR_NT = 256;
+
+template <int NB, bool OBJ>
+__global__ void __launch_bounds__(PR_NT)
+prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
+             const double* __restrict__ scal, float* __restrict__ gp,
+             double* __restrict__ partials, int N, int nz, int mode_fista, PriorParams pp) {
+  constexpr int TR = PR_TR, TCc = PR_TC, ZC = PR_ZC, NT = PR_NT;
+  constexpr int HR = TR + 2, HC = TCc + 2, HA = HR * HC;
+  constexpr int VPT = TR * TCc / NT;
+  __shared__ float ybuf[3][HA];
+  __shared__ float pin[4][HA];
+  __shared__ float pz[NB == 26 ? 9 : 1][HA];
+  __shared__ double sred[(NT / 64) * 4];
+
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.x * TCc, r0 = blockIdx.y * TR, z0 = blockIdx.z * ZC;
+  const int z1 = min(z0 + ZC, nz);
+  const float mu = mode_fista ? (float)scal[SC_MU] : 0.f;
+
+  auto load_plane = [&](int z, float* dst) {
+    for (int e = t; e < HA; e += NT) {
+      const int hr = e / HC, hc = e - hr * HC;
+      const int r = r0 - 1 + hr, c = c0 - 1 + hc;
+      float v = 0.f;
+      if (r >= 0 && r < N && c >= 0 && c < N) {
+        const idx_t o = ((idx_t)z * N + r) * N + c;
+        const float a = xk[o];
+        v = mode_fista ? a + mu * (a - xkm1[o]) : a;
+      }
+      dst[e] = v;
+    }
+  };
+  auto inside = [&](int hr, int hc) {
+    const int r = r0 - 1 + hr, c = c0 - 1 + hc;
+    return r >= 0 && r < N && c >= 0 && c < N;
+  };
+  auto owned = [&](int hr, int hc) { return hr >= 1 && hr <= TR && hc >= 1 && hc <= TCc; };
+
+  float acc[VPT], accn[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) acc[j] = accn[j] = 0.f;
+  double phi = 0.0;
+
+  int bp = 0, bc = 1, bn = 2;  // previous / current / next plane buffers
+  load_plane(z0, ybuf[bc]);
+  if (NB == 26 && z0 > 0) load_plane(z0 - 1, ybuf[bp]);
+  __syncthreads();
+
+  // cross-plane pairs between planes (zs, zs+1) held in buffers (b0, b1); contributions
+  // to the upper plane's voxels go to accn (sign -), to the lower plane's to acc (sign +)
+  auto cross = [&](int b0, int b1, bool count_phi, bool lower_is_output) {
+    for (int e = t; e < 9 * HA; e += NT) {
+      const int o = e / HA, pidx = e - o * HA;
+      const int dy = o / 3 - 1, dx = o % 3 - 1;
+      const int hr = pidx / HC, hc = pidx - hr * HC;
+      const int qr = hr + dy, qc = hc + dx;
+      float val = 0.f;
+      if (qr >= 0 && qr < HR && qc >= 0 && qc < HC && inside(hr, hc) && inside(qr, qc)) {
+        float rv = 0.f;
+        qggmrf<OBJ>(ybuf[b0][pidx] - ybuf[b1][qr * HC + qc], pp, val, rv);
+        if (OBJ && count_phi && owned(hr, hc))
+          phi += (double)(pp.wts[1 + (dy != 0) + (dx != 0)] * rv);
+      }
+      pz[o][pidx] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = t + j * NT, vr = v / TCc, vc = v - vr * TCc;
+      const int sidx = (vr + 1) * HC + vc + 1;
+      float up = 0.f, dn = 0.f;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        const int dy = o / 3 - 1, dx = o % 3 - 1;
+        const float w = pp.wts[1 + (dy != 0) + (dx != 0)];
+        if (lower_is_output) up += w * pz[o][sidx];
+        dn += w * pz[o][sidx - (dy * HC + dx)];
+      }
+      if (lower_is_output) acc[j] += up;
+      accn[j] -= dn;
+    }
+    __syncthreads();
+  };
+
+  if (NB == 26 && z0 > 0) {
+    cross(bp, bc, false, false);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      acc[j] = accn[j];
+      accn[j] = 0.f;
+    }
+  }
+
+  for (int z = z0; z < z1; ++z) {
+    const bool has_next = NB == 26 && z + 1 < nz;
+    if (has_next) load_plane(z + 1, ybuf[bn]);
+    // in-plane pairs: offsets (0,1), (1,-1), (1,0), (1,1) in (dy, dx)
+    for (int e = t; e < 4 * HA; e += NT) {
+      const int o = e / HA, pidx = e - o * HA;
+      const int dy = o == 0 ? 0 : 1, dx = o == 0 ? 1 : o - 2;
+      const int hr = pidx / HC, hc = pidx - hr * HC;
+      const int qr = hr + dy, qc = hc + dx;
+      float val = 0.f;
+      if (qr < HR && qc >= 0 && qc < HC && inside(hr, hc) && inside(qr, qc)) {
+        float rv = 0.f;
+        qggmrf<OBJ>(ybuf[bc][pidx] - ybuf[bc][qr * HC + qc], pp, val, rv);
+        if (OBJ && owned(hr, hc)) phi += (double)(pp.wts[1 + (dy != 0 && dx != 0)] * rv);
+      }
+      pin[o][pidx] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = t + j * NT, vr = v / TCc, vc = v - vr * TCc;
+      const int sidx = (vr + 1) * HC + vc + 1;
+      float a = 0.f;
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const int dy = o == 0 ? 0 : 1, dx = o == 0 ? 1 : o - 2;
+        const float w = pp.wts[1 + (dy != 0 && dx != 0)];
+        a += w * (pin[o][sidx] - pin[o][sidx - (dy * HC + dx)]);
+      }
+      acc[j] += a;
+    }
+    __syncthreads();
+    if (has_next) cross(bc, bn, true, true);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = t + j * NT, vr = v / TCc, vc = v - vr * TCc;
+      const int r = r0 + vr, c = c0 + vc;
+      if (r < N && c < N) gp[((idx_t)z * N + r) * N + c] = pp.beta * acc[j];
+      acc[j] = accn[j];
+      accn[j] = 0.f;
+    }
+    const int tmp = bp;
+    bp = bc;
+    bc = bn;
+    bn = tmp;
+  }
+  if (partials) {
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum4<NT>(phi, 0.0, 0.0, 0.0, partials + (idx_t)bid * 4, sred);
+  }
+}
+
 // --------------------------------------------------------------------------------- pass R'
 template <int P, int PAIRS, int MODE, int NB, bool OBJ>
 __global__ void __launch_bounds__(PAIRS * (P / kE))
 rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
                 const float* __restrict__ xkm1, const float* __restrict__ bvec,
-                float* __restrict__ out, double* __restrict__ partials,
-                const double* __restrict__ scal, const cpx<float>* __restrict__ tw, int N,
-                int nz, PriorParams pp) {
+                const float* __restrict__ gpv, float* __restrict__ out,
+                double* __restrict__ partials, const double* __restrict__ scal,
+                const cpx<float>* __restrict__ tw, int N, int nz, PriorParams pp) {
   using PL = fft::Plan<P, kE>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int NT = PAIRS * TPF, RB = 2 * PAIRS, H = P / 2;
   constexpr int REG = fft::row_region<P>();
   constexpr int CW = 64;
   constexpr int ZD = (NB == 26) ? 3 : 1;
-  constexpr int YT = ZD * (RB + 2) * (CW + 2);
+  constexpr int YT = NB == 0 ? 1 : ZD * (RB + 2) * (CW + 2);
   constexpr int FFT_BYTES = PAIRS * REG * 8;
   constexpr int YT_BYTES = YT * 4;
   constexpr int A_BYTES = FFT_BYTES > YT_BYTES ? FFT_BYTES : YT_BYTES;
@@ -285,7 +439,31 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
   __syncthreads();
 
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  if constexpr (MODE == MODE_POWER) {
+  if constexpr (MODE != MODE_POWER && NB == 0) {
+    // prior gradient precomputed by prior_kernel: point-wise epilogue, no neighbour tile
+    const float mu = (MODE == MODE_FISTA) ? (float)scal[SC_MU] : 0.f;
+    const float invL = (MODE == MODE_FISTA) ? (float)scal[SC_INVL] : 0.f;
+    for (int e = t; e < RB * N; e += NT) {
+      const int ry = e / N, col = e - ry * N, row = r0 + ry;
+      if (row < N) {
+        const idx_t o = ((idx_t)z * N + row) * N + col;
+        const float a = xk[o];
+        const float ys = (MODE == MODE_FISTA) ? a + mu * (a - xkm1[o]) : a;
+        const float ty = tyt[ry * H + col];
+        const float bs = bvec[o];
+        const float g = ty - bs + gpv[o];
+        if constexpr (MODE == MODE_FISTA) {
+          const float xn = ys - g * invL;
+          out[o] = xn;
+          acc3 += (double)(ys - xn) * (double)(xn - a);
+        } else {
+          out[o] = g;
+        }
+        acc0 += (double)ys * (double)ty;
+        acc1 += (double)ys * (double)bs;
+      }
+    }
+  } else if constexpr (MODE == MODE_POWER) {
     for (int e = t; e < RB * N; e += NT) {
       const int ry = e / N, col = e - ry * N, row = r0 + ry;
       if (row < N) {
@@ -331,11 +509,13 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
 #pragma unroll
               for (int dx = -1; dx <= 1; ++dx) {
                 if (dz == 0 && dy == 0 && dx == 0) continue;
-                if (!(vz[dz + 1] && vy[dy + 1] && vx[dx + 1])) continue;
+                // a neighbour outside the volume enters with difference 0, where rho and
+                // rho' vanish exactly: the pair is omitted without a branch
+                const bool valid = vz[dz + 1] && vy[dy + 1] && vx[dx + 1];
                 const float yn = ytile[cidx + (dz * (RB + 2) + dy) * (CW + 2) + dx];
                 const float wgt = pp.wts[(dz != 0) + (dy != 0) + (dx != 0)];
                 float rp, rv = 0.f;
-                qggmrf<OBJ>(ys - yn, pp, rp, rv);
+                qggmrf<OBJ>(valid ? ys - yn : 0.f, pp, rp, rv);
                 gsum += wgt * rp;
                 if constexpr (OBJ) {
                   // each unordered pair once: the lexicographically positive offset
@@ -370,7 +550,8 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
 // -------------------------------------------------------------------------------- finalize
 template <int MODE>
 __global__ void __launch_bounds__(256)
-finalize_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ scal,
+finalize_kernel(const double* __restrict__ partials, int nblocks,
+                const double* __restrict__ prior_partials, int nprior, double* __restrict__ scal,
                 double* __restrict__ hist, int32_t* __restrict__ rhist,
                 double* __restrict__ obj_out) {
   __shared__ double sh[4][256];
@@ -379,6 +560,8 @@ finalize_kernel(const double* __restrict__ partials, int nblocks, double* __rest
   for (int b = t; b < nblocks; b += 256)
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] += partials[(idx_t)b * 4 + i];
+  // Phi from the separate prior kernel (slot 0 of its partials) lands in slot 2
+  for (int b = t; b < nprior; b += 256) a[2] += prior_partials[(idx_t)b * 4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) sh[i][t] = a[i];
   __syncthreads();
@@ -475,28 +658,32 @@ hipError_t cols_conv_p(const cpx<float>* S1, cpx<float>* S2, const float* fk, co
 
 template <int P, int MODE, int NB, bool OBJ>
 hipError_t rows_inv_launch(const cpx<float>* S2, const float* xk, const float* xkm1,
-                           const float* b, float* out, double* partials, const double* scal,
-                           const cpx<float>* tw, int N, int nz, const PriorParams& pp,
-                           int* nblocks, hipStream_t st) {
+                           const float* b, const float* gpv, float* out, double* partials,
+                           const double* scal, const cpx<float>* tw, int N, int nz,
+                           const PriorParams& pp, int* nblocks, hipStream_t st) {
   constexpr int PAIRS = inv_pairs(P);
   constexpr int NT = PAIRS * fft::Plan<P, kE>::TPF;
   constexpr int RB = 2 * PAIRS;
   const int nb = nz * ((N + RB - 1) / RB);
   *nblocks = nb;
   hipLaunchKernelGGL((rows_inv_kernel<P, PAIRS, MODE, NB, OBJ>), dim3(nb), dim3(NT), 0, st, S2,
-                     xk, xkm1, b, out, partials, scal, tw, N, nz, pp);
+                     xk, xkm1, b, gpv, out, partials, scal, tw, N, nz, pp);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t rows_inv_p(int mode, int nbh, bool obj, const cpx<float>* S2, const float* xk,
-                      const float* xkm1, const float* b, float* out, double* partials,
-                      const double* scal, const cpx<float>* tw, int N, int nz,
+                      const float* xkm1, const float* b, const float* gpv, float* out,
+                      double* partials, const double* scal, const cpx<float>* tw, int N, int nz,
                       const PriorParams& pp, int* nblocks, hipStream_t st) {
-#define TOMO_INV(MODE, NB, OBJ)                                                              \
-  return rows_inv_launch<P, MODE, NB, OBJ>(S2, xk, xkm1, b, out, partials, scal, tw, N, nz, \
+#define TOMO_INV(MODE, NB, OBJ)                                                                 \
+  return rows_inv_launch<P, MODE, NB, OBJ>(S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, nz, \
                                            pp, nblocks, st)
   if (mode == MODE_POWER) TOMO_INV(MODE_POWER, 8, false);
+  if (gpv) {  // prior gradient precomputed
+    if (mode == MODE_GRAD) TOMO_INV(MODE_GRAD, 0, false);
+    TOMO_INV(MODE_FISTA, 0, false);
+  }
   if (mode == MODE_GRAD) {
     if (nbh == 26) { if (obj) TOMO_INV(MODE_GRAD, 26, true); TOMO_INV(MODE_GRAD, 26, false); }
     if (obj) TOMO_INV(MODE_GRAD, 8, true);
@@ -556,28 +743,58 @@ hipError_t launch_cols_conv(int P, const cpx<float>* S1, cpx<float>* S2, const f
 }
 
 hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj, const cpx<float>* S2,
-                           const float* xk, const float* xkm1, const float* b, float* out,
-                           double* partials, const double* scal, const cpx<float>* tw, int N,
-                           int nz, const PriorParams& pp, int* nblocks_out, hipStream_t st) {
-#define CALL(PP)                                                                         \
-  rows_inv_p<PP>(mode, neighbours, with_obj, S2, xk, xkm1, b, out, partials, scal, tw, N, \
+                           const float* xk, const float* xkm1, const float* b, const float* gpv,
+                           float* out, double* partials, const double* scal,
+                           const cpx<float>* tw, int N, int nz, const PriorParams& pp,
+                           int* nblocks_out, hipStream_t st) {
+#define CALL(PP)                                                                              \
+  rows_inv_p<PP>(mode, neighbours, with_obj, S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, \
                  nz, pp, nblocks_out, st)
   TOMO_PSWITCH(CALL)
 #undef CALL
 }
 
-hipError_t launch_finalize(int mode, const double* partials, int nblocks, double* scal,
+int prior_blocks(int N, int nz) {
+  return ((N + PR_TC - 1) / PR_TC) * ((N + PR_TR - 1) / PR_TR) * ((nz + PR_ZC - 1) / PR_ZC);
+}
+
+hipError_t launch_prior(int mode, int neighbours, bool with_obj, const float* xk,
+                        const float* xkm1, const double* scal, float* gp, double* partials,
+                        int N, int nz, const PriorParams& pp, hipStream_t st) {
+  const dim3 grid((N + PR_TC - 1) / PR_TC, (N + PR_TR - 1) / PR_TR, (nz + PR_ZC - 1) / PR_ZC);
+  const int fista = mode == MODE_FISTA ? 1 : 0;
+  double* part = with_obj ? partials : nullptr;
+  if (neighbours == 26) {
+    if (with_obj)
+      hipLaunchKernelGGL((prior_kernel<26, true>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
+                         part, N, nz, fista, pp);
+    else
+      hipLaunchKernelGGL((prior_kernel<26, false>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
+                         part, N, nz, fista, pp);
+  } else {
+    if (with_obj)
+      hipLaunchKernelGGL((prior_kernel<8, true>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
+                         part, N, nz, fista, pp);
+    else
+      hipLaunchKernelGGL((prior_kernel<8, false>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
+                         part, N, nz, fista, pp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int mode, const double* partials, int nblocks,
+                           const double* prior_partials, int nprior, double* scal,
                            double* obj_hist, int32_t* restart_hist, double* obj_out,
                            hipStream_t st) {
   if (mode == MODE_POWER)
     hipLaunchKernelGGL((finalize_kernel<MODE_POWER>), dim3(1), dim3(256), 0, st, partials,
-                       nblocks, scal, obj_hist, restart_hist, obj_out);
+                       nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   else if (mode == MODE_GRAD)
     hipLaunchKernelGGL((finalize_kernel<MODE_GRAD>), dim3(1), dim3(256), 0, st, partials,
-                       nblocks, scal, obj_hist, restart_hist, obj_out);
+                       nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   else
     hipLaunchKernelGGL((finalize_kernel<MODE_FISTA>), dim3(1), dim3(256), 0, st, partials,
-                       nblocks, scal, obj_hist, restart_hist, obj_out);
+                       nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   return hipGetLastError();
 }
 

@@ -67,8 +67,26 @@ struct tomo_plan_s {
   size_t off_ghat = 0, off_dfttab = 0, off_post = 0;
   size_t off_g0 = 0, off_wx = 0, off_wy = 0;
   size_t off_scratch = 0, scratch_bytes = 0;
+  size_t off_gp = 0, off_ppartials = 0;
+  bool fused_prior = false;
   bool tables_ready = false, psf_ready = false;
   std::string err;
+
+  // iteration graphs: replayed on an internal stream ordered against `stream` by events
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  struct GraphKey { int level, ik, nz; double* hist; int32_t* rhist; bool obj; };
+  struct GraphEnt { GraphKey key; hipGraphExec_t exec; };
+  std::vector<GraphEnt> graphs;
+  bool use_graphs = true;
+
+  // diagnostics: event pairs around timed kernel classes
+  uint32_t tmask = 0;
+  struct Pending { hipEvent_t a, b; int cls; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double tms[TOMO_T_COUNT] = {};
+  int64_t tcnt[TOMO_T_COUNT] = {};
 
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -141,6 +159,10 @@ void layout(tomo_plan p) {
     l.off_b = take((size_t)p->nz * l.n * l.n * sizeof(float));
   }
   for (int i = 0; i < 3; ++i) p->off_x[i] = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
+  p->off_gp = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
+  size_t maxprior = 1;
+  for (const Level& l : p->lv) maxprior = std::max(maxprior, (size_t)prior_blocks(l.n, p->nz));
+  p->off_ppartials = take(maxprior * 4 * sizeof(double));
   const size_t npts_max = (size_t)na * (fin.nd - 1);
   p->off_ghat = take((size_t)p->nz * npts_max * sizeof(cpx<float>));
   p->off_dfttab = take((size_t)fin.nd * sizeof(cpx<float>));
@@ -167,6 +189,44 @@ void layout(tomo_plan p) {
 
 tomo_status check_ws(tomo_plan p) {
   if (!p->ws) return fail(p, TOMO_ERR_NO_WORKSPACE, "no workspace attached");
+  return TOMO_OK;
+}
+
+hipEvent_t take_event(tomo_plan p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Opens a timed region for kernel class `cls` when it is enabled; returns the pending index.
+int tbegin(tomo_plan p, int cls) {
+  if (!(p->tmask & (1u << cls))) return -1;
+  hipEvent_t a = take_event(p), b = take_event(p);
+  if (!a || !b) return -1;
+  hipEventRecord(a, p->stream);
+  p->pending.push_back({a, b, cls});
+  return (int)p->pending.size() - 1;
+}
+void tend(tomo_plan p, int idx) {
+  if (idx >= 0) hipEventRecord(p->pending[idx].b, p->stream);
+}
+
+tomo_status tresolve(tomo_plan p) {
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  for (auto& e : p->pending) {
+    float ms = 0.f;
+    HIPCHK(p, hipEventElapsedTime(&ms, e.a, e.b));
+    p->tms[e.cls] += ms;
+    p->tcnt[e.cls] += 1;
+    p->pool.push_back(e.a);
+    p->pool.push_back(e.b);
+  }
+  p->pending.clear();
   return TOMO_OK;
 }
 
@@ -202,8 +262,18 @@ GridGeom bp_geom(tomo_plan p, const Level& l) {
 }
 
 // out[nz][N_l][N_l] = R*_l g_l (ramp = 0) or FBP (ramp = 1) of level l.
+tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sino, float* out,
+                                   int ramp);
 tomo_status backproject_level(tomo_plan p, const Level& l, const float* sino, float* out,
                               int ramp) {
+  const int ti = tbegin(p, TOMO_T_BACKPROJECT);
+  const tomo_status s = backproject_level_impl(p, l, sino, out, ramp);
+  tend(p, ti);
+  return s;
+}
+
+tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sino, float* out,
+                                   int ramp) {
   hipStream_t st = p->stream;
   const GridGeom gg = bp_geom(p, l);
   cpx<float>* ghat = p->at<cpx<float>>(p->off_ghat);
@@ -232,18 +302,36 @@ tomo_status backproject_level(tomo_plan p, const Level& l, const float* sino, fl
   return TOMO_OK;
 }
 
-// One application of the Toeplitz passes on level l.
+// One application of the Toeplitz passes on level l (and, outside power mode, of the prior
+// kernel unless the fused-prior epilogue is selected).  *nprior receives the number of prior
+// partial sums the finalize must add (0 when none).
 tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const float* xk,
                             const float* xkm1, const float* b, float* out, bool obj,
-                            int* nblocks) {
+                            int* nblocks, int* nprior = nullptr) {
   hipStream_t st = p->stream;
   cpx<float>* S1 = p->S1();
   cpx<float>* S2 = p->S2(l);
+  const float* gpv = nullptr;
+  if (nprior) *nprior = 0;
+  if (mode != MODE_POWER && !p->fused_prior) {
+    const int tp = tbegin(p, TOMO_T_PRIOR);
+    HIPCHK(p, launch_prior(mode, p->g.neighbours, obj, xk, xkm1, p->scal(), p->at<float>(p->off_gp),
+                           p->at<double>(p->off_ppartials), l.n, nz, p->pp, st));
+    tend(p, tp);
+    gpv = p->at<float>(p->off_gp);
+    if (nprior && obj) *nprior = prior_blocks(l.n, nz);
+  }
+  int ti = tbegin(p, TOMO_T_ROWS_FWD);
   HIPCHK(p, launch_rows_fwd(l.P, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz, st));
+  tend(p, ti);
+  ti = tbegin(p, TOMO_T_COLS_CONV);
   HIPCHK(p, launch_cols_conv(l.P, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
                              p->tw32(l.P), l.n, nz, st));
-  HIPCHK(p, launch_rows_inv(l.P, mode, p->g.neighbours, obj, S2, xk, xkm1, b, out, p->partials(),
-                            p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks, st));
+  tend(p, ti);
+  ti = tbegin(p, TOMO_T_ROWS_INV);
+  HIPCHK(p, launch_rows_inv(l.P, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
+                            p->partials(), p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks, st));
+  tend(p, ti);
   return TOMO_OK;
 }
 
@@ -286,8 +374,8 @@ tomo_status psf_level(tomo_plan p, Level& l) {
     int nb = 0;
     tomo_status s = toeplitz_passes(p, l, MODE_POWER, 1, v, v, nullptr, w, false, &nb);
     if (s != TOMO_OK) return s;
-    HIPCHK(p, launch_finalize(MODE_POWER, p->partials(), nb, p->scal(), nullptr, nullptr,
-                              nullptr, st));
+    HIPCHK(p, launch_finalize(MODE_POWER, p->partials(), nb, nullptr, 0, p->scal(), nullptr,
+                              nullptr, nullptr, st));
     std::swap(v, w);
   }
   double lam = 0.0;
@@ -298,6 +386,67 @@ tomo_status psf_level(tomo_plan p, Level& l) {
     return fail(p, TOMO_ERR_NONFINITE, "power iteration gave lambda = %g", lam);
   l.lambda = lam;
   l.L = 1.01 * lam + 2.0 * p->g.beta * p->rho2_0;
+  return TOMO_OK;
+}
+
+// One FISTA iteration on level l with buffers (ik, ikm1, inext).
+tomo_status fista_iteration(tomo_plan p, const Level& l, int ik, int ikm1, int inext,
+                            const float* b, double* hist, int32_t* rhist, hipStream_t st) {
+  int nb = 0;
+  hipStream_t keep = p->stream;
+  p->stream = st;
+  int npr = 0;
+  tomo_status s = toeplitz_passes(p, l, MODE_FISTA, p->nz, p->xbuf(ik), p->xbuf(ikm1), b,
+                                  p->xbuf(inext), hist != nullptr, &nb, &npr);
+  if (s == TOMO_OK) {
+    const int tf = tbegin(p, TOMO_T_FINALIZE);
+    hipError_t e = launch_finalize(MODE_FISTA, p->partials(), nb, p->at<double>(p->off_ppartials),
+                                   npr, p->scal(), hist, rhist, nullptr, st);
+    tend(p, tf);
+    if (e != hipSuccess) s = fail(p, TOMO_ERR_HIP, "finalize launch: %s", hipGetErrorString(e));
+  }
+  p->stream = keep;
+  return s;
+}
+
+// Graph of three consecutive iterations starting from buffers (ik, ik, (ik+1)%3) after the
+// first iteration of a level, i.e. the steady rotation (ik, ikm1, inext) -> period 3.
+tomo_status get_graph(tomo_plan p, int level, int ik, int ikm1, int inext, const float* b,
+                      double* hist, int32_t* rhist, hipGraphExec_t* out) {
+  for (auto& g : p->graphs)
+    if (g.key.level == level && g.key.ik == ik * 9 + ikm1 * 3 + inext && g.key.nz == p->nz &&
+        g.key.hist == hist && g.key.rhist == rhist) {
+      *out = g.exec;
+      return TOMO_OK;
+    }
+  if (!p->gstream) {
+    HIPCHK(p, hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+    HIPCHK(p, hipEventCreateWithFlags(&p->gev_in, hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->gev_out, hipEventDisableTiming));
+  }
+  const Level& l = p->lv[level];
+  hipGraph_t graph = nullptr;
+  HIPCHK(p, hipStreamBeginCapture(p->gstream, hipStreamCaptureModeRelaxed));
+  tomo_status s = TOMO_OK;
+  int a = ik, b0 = ikm1, c = inext;
+  for (int k = 0; k < 3 && s == TOMO_OK; ++k) {
+    s = fista_iteration(p, l, a, b0, c, b, hist, rhist, p->gstream);
+    b0 = a;
+    a = c;
+    c = 3 - a - b0;
+  }
+  hipError_t e = hipStreamEndCapture(p->gstream, &graph);
+  if (s != TOMO_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(p, TOMO_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(p, TOMO_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  p->graphs.push_back({{level, ik * 9 + ikm1 * 3 + inext, p->nz, hist, rhist, hist != nullptr}, exec});
+  *out = exec;
   return TOMO_OK;
 }
 
@@ -339,7 +488,8 @@ tomo_status validate_geom(const tomo_geometry_t* g) {
   if (!(g->T > 0.0) || !std::isfinite(g->T)) return fail(nullptr, TOMO_ERR_INVALID_ARG, "T must be > 0");
   if (g->neighbours != 8 && g->neighbours != 26)
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "neighbours must be 8 or 26");
-  if (g->flags != 0) return fail(nullptr, TOMO_ERR_INVALID_ARG, "flags must be 0");
+  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_FUSED_PRIOR))
+    return fail(nullptr, TOMO_ERR_INVALID_ARG, "unknown flag bits 0x%x", g->flags);
   if (g->angles)
     for (int i = 0; i < g->n_angles; ++i)
       if (!std::isfinite(g->angles[i]))
@@ -375,6 +525,8 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   p->device = dev;
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->nz = geom->n_slices;
+  p->use_graphs = (geom->flags & TOMO_FLAG_NO_GRAPH) == 0;
+  p->fused_prior = (geom->flags & TOMO_FLAG_FUSED_PRIOR) != 0;
   p->n_levels = geom->n_levels == 0 ? 1 : geom->n_levels;
   if (p->g.kb_width == 0) p->g.kb_width = 6;
   if (p->g.kb_oversamp == 0.0) p->g.kb_oversamp = 2.0;
@@ -446,6 +598,8 @@ tomo_status tomo_plan_set_workspace(tomo_plan p, void* dev, size_t bytes) {
   if (!aligned(dev)) return fail(p, TOMO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (bytes < p->need)
     return fail(p, TOMO_ERR_WORKSPACE_TOO_SMALL, "workspace %zu B < required %zu B", bytes, p->need);
+  for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);  // captured with the old pointers
+  p->graphs.clear();
   p->ws = static_cast<char*>(dev);
   p->ws_bytes = bytes;
   p->tables_ready = false;
@@ -459,8 +613,12 @@ tomo_status tomo_precompute_psf(tomo_plan p) {
   if (s != TOMO_OK) return s;
   HIPCHK(p, hipSetDevice(p->device));
   if ((s = ensure_tables(p)) != TOMO_OK) return s;
-  for (Level& l : p->lv)
-    if ((s = psf_level(p, l)) != TOMO_OK) return s;
+  for (Level& l : p->lv) {
+    const int ti = tbegin(p, TOMO_T_PSF);
+    s = psf_level(p, l);
+    tend(p, ti);
+    if (s != TOMO_OK) return s;
+  }
   p->psf_ready = true;
   return TOMO_OK;
 }
@@ -498,12 +656,12 @@ tomo_status tomo_gradient(tomo_plan p, const float* x, const float* b, float* gr
   if (s != TOMO_OK) return s;
   if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
   HIPCHK(p, hipSetDevice(p->device));
-  int nb = 0;
+  int nb = 0, npr = 0;
   if ((s = toeplitz_passes(p, p->lv.back(), MODE_GRAD, p->nz, x, x, b, grad, obj_dev != nullptr,
-                           &nb)) != TOMO_OK)
+                           &nb, &npr)) != TOMO_OK)
     return s;
-  HIPCHK(p, launch_finalize(MODE_GRAD, p->partials(), nb, p->scal(), nullptr, nullptr, obj_dev,
-                            p->stream));
+  HIPCHK(p, launch_finalize(MODE_GRAD, p->partials(), nb, p->at<double>(p->off_ppartials), npr,
+                            p->scal(), nullptr, nullptr, obj_dev, p->stream));
   return TOMO_OK;
 }
 
@@ -556,17 +714,35 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
     HIPCHK(p, launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st));
     HIPCHK(p, launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / L, st));
     int ik = cur, ikm1 = cur, inext = (cur + 1) % 3;
-    for (int k = 0; k < opts->iters[li]; ++k) {
-      int nb = 0;
-      if ((s = toeplitz_passes(p, l, MODE_FISTA, p->nz, p->xbuf(ik), p->xbuf(ikm1), b,
-                               p->xbuf(inext), opts->objective_dev != nullptr, &nb)) != TOMO_OK)
+    const int n_it = opts->iters[li];
+    // Graph replay of 3-iteration blocks once the buffer rotation is periodic; the events
+    // order the internal stream after everything already enqueued on the plan's stream.
+    const bool graphs = p->use_graphs && p->tmask == 0 && n_it >= 7;
+    int k = 0;
+    while (k < n_it) {
+      if (graphs && k >= 1 && n_it - k >= 3) {
+        hipGraphExec_t exec = nullptr;
+        if ((s = get_graph(p, li, ik, ikm1, inext, b, opts->objective_dev, opts->restart_dev,
+                           &exec)) != TOMO_OK)
+          return s;
+        HIPCHK(p, hipEventRecord(p->gev_in, st));
+        HIPCHK(p, hipStreamWaitEvent(p->gstream, p->gev_in, 0));
+        while (n_it - k >= 3) {
+          HIPCHK(p, hipGraphLaunch(exec, p->gstream));
+          k += 3;
+        }
+        HIPCHK(p, hipEventRecord(p->gev_out, p->gstream));
+        HIPCHK(p, hipStreamWaitEvent(st, p->gev_out, 0));
+        continue;  // three iterations restore the buffer assignment
+      }
+      if ((s = fista_iteration(p, l, ik, ikm1, inext, b, opts->objective_dev, opts->restart_dev,
+                               st)) != TOMO_OK)
         return s;
-      HIPCHK(p, launch_finalize(MODE_FISTA, p->partials(), nb, sc, opts->objective_dev,
-                                opts->restart_dev, nullptr, st));
       // x_{k-1} <- x_k, x_k <- x_{k+1}; the freed buffer receives the next iterate
       ikm1 = ik;
       ik = inext;
       inext = 3 - ik - ikm1;
+      ++k;
     }
     cur = ik;
   }
@@ -621,7 +797,46 @@ tomo_status tomo_lanczos_prolong(const float* in, float* out, int32_t n, int32_t
   return TOMO_OK;
 }
 
+tomo_status tomo_timing_enable(tomo_plan p, uint32_t class_mask) {
+  if (!p) return fail(nullptr, TOMO_ERR_INVALID_ARG, "plan is NULL");
+  if (!p->pending.empty()) {
+    tomo_status s = tresolve(p);
+    if (s != TOMO_OK) return s;
+  }
+  p->tmask = class_mask & ((1u << TOMO_T_COUNT) - 1);
+  for (int i = 0; i < TOMO_T_COUNT; ++i) {
+    p->tms[i] = 0.0;
+    p->tcnt[i] = 0;
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_timing_read(tomo_plan p, double* total_ms, int64_t* counts) {
+  if (!p) return fail(nullptr, TOMO_ERR_INVALID_ARG, "plan is NULL");
+  tomo_status s = tresolve(p);
+  if (s != TOMO_OK) return s;
+  for (int i = 0; i < TOMO_T_COUNT; ++i) {
+    if (total_ms) total_ms[i] = p->tms[i];
+    if (counts) counts[i] = p->tcnt[i];
+  }
+  return TOMO_OK;
+}
+
 tomo_status tomo_plan_destroy(tomo_plan p) {
+  if (!p) return TOMO_OK;
+  if (!p->pending.empty()) hipStreamSynchronize(p->stream);
+  for (auto& e : p->pending) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  for (hipEvent_t e : p->pool) hipEventDestroy(e);
+  for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
+  if (p->gstream) {
+    hipStreamSynchronize(p->gstream);
+    hipStreamDestroy(p->gstream);
+  }
+  if (p->gev_in) hipEventDestroy(p->gev_in);
+  if (p->gev_out) hipEventDestroy(p->gev_out);
   delete p;
   return TOMO_OK;
 }

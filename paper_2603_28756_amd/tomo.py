@@ -23,6 +23,9 @@ STATUS_NAMES = {
     5: "WORKSPACE_TOO_SMALL", 6: "NOT_READY", 7: "HIP", 8: "NONFINITE", 9: "INTERNAL",
 }
 INIT_FBP, INIT_ZERO, INIT_USER = 0, 1, 2
+T_ROWS_FWD, T_COLS_CONV, T_ROWS_INV, T_FINALIZE, T_BACKPROJECT, T_PSF, T_PRIOR, T_COUNT = range(8)
+FLAG_NO_GRAPH = 1
+FLAG_FUSED_PRIOR = 2
 
 
 class TomoError(RuntimeError):
@@ -74,6 +77,9 @@ EXPORTS = {
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "tomo_lanczos_prolong": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
                              ctypes.c_int),
+    "tomo_timing_enable": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
+    "tomo_timing_read": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+                         ctypes.c_int),
     "tomo_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "tomo_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tomo_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
@@ -131,7 +137,8 @@ class Plan:
                  pad: int = 0, n_levels: int = 1, kb_width: int = 6, kb_oversamp: float = 2.0,
                  kb_beta: float = 0.0, beta: float = 0.01, p: float = 1.2, q: float = 2.0,
                  sigma: float = 0.1, T: float = 1.0, neighbours: int = 26, stream=None,
-                 device: Optional[torch.device] = None):
+                 device: Optional[torch.device] = None, graphs: bool = True,
+                 fused_prior: bool = False):
         lib = load_library()
         self._lib = lib
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
@@ -146,7 +153,8 @@ class Plan:
         g.pad, g.n_levels, g.kb_width = pad, n_levels, kb_width
         g.kb_oversamp, g.kb_beta = kb_oversamp, kb_beta
         g.beta, g.p, g.q, g.sigma, g.T = beta, p, q, sigma, T
-        g.neighbours, g.flags = neighbours, 0
+        g.neighbours = neighbours
+        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_FUSED_PRIOR if fused_prior else 0)
         self.geometry = g
         self.n, self.n_slices, self.n_angles, self.n_det = n, n_slices, n_angles, n_det
         self.n_levels = n_levels
@@ -216,6 +224,18 @@ class Plan:
         lam = ctypes.c_double()
         _check(self._lib.tomo_psf_info(self._h, level, _ptr(fk), ctypes.byref(L), ctypes.byref(lam)), self._h)
         return fk, L.value, lam.value
+
+    def timing_enable(self, classes: Sequence[int]):
+        mask = 0
+        for c in classes:
+            mask |= 1 << int(c)
+        _check(self._lib.tomo_timing_enable(self._h, mask), self._h)
+
+    def timing_read(self):
+        ms = (ctypes.c_double * T_COUNT)()
+        cnt = (ctypes.c_int64 * T_COUNT)()
+        _check(self._lib.tomo_timing_read(self._h, ms, cnt), self._h)
+        return list(ms), list(cnt)
 
     def level_dims(self, level: int):
         n, nd, pad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -73,11 +73,13 @@ def test_backproject_and_fbp(n, nz, na, nd, c):
     assert rel_l2(to_np(out), ofbp.fbp(sino, geom)) < 1e-5
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("nb", [8, 26])
-@pytest.mark.parametrize("n,nz,na,nd,c", CASES[:3])
-def test_gradient_and_objective(n, nz, na, nd, c, nb):
+@pytest.mark.parametrize("n,nz,na,nd,c", CASES[:3] + [(48, 37, 20, 68, None)])
+def test_gradient_and_objective(n, nz, na, nd, c, nb, fused):
+    # nz = 37 spans three z-chunks of the prior kernel with a ragged last chunk
     sino, ang, center, phantom = problem(n, nz, na, nd, seed=n + 3, center=c)
-    plan = make_plan(n, nz, ang, nd, center=center, neighbours=nb)
+    plan = make_plan(n, nz, ang, nd, center=center, neighbours=nb, fused_prior=fused)
     plan.precompute_psf()
     geom = oracle_geom(n, ang, nd, center)
     _, _, P = plan.level_dims(0)
@@ -107,12 +109,13 @@ def _oracle_fista(sino, ang, nd, center, n, nb, iters, init, restart=True, L=Non
     return solver.fista(prob, x0, iters, L=L, restart=restart)
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("n,nz,na,nd,nb,iters", [(64, 3, 45, 92, 26, 20), (128, 1, 90, 182, 8, 20),
                                                  (100, 2, 30, 142, 26, 12)])
-def test_reconstruct_parity(n, nz, na, nd, nb, iters):
+def test_reconstruct_parity(n, nz, na, nd, nb, iters, fused):
     from paper_2603_28756_amd import tomo
     sino, ang, center, _ = problem(n, nz, na, nd, seed=n + 4)
-    plan = make_plan(n, nz, ang, nd, neighbours=nb)
+    plan = make_plan(n, nz, ang, nd, neighbours=nb, fused_prior=fused)
     x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
     hist = torch.zeros(iters, dtype=torch.float64, device=dev())
     rs = torch.zeros(iters, dtype=torch.int32, device=dev())
@@ -178,3 +181,27 @@ def test_not_ready_before_psf():
     with pytest.raises(tomo.TomoError) as e:
         plan.gradient(x, x.clone(), torch.empty_like(x))
     assert e.value.status == 6
+
+
+def test_graph_replay_matches_direct_launches():
+    # The iteration loop replays captured 3-iteration graphs; every replay must equal the
+    # directly launched iterations bit for bit, also after unrelated eager work between calls.
+    from paper_2603_28756_amd import tomo
+    n, nz, na, nd, iters = 64, 2, 30, 92, 20
+    sino, ang, center, _ = problem(n, nz, na, nd, seed=21)
+    g = to_dev(sino)
+    outs = []
+    for graphs in (False, True, True):
+        plan = make_plan(n, nz, ang, nd, neighbours=26, graphs=graphs)
+        for rep in range(2):
+            x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
+            hist = torch.zeros(iters, dtype=torch.float64, device=dev())
+            plan.reconstruct(g, x, [iters], init=tomo.INIT_FBP, objective=hist)
+            junk = torch.randn(1 << 20, device=dev())
+            junk.mul_(2.0).sum().item()
+            torch.cuda.synchronize()
+            outs.append((x.clone(), hist.clone()))
+    ref_x, ref_h = outs[0]
+    for x, h in outs[1:]:
+        assert torch.equal(x, ref_x)
+        assert torch.equal(h, ref_h)

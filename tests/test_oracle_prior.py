@@ -103,3 +103,14 @@ def test_invalid_parameters():
         qg.QGGMRF(p=1.5, q=1.2)
     with pytest.raises(ValueError):
         qg.QGGMRF(neighbours=6)
+
+
+@pytest.mark.parametrize("nb", [8, 26])
+def test_gradient_at_matches_full_gradient(nb):
+    pr = qg.QGGMRF(neighbours=nb)
+    rng = np.random.default_rng(nb)
+    x = 0.2 * rng.standard_normal((3, 7, 6))
+    full = qg.gradient(x, pr)
+    vox = [(0, 0, 0), (1, 3, 2), (2, 6, 5), (0, 6, 0), (2, 0, 5)]
+    got = qg.gradient_at(x, pr, vox)
+    assert np.allclose(got, [full[v] for v in vox], rtol=1e-13, atol=1e-13)

@@ -77,3 +77,13 @@ def test_volume_is_slicewise():
     g = radon.forward(vol, geom)
     for z in range(3):
         assert np.allclose(g[z], radon.forward(vol[z], geom), rtol=0, atol=1e-12)
+
+
+def test_polar_to_pixels_matches_full_image():
+    geom = G.Geometry(20, synth.uniform_angles(9), 30, 14.5)
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal((9, 30))
+    gh = radon.sino_spectrum(g, geom)
+    full = radon.polar_to_image(gh, geom)
+    ys, xs = rng.integers(0, 20, 7), rng.integers(0, 20, 7)
+    assert np.allclose(radon.polar_to_pixels(gh, geom, ys, xs), full[ys, xs], rtol=0, atol=1e-12)
