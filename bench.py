@@ -100,8 +100,8 @@ def main() -> int:
     ap.add_argument("--workload", default="volume_64x512")
     ap.add_argument("--iters", type=int, default=0, help="override the workload's iteration count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fused-prior", action="store_true",
-                    help="evaluate the prior inside the epilogue (comparison variant)")
+    ap.add_argument("--split-prior", action="store_true",
+                    help="evaluate the prior in the separate pair-shared kernel (comparison variant)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -137,7 +137,7 @@ def main() -> int:
     plan = tomo.Plan(wl.n, wl.n_slices, wl.n_angles, wl.n_det, angles=list(pr["angles"]),
                      n_levels=wl.levels, kb_width=wl.kb_width, kb_oversamp=wl.kb_oversamp,
                      beta=wl.beta, p=wl.p, q=wl.q, sigma=wl.sigma, T=wl.T,
-                     neighbours=wl.neighbours, device=dev, fused_prior=args.fused_prior)
+                     neighbours=wl.neighbours, device=dev, split_prior=args.split_prior)
     x = torch.empty((wl.n_slices, wl.n, wl.n), dtype=torch.float32, device=dev)
     _, _, P = plan.level_dims(wl.levels - 1)
 
@@ -203,7 +203,7 @@ def main() -> int:
             "n_det": wl.n_det, "iterations": iters, "pad": P, "kb_width": wl.kb_width,
             "kb_oversamp": wl.kb_oversamp, "neighbours": wl.neighbours, "noise": wl.noise,
             "step": "PSF spectrum + step constant precompute, R*g, FBP start, iterations",
-            "prior": "fused epilogue" if args.fused_prior else "pair-shared kernel",
+            "prior": "pair-shared kernel" if args.split_prior else "fused epilogue",
         },
         "roofline": {
             "bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -100,10 +100,10 @@ typedef struct {
  * captured three-iteration HIP graphs (which tomo_reconstruct uses for levels with at
  * least 7 iterations, on an internal stream ordered after the plan's stream). */
 #define TOMO_FLAG_NO_GRAPH 1u
-/* tomo_geometry_t.flags: evaluate the qGGMRF gradient inside the inverse-row epilogue over a
- * neighbour tile (each pair evaluated from both of its voxels) instead of the separate
- * z-marching prior kernel that evaluates each pair once.  Same results to rounding. */
-#define TOMO_FLAG_FUSED_PRIOR 2u
+/* tomo_geometry_t.flags: evaluate the qGGMRF gradient in a separate z-marching kernel that
+ * evaluates each neighbour pair once, instead of inside the inverse-row epilogue over a
+ * neighbour tile (each pair evaluated from both of its voxels).  Same results to rounding. */
+#define TOMO_FLAG_SPLIT_PRIOR 2u
 
 /* Options of tomo_reconstruct(). */
 typedef struct {
@@ -231,6 +231,39 @@ tomo_status tomo_timing_enable(tomo_plan plan, uint32_t class_mask);
  * (host int64[TOMO_T_COUNT]); either pointer may be NULL.  Accumulators keep
  * running.  Errors: INVALID_ARG, HIP. */
 tomo_status tomo_timing_read(tomo_plan plan, double* total_ms, int64_t* counts);
+
+/* ---- batches of independent problems ------------------------------------------------- */
+typedef struct tomo_batch_s* tomo_batch;
+
+typedef struct {
+  int32_t n_nonfinite;    /* problems with a non-finite iteration                          */
+  int32_t n_restarts;     /* restarts summed over all problems                             */
+  int32_t wait_timeouts;  /* 1 if a tile of the persistent kernel gave up waiting (results
+                             invalid; reported as TOMO_ERR_INTERNAL)                        */
+} tomo_batch_stats_t;
+
+/* Group `n` single-level plans (each with its workspace attached, FFT size 256..2048, i.e.
+ * 128 <= N <= 1024 at the default padding) into a batch advanced together: every iteration
+ * of every problem runs in ONE persistent kernel launch that takes tiles of the three
+ * Toeplitz passes of all problems from a phase-ordered queue (Sec. 2.1 and the accelerated
+ * method of Sec. 2 applied to each problem independently; the prior is evaluated in the
+ * inverse-row epilogue).  Problems keep their own geometry, prior, step constant, momentum
+ * and restart state.  The plans must outlive the batch and must not be used concurrently
+ * with it.  Errors: INVALID_ARG, NO_DEVICE, HIP. */
+tomo_status tomo_batch_create(const tomo_plan* plans, int32_t n, void* hip_stream, tomo_batch* out);
+tomo_status tomo_batch_workspace_size(tomo_batch batch, size_t* bytes);
+/* Caller-owned device memory (>= tomo_batch_workspace_size, 256-byte aligned) for the
+ * problem descriptors, the work queue and its counters. */
+tomo_status tomo_batch_set_workspace(tomo_batch batch, void* dev, size_t bytes);
+/* For every problem j: R* g_j and the FBP start from sinos[j] (device, that plan's sinogram
+ * layout), the PSF spectrum if not ready, then `iters` iterations of all problems together
+ * (captured three-iteration graphs replayed on the batch's internal stream), result into
+ * xs[j] (device, [n_slices][N][N]).  sinos and xs are host arrays of n device pointers.
+ * Synchronises the batch stream when stats is non-NULL.
+ * Errors: INVALID_ARG, NO_WORKSPACE, HIP, NONFINITE / INTERNAL (with stats). */
+tomo_status tomo_batch_reconstruct(tomo_batch batch, const float* const* sinos, float* const* xs,
+                                   int32_t iters, int32_t restart, tomo_batch_stats_t* stats);
+tomo_status tomo_batch_destroy(tomo_batch batch);  /* NULL ok */
 
 /* Destroy a plan (NULL is accepted).  Does not free the caller's workspace. */
 tomo_status tomo_plan_destroy(tomo_plan plan);

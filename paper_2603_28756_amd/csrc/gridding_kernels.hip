@@ -89,8 +89,8 @@ __global__ void angle_table_kernel(const double* ang, double* tab, int n) {
 
 // DFT table tab[m] = exp(-2 pi i m / nd) and per-frequency factor
 // post[l] = (1/nd)(1/stride) exp(+2 pi i l c / nd) * (ramp ? pi |l| / (nd n_angles) : 1).
-__global__ void radial_tables_kernel(cpx<float>* tab, cpx<float>* post, int nd, double c,
-                                     int stride, int n_angles, int ramp) {
+__global__ void radial_tables_kernel(cpx<float>* tab, cpx<float>* post, float* rampf, int nd,
+                                     double c, int stride, int n_angles, int ramp) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m < nd) {
     double s, co;
@@ -102,8 +102,10 @@ __global__ void radial_tables_kernel(cpx<float>* tab, cpx<float>* post, int nd, 
     double s, co;
     sincospi(2.0 * (double)l * c / (double)nd, &s, &co);
     double f = 1.0 / ((double)nd * (double)stride);
-    if (ramp) f *= M_PI * fabs((double)l) / ((double)nd * (double)n_angles);
+    const double rf = M_PI * fabs((double)l) / ((double)nd * (double)n_angles);
+    if (ramp) f *= rf;
     post[m] = mk((float)(co * f), (float)(s * f));
+    if (rampf) rampf[m] = (float)rf;
   }
 }
 
@@ -111,8 +113,8 @@ __global__ void radial_tables_kernel(cpx<float>* tab, cpx<float>* post, int nd, 
 constexpr int RD_ROWS = 16, RD_JC = 256;
 __global__ void __launch_bounds__(256)
 radial_dft_kernel(const float* __restrict__ sino, int nd_full, int nd, int stride, int rows,
-                  cpx<float>* __restrict__ ghat, const cpx<float>* __restrict__ tab,
-                  const cpx<float>* __restrict__ post) {
+                  int n_angles, int nz, cpx<float>* __restrict__ ghat,
+                  const cpx<float>* __restrict__ tab, const cpx<float>* __restrict__ post) {
   __shared__ float gt[RD_ROWS][RD_JC];
   const int t = threadIdx.x;
   const int nl = nd - 1;
@@ -150,7 +152,11 @@ radial_dft_kernel(const float* __restrict__ sino, int nd_full, int nd, int strid
 #pragma unroll
     for (int r = 0; r < RD_ROWS; ++r) {
       const int row = row0 + r;
-      if (row < rows) ghat[(idx_t)row * nl + lidx] = cmul(mk(ar[r], ai[r]), f);
+      if (row < rows) {
+        // slice-innermost layout: sample p = (angle, l), all slices of p contiguous
+        const int z = row / n_angles, i = row - z * n_angles;
+        ghat[((idx_t)i * nl + lidx) * nz + z] = cmul(mk(ar[r], ai[r]), f);
+      }
     }
   }
 }
@@ -174,6 +180,222 @@ __global__ void point_table_kernel(const double* __restrict__ atab, int2* __rest
   for (int a = 0; a < W; ++a) {
     wx[(idx_t)p * W + a] = (T)kb_phi((double)(ox + a) - kx, W, beta);
     wy[(idx_t)p * W + a] = (T)kb_phi((double)(oy + a) - ky, W, beta);
+  }
+}
+
+// Every sample p whose footprint covers grid cell (ix, iy), in a fixed order (wrap shift,
+// angle, l): f(p, wx[p][ox] * wy[p][oy]).
+template <typename T, class F>
+TOMO_DEV void visit_cell(int ix, int iy, const double* __restrict__ atab,
+                         const int2* __restrict__ g0, const T* __restrict__ wx,
+                         const T* __restrict__ wy, int M, int nd, int n_angles, int W, F&& f) {
+  const int half = M / 2;
+  const int gx = ix < half ? ix : ix - M;
+  const int gy = iy < half ? iy : iy - M;
+  const int nl = nd - 1, lmax = nd / 2 - 1;
+  const float step = (float)M / (float)nd;
+  const float hw = 0.5f * (float)W + 1.5f;
+  const float reach = (float)half + hw;
+  for (int sx = -1; sx <= 1; ++sx) {
+    const int gxp = gx + sx * M;
+    if (fabsf((float)gxp) > reach) continue;
+    for (int sy = -1; sy <= 1; ++sy) {
+      const int gyp = gy + sy * M;
+      if (fabsf((float)gyp) > reach) continue;
+      for (int i = 0; i < n_angles; ++i) {
+        const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
+        float lo = (float)(-lmax), hi = (float)lmax;
+        if (fabsf(cx) > 1e-6f) {
+          const float a = ((float)gxp - hw) / cx, b = ((float)gxp + hw) / cx;
+          lo = fmaxf(lo, fminf(a, b));
+          hi = fminf(hi, fmaxf(a, b));
+        } else if (fabsf((float)gxp) > hw) {
+          continue;
+        }
+        if (fabsf(cy) > 1e-6f) {
+          const float a = ((float)gyp - hw) / cy, b = ((float)gyp + hw) / cy;
+          lo = fmaxf(lo, fminf(a, b));
+          hi = fminf(hi, fmaxf(a, b));
+        } else if (fabsf((float)gyp) > hw) {
+          continue;
+        }
+        const int l0 = (int)ceilf(lo), l1 = (int)floorf(hi);
+        for (int l = l0; l <= l1; ++l) {
+          const int p = i * nl + (l + lmax);
+          const int2 o = g0[p];
+          const int ox = gxp - o.x, oy = gyp - o.y;
+          if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W)
+            f(p, wx[(idx_t)p * W + ox] * wy[(idx_t)p * W + oy]);
+        }
+      }
+    }
+  }
+}
+
+// Cell-sorted contribution lists (CSR over grid cells): count, then fill at scanned offsets.
+__global__ void __launch_bounds__(256)
+csr_count_kernel(int* __restrict__ cnt, const double* __restrict__ atab,
+                 const int2* __restrict__ g0, const float* __restrict__ wx,
+                 const float* __restrict__ wy, int M, int nd, int n_angles, int W) {
+  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (idx_t)M * M) return;
+  const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
+  int c = 0;
+  visit_cell<float>(ix, iy, atab, g0, wx, wy, M, nd, n_angles, W, [&](int, float) { ++c; });
+  cnt[cell] = c;
+}
+
+__global__ void __launch_bounds__(256)
+csr_fill_kernel(const int* __restrict__ row_ptr, int* __restrict__ idx, float* __restrict__ wts,
+                const double* __restrict__ atab, const int2* __restrict__ g0,
+                const float* __restrict__ wx, const float* __restrict__ wy, int M, int nd,
+                int n_angles, int W) {
+  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (idx_t)M * M) return;
+  const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
+  int k = row_ptr[cell];
+  visit_cell<float>(ix, iy, atab, g0, wx, wy, M, nd, n_angles, W, [&](int p, float w) {
+    idx[k] = p;
+    wts[k] = w;
+    ++k;
+  });
+}
+
+// Exclusive scan of n ints (block-local scans of 4096 elements, then their sums).
+constexpr int SCAN_PER_BLOCK = 4096;
+__global__ void __launch_bounds__(1024)
+scan_blocks_kernel(const int* __restrict__ in, int* __restrict__ out, int* __restrict__ sums,
+                   idx_t n) {
+  __shared__ int sh[1024];
+  const idx_t base = (idx_t)blockIdx.x * SCAN_PER_BLOCK + (idx_t)threadIdx.x * 4;
+  int v[4], tsum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[j] = base + j < n ? in[base + j] : 0;
+    tsum += v[j];
+  }
+  sh[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int add = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - tsum;  // exclusive prefix of this thread
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 1023) sums[blockIdx.x] = sh[1023];
+}
+
+__global__ void __launch_bounds__(1024)
+scan_sums_kernel(int* __restrict__ sums, int nb, int* __restrict__ total_out) {
+  __shared__ int sh[1024];
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  int tsum = 0;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) tsum += sums[b0 + j];
+  sh[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int add = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - tsum;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) {
+      const int v = sums[b0 + j];
+      sums[b0 + j] = run;
+      run += v;
+    }
+  if (threadIdx.x == 1023) *total_out = sh[1023];
+}
+
+__global__ void scan_add_kernel(int* __restrict__ out, const int* __restrict__ sums, idx_t n) {
+  const idx_t i = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] += sums[i / SCAN_PER_BLOCK];
+}
+
+// H[z][cell] = sum over the cell's list of w * c[p][z0 + z] (times the per-l factor lscale[p mod
+// (nd-1)] when given), z < nzb; samples hold all slices contiguously.
+template <int ZB>
+__global__ void __launch_bounds__(256)
+gather_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid,
+              const int* __restrict__ row_ptr, const int* __restrict__ idx,
+              const float* __restrict__ wts, const float* __restrict__ lscale, int M, int nl,
+              int nz, int z0, int nzb) {
+  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (idx_t)M * M) return;
+  float ar[ZB], ai[ZB];
+#pragma unroll
+  for (int z = 0; z < ZB; ++z) ar[z] = ai[z] = 0.f;
+  const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
+  for (int k = k0; k < k1; ++k) {
+    const int p = idx[k];
+    float w = wts[k];
+    if (lscale) w *= lscale[p % nl];
+    const cpx<float>* c = vals + (idx_t)p * nz + z0;
+#pragma unroll
+    for (int z = 0; z < ZB; ++z) {
+      if (z < nzb) {
+        const cpx<float> v = c[z];
+        ar[z] += w * v.re;
+        ai[z] += w * v.im;
+      }
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < ZB; ++z)
+    if (z < nzb) grid[(idx_t)z * M * M + cell] = mk(ar[z], ai[z]);
+}
+
+// Same sums with lanes over slices: a wave walks the lists of 64/ZL cells at a time, each
+// group of ZL lanes reading ZL consecutive slices of a sample (one contiguous line); results
+// are transposed through LDS so that each slice's row of 64 cells is written contiguously.
+template <int ZL>
+__global__ void __launch_bounds__(256)
+gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid,
+                const int* __restrict__ row_ptr, const int* __restrict__ idx,
+                const float* __restrict__ wts, const float* __restrict__ lscale, int M, int nl,
+                int nz, int z0, int nzb) {
+  constexpr int G = 64 / ZL;   // cells per wave step
+  constexpr int CB = 64;       // cells per block
+  __shared__ cpx<float> tile[ZL][CB + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / ZL, zl = lane - g * ZL;
+  const idx_t cells = (idx_t)M * M;
+  const idx_t cell0 = (idx_t)blockIdx.x * CB;
+  const int zi = blockIdx.y * ZL + zl;
+  for (int cs = wave * G + g; cs < CB; cs += 4 * G) {
+    const idx_t cell = cell0 + cs;
+    float ar = 0.f, ai = 0.f;
+    if (cell < cells) {
+      const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
+      for (int k = k0; k < k1; ++k) {
+        const int pp = idx[k];
+        float w = wts[k];
+        if (lscale) w *= lscale[pp % nl];
+        if (zi < nzb) {
+          const cpx<float> v = vals[(idx_t)pp * nz + z0 + zi];
+          ar += w * v.re;
+          ai += w * v.im;
+        }
+      }
+    }
+    tile[zl][cs] = mk(ar, ai);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ZL * CB; e += 256) {
+    const int z = e / CB, c = e - z * CB;
+    const idx_t cell = cell0 + c;
+    const int zo = blockIdx.y * ZL + z;
+    if (cell < cells && zo < nzb) grid[(idx_t)zo * cells + cell] = tile[z][c];
   }
 }
 
@@ -338,18 +560,22 @@ hipError_t fft2d_p(cpx<T>* data, int batch, int dir, const cpx<T>* tw, hipStream
 
 // ---------------------------------------------------------------------- crop / deapodise
 // out[z][my][mx] = Re H[z][(my - N/2) mod M][(mx - N/2) mod M] / (phi^(x/M) phi^(y/M))
+// inv[m] = 1 / phi^((m - N/2) / M), m = 0..N-1 (float64 evaluation, float32 result).
+__global__ void deapod_table_kernel(float* __restrict__ inv, int N, int M, int W, double beta) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < N) inv[m] = (float)(1.0 / kb_phihat((double)(m - N / 2) / M, W, beta));
+}
+
 __global__ void crop_deapod_kernel(const cpx<float>* __restrict__ grid, float* __restrict__ out,
-                                   int N, int M, int W, double beta, int nzb) {
+                                   const float* __restrict__ inv, int N, int M, int nzb) {
   const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
   const idx_t tot = (idx_t)nzb * N * N;
   if (i >= tot) return;
   const int z = (int)(i / ((idx_t)N * N));
   const int rem = (int)(i - (idx_t)z * N * N);
   const int my = rem / N, mx = rem - my * N;
-  const int x = mx - N / 2, y = my - N / 2;
-  const int gx = (x + M) % M, gy = (y + M) % M;
-  const double d = kb_phihat((double)x / M, W, beta) * kb_phihat((double)y / M, W, beta);
-  out[i] = (float)((double)grid[(idx_t)z * M * M + (idx_t)gy * M + gx].re / d);
+  const int gx = (mx - N / 2 + M) % M, gy = (my - N / 2 + M) % M;
+  out[i] = grid[(idx_t)z * M * M + (idx_t)gy * M + gx].re * inv[my] * inv[mx];
 }
 
 // Embedded PSF: emb[v][u] = K(dy, dx) for |dx|, |dy| <= N-1 (dy = v or v - P, dx likewise),
@@ -508,10 +734,10 @@ hipError_t launch_angle_table(const double* angles_dev, double* tab, int n, hipS
   hipLaunchKernelGGL(angle_table_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, angles_dev, tab, n);
   return hipGetLastError();
 }
-hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, const GridGeom& gg,
-                                int ramp, hipStream_t st) {
+hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, float* rampf,
+                                const GridGeom& gg, int ramp, hipStream_t st) {
   hipLaunchKernelGGL(radial_tables_kernel, dim3(nblk(gg.n_det, 256)), dim3(256), 0, st, dft_tab,
-                     post, gg.n_det, gg.c, gg.stride, gg.n_angles, ramp);
+                     post, rampf, gg.n_det, gg.c, gg.stride, gg.n_angles, ramp);
   return hipGetLastError();
 }
 hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat,
@@ -520,7 +746,61 @@ hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat
   const int rows = nz * gg.n_angles;
   const dim3 grid(nblk(gg.n_det - 1, 256), nblk(rows, RD_ROWS));
   hipLaunchKernelGGL(radial_dft_kernel, grid, dim3(256), 0, st, sino, n_det_full, gg.n_det,
-                     gg.stride, rows, ghat, dft_tab, post);
+                     gg.stride, rows, gg.n_angles, nz, ghat, dft_tab, post);
+  return hipGetLastError();
+}
+hipError_t launch_csr_build(const double* atab, const int2* g0, const float* wx, const float* wy,
+                            const GridGeom& gg, int* cnt, int* row_ptr, int* idx, float* wts,
+                            int* scan_sums, hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  const unsigned nb = nblk(cells, 256);
+  hipLaunchKernelGGL(csr_count_kernel, dim3(nb), dim3(256), 0, st, cnt, atab, g0, wx, wy, gg.M,
+                     gg.n_det, gg.n_angles, gg.W);
+  const int nsb = (int)((cells + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nsb), dim3(1024), 0, st, cnt, row_ptr, scan_sums,
+                     cells);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, scan_sums, nsb,
+                     row_ptr + cells);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, st, row_ptr, scan_sums, cells);
+  hipLaunchKernelGGL(csr_fill_kernel, dim3(nb), dim3(256), 0, st, row_ptr, idx, wts, atab, g0,
+                     wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W);
+  return hipGetLastError();
+}
+hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
+                         const int* idx, const float* wts, const float* lscale,
+                         const GridGeom& gg, int nz, int z0, int nzb, hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  const int nl = gg.n_det - 1;
+  if (nzb >= 3) {
+    const int zl = nzb > 32 ? 64 : nzb > 16 ? 32 : nzb > 4 ? 16 : 4;
+    const dim3 blocks(nblk(cells, 64), (nzb + zl - 1) / zl);
+#define TOMO_GZ(ZLV)                                                                          \
+  hipLaunchKernelGGL((gather_z_kernel<ZLV>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx, \
+                     wts, lscale, gg.M, nl, nz, z0, nzb)
+    if (zl == 64) TOMO_GZ(64);
+    else if (zl == 32) TOMO_GZ(32);
+    else if (zl == 16) TOMO_GZ(16);
+    else TOMO_GZ(4);
+#undef TOMO_GZ
+    return hipGetLastError();
+  }
+  const dim3 blocks(nblk(cells, 256));
+  if (nzb <= 1)
+    hipLaunchKernelGGL((gather_kernel<1>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx, wts,
+                       lscale, gg.M, nl, nz, z0, nzb);
+  else if (nzb <= 4)
+    hipLaunchKernelGGL((gather_kernel<4>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx, wts,
+                       lscale, gg.M, nl, nz, z0, nzb);
+  else if (nzb <= 16)
+    hipLaunchKernelGGL((gather_kernel<16>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx,
+                       wts, lscale, gg.M, nl, nz, z0, nzb);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_deapod_table(float* inv, const GridGeom& gg, hipStream_t st) {
+  hipLaunchKernelGGL(deapod_table_kernel, dim3(nblk(gg.n, 256)), dim3(256), 0, st, inv, gg.n,
+                     gg.M, gg.W, gg.beta);
   return hipGetLastError();
 }
 template <typename T>
@@ -535,27 +815,6 @@ template hipError_t launch_point_table<float>(const double*, int2*, float*, floa
                                               const GridGeom&, hipStream_t);
 template hipError_t launch_point_table<double>(const double*, int2*, double*, double*,
                                                const GridGeom&, hipStream_t);
-
-hipError_t launch_spread_f32(const cpx<float>* ghat, cpx<float>* grid, const double* atab,
-                             const int2* g0, const float* wx, const float* wy,
-                             const GridGeom& gg, int z0, int nzb, int /*ghat_slices*/,
-                             hipStream_t st) {
-  const idx_t cells = (idx_t)gg.M * gg.M;
-  const idx_t spts = (idx_t)gg.n_angles * (gg.n_det - 1);
-  const dim3 blocks(nblk(cells, 256));
-  if (nzb <= 1)
-    hipLaunchKernelGGL((spread_kernel<float, 1, false>), blocks, dim3(256), 0, st, ghat, grid,
-                       atab, g0, wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W, z0, nzb, spts, 0.f);
-  else if (nzb <= 4)
-    hipLaunchKernelGGL((spread_kernel<float, 4, false>), blocks, dim3(256), 0, st, ghat, grid,
-                       atab, g0, wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W, z0, nzb, spts, 0.f);
-  else if (nzb <= 8)
-    hipLaunchKernelGGL((spread_kernel<float, 8, false>), blocks, dim3(256), 0, st, ghat, grid,
-                       atab, g0, wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W, z0, nzb, spts, 0.f);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
 
 hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* atab, const int2* g0,
                                  const double* wx, const double* wy, const GridGeom& gg,
@@ -596,11 +855,11 @@ hipError_t launch_fft2d_f64(cpx<double>* data, int M, int batch, int dir,
 #undef CALL
 }
 
-hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const GridGeom& gg, int nzb,
-                              hipStream_t st) {
+hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const float* inv,
+                              const GridGeom& gg, int nzb, hipStream_t st) {
   const idx_t tot = (idx_t)nzb * gg.n * gg.n;
-  hipLaunchKernelGGL(crop_deapod_kernel, dim3(nblk(tot, 256)), dim3(256), 0, st, grid, out, gg.n,
-                     gg.M, gg.W, gg.beta, nzb);
+  hipLaunchKernelGGL(crop_deapod_kernel, dim3(nblk(tot, 256)), dim3(256), 0, st, grid, out, inv,
+                     gg.n, gg.M, nzb);
   return hipGetLastError();
 }
 hipError_t launch_psf_embed(const cpx<double>* grid, cpx<double>* emb, const GridGeom& gg, int N,

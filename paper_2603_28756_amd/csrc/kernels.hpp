@@ -60,6 +60,36 @@ hipError_t launch_finalize(int mode, const double* partials, int nblocks,
                            double* obj_hist, int32_t* restart_hist, double* obj_out,
                            hipStream_t st);
 
+// ---- batched iteration over independent problems ------------------------------------------
+// One problem of a batch; every pointer lives in that problem's own plan workspace.
+struct BatchProb {
+  int N, P, nz, neighbours;
+  int nR, nC, nRp;          // tiles of pass R, pass C, pass R'
+  int pad0;
+  float* x[3];              // rotating iterates
+  const float* b;
+  const float* fk;
+  const float* fkn;
+  cpx<float>* S1;
+  cpx<float>* S2;
+  double* partials;         // [nRp][4]
+  double* scal;             // scalar block (SC_*)
+  const cpx<float>* tw;     // twiddles for P
+  double* hist;             // nullable objective history (indexed by SC_ITER)
+  int32_t* rhist;           // nullable restart flags
+  PriorParams pp;
+};
+constexpr int kBatchThreads = 256;
+// Tile counts of problem (N, P, nz) in the batched kernel.
+void batch_tile_counts(int N, int P, int nz, int* nR, int* nC, int* nRp);
+bool batch_supports(int P);
+// items: int2 {prob | phase << 24, tile}, ordered by phase; ctl[0] = queue head, ctl[1] =
+// finished blocks, ctl[2] = error flag; cnt[3][nprob] = finished tiles per phase.
+hipError_t launch_batch_iteration(const BatchProb* probs, const int2* items, int n_items,
+                                  int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext,
+                                  int grid, hipStream_t st);
+hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st);
+
 // ---- tables and utilities ---------------------------------------------------------------
 hipError_t launch_twiddles_f32(cpx<float>* tw, int P, hipStream_t st);
 hipError_t launch_twiddles_f64(cpx<double>* tw, int P, hipStream_t st);
@@ -82,8 +112,8 @@ struct GridGeom {
   int stride;     // detector subsampling stride of the level (1 = finest)
 };
 
-hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, const GridGeom& gg,
-                                int ramp, hipStream_t st);
+hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, float* rampf,
+                                const GridGeom& gg, int ramp, hipStream_t st);
 hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat,
                              const cpx<float>* dft_tab, const cpx<float>* post,
                              const GridGeom& gg, int nz, hipStream_t st);
@@ -91,10 +121,16 @@ template <typename T>
 hipError_t launch_point_table(const double* angle_tab /* [n_angles][2] cos,sin */, int2* g0, T* wx,
                               T* wy, const GridGeom& gg, hipStream_t st);
 hipError_t launch_angle_table(const double* angles_dev, double* tab, int n_angles, hipStream_t st);
-hipError_t launch_spread_f32(const cpx<float>* ghat, cpx<float>* grid, const double* angle_tab,
-                             const int2* g0, const float* wx, const float* wy,
-                             const GridGeom& gg, int z0, int nzb, int ghat_slices,
-                             hipStream_t st);
+// Cell-sorted contribution lists of a geometry: cnt [M*M] scratch, row_ptr [M*M+1],
+// idx/wts [n_samples * W^2], scan_sums [M*M/4096 + 1].
+hipError_t launch_csr_build(const double* atab, const int2* g0, const float* wx, const float* wy,
+                            const GridGeom& gg, int* cnt, int* row_ptr, int* idx, float* wts,
+                            int* scan_sums, hipStream_t st);
+// grid[z][cell] for slices z0 .. z0+nzb-1 (nzb <= 64) from samples [p][nz] complex64.
+hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
+                         const int* idx, const float* wts, const float* lscale,
+                         const GridGeom& gg, int nz, int z0, int nzb, hipStream_t st);
+hipError_t launch_deapod_table(float* inv, const GridGeom& gg, hipStream_t st);
 hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* angle_tab, const int2* g0,
                                  const double* wx, const double* wy, const GridGeom& gg,
                                  hipStream_t st);
@@ -102,8 +138,8 @@ hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir,
                             const cpx<float>* tw, hipStream_t st);
 hipError_t launch_fft2d_f64(cpx<double>* data, int M, int batch, int dir,
                             const cpx<double>* tw, hipStream_t st);
-hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const GridGeom& gg, int nzb,
-                              hipStream_t st);
+hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const float* inv,
+                              const GridGeom& gg, int nzb, hipStream_t st);
 hipError_t launch_psf_embed(const cpx<double>* grid, cpx<double>* emb, const GridGeom& gg,
                             int N, int P, hipStream_t st);
 hipError_t launch_fk_store(const cpx<double>* spec, float* fk, float* fkn, int P,

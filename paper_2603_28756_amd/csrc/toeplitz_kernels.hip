@@ -63,29 +63,30 @@ TOMO_DEV void block_sum4(double a0, double a1, double a2, double a3, double* out
 }
 
 // ---------------------------------------------------------------------------------- pass R
+template <int P, int PAIRS>
+constexpr int rows_fwd_lds() { return PAIRS * fft::row_region<P>() * 8; }
+
+// Block `blk` transforms row pairs blk*PAIRS .. blk*PAIRS+PAIRS-1 (counted over all slices).
+// y = x_k + mu (x_k - x_{k-1}), or s * x_k in power mode.
 template <int P, int PAIRS, int MODE>
-__global__ void __launch_bounds__(PAIRS * (P / kE))
-rows_fwd_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
-                const double* __restrict__ scal, cpx<float>* __restrict__ S1,
-                const cpx<float>* __restrict__ tw, int N, int n_pairs) {
+TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restrict__ xk,
+                            const float* __restrict__ xkm1, float mu, float s,
+                            cpx<float>* __restrict__ S1, const cpx<float>* __restrict__ tw, int N,
+                            int n_pairs) {
   using PL = fft::Plan<P, kE>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int REG = fft::row_region<P>();
   constexpr int H = P / 2;
-  __shared__ cpx<float> lds[PAIRS * REG];
+  cpx<float>* lds = reinterpret_cast<cpx<float>*>(smem);
 
   const int t = threadIdx.x, pr = t / TPF, q = t - pr * TPF;
-  const int gp = blockIdx.x * PAIRS + pr;
+  const int gp = blk * PAIRS + pr;
   const bool active = gp < n_pairs;
   const int halfN = N >> 1;
   const int z = active ? gp / halfN : 0;
   const int r1 = active ? 2 * (gp - z * halfN) : 0;
   const idx_t row1 = ((idx_t)z * N + r1) * N;
   const idx_t row2 = row1 + N;
-
-  float mu = 0.f, s = 1.f;
-  if constexpr (MODE == MODE_POWER) s = (float)scal[SC_PSCALE];
-  else mu = (float)scal[SC_MU];
 
   cpx<float> v[E];
 #pragma unroll
@@ -133,21 +134,36 @@ rows_fwd_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
   }
 }
 
+template <int P, int PAIRS, int MODE>
+__global__ void __launch_bounds__(PAIRS * (P / kE))
+rows_fwd_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
+                const double* __restrict__ scal, cpx<float>* __restrict__ S1,
+                const cpx<float>* __restrict__ tw, int N, int n_pairs) {
+  __shared__ __align__(16) unsigned char smem[rows_fwd_lds<P, PAIRS>()];
+  float mu = 0.f, s = 1.f;
+  if constexpr (MODE == MODE_POWER) s = (float)scal[SC_PSCALE];
+  else mu = (float)scal[SC_MU];
+  rows_fwd_body<P, PAIRS, MODE>(smem, blockIdx.x, xk, xkm1, mu, s, S1, tw, N, n_pairs);
+}
+
 // ---------------------------------------------------------------------------------- pass C
 template <int P, int TC>
-__global__ void __launch_bounds__(TC * (P / kE))
-cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
-                 const float* __restrict__ fk, const float* __restrict__ fkn,
-                 const cpx<float>* __restrict__ tw, int N) {
+constexpr int cols_conv_lds() { return P * TC * 8; }
+
+// Column tile `bx` (columns bx*TC .. bx*TC+TC-1) of slice z.
+template <int P, int TC>
+TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
+                             const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
+                             const float* __restrict__ fk, const float* __restrict__ fkn,
+                             const cpx<float>* __restrict__ tw, int N) {
   using PL = fft::Plan<P, kE>;
   using IPL = fft::RevPlan<PL>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int H = P / 2;
-  __shared__ cpx<float> lds[P * TC];
+  cpx<float>* lds = reinterpret_cast<cpx<float>*>(smem);
 
   const int t = threadIdx.x, c = t % TC, q = t / TC;
-  const int u = blockIdx.x * TC + c;
-  const int z = blockIdx.y;
+  const int u = bx * TC + c;
   const cpx<float>* in = S1 + (idx_t)z * N * H + u;
 
   cpx<float> v[E];
@@ -162,7 +178,7 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
   fft::LdsCols<float, TC> L{lds, c};
   fft::run_stages<PL, 0, -1>(v, q, tw, L);
 
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     // Column 0 carries the DC column (real part) and the Nyquist column (imag part); both
     // are real, so their spectra C0, CN are Hermitian and C0 FK0 + i CN FKN is recovered
     // from Z[v] and conj Z[-v].
@@ -207,6 +223,15 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
       const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
       if (n < N) out[(idx_t)n * H] = v[m * R0 + r];
     }
+}
+
+template <int P, int TC>
+__global__ void __launch_bounds__(TC * (P / kE))
+cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
+                 const float* __restrict__ fk, const float* __restrict__ fkn,
+                 const cpx<float>* __restrict__ tw, int N) {
+  __shared__ __align__(16) unsigned char smem[cols_conv_lds<P, TC>()];
+  cols_conv_body<P, TC>(smem, blockIdx.x, blockIdx.y, S1, S2, fk, fkn, tw, N);
 }
 
 // ---------------------------------------------------------------------------- prior (3D)
@@ -313,6 +338,12 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
 
   for (int z = z0; z < z1; ++z) {
     const bool has_next = NB == 26 && z + 1 < nz;
+    if (NB != 26 && z > z0) {
+      // in-plane prior: no plane carries over, reload the current one (the previous step's
+      // readers finished at its last barrier)
+      load_plane(z, ybuf[bc]);
+      __syncthreads();
+    }
     if (has_next) load_plane(z + 1, ybuf[bn]);
     // in-plane pairs: offsets (0,1), (1,-1), (1,0), (1,1) in (dy, dx)
     for (int e = t; e < 4 * HA; e += NT) {
@@ -352,10 +383,12 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
       acc[j] = accn[j];
       accn[j] = 0.f;
     }
-    const int tmp = bp;
-    bp = bc;
-    bc = bn;
-    bn = tmp;
+    if (NB == 26) {
+      const int tmp = bp;
+      bp = bc;
+      bc = bn;
+      bn = tmp;
+    }
   }
   if (partials) {
     const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -364,33 +397,43 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
 }
 
 // --------------------------------------------------------------------------------- pass R'
+template <int P, int PAIRS, int NB>
+struct RowsInvLds {
+  static constexpr int TPF = P / kE, NT = PAIRS * TPF, RB = 2 * PAIRS, H = P / 2;
+  static constexpr int CW = 64;
+  static constexpr int ZD = (NB == 26) ? 3 : 1;
+  static constexpr int YT = NB == 0 ? 1 : ZD * (RB + 2) * (CW + 2);
+  static constexpr int FFT_BYTES = PAIRS * fft::row_region<P>() * 8;
+  static constexpr int YT_BYTES = YT * 4;
+  static constexpr int A_BYTES = FFT_BYTES > YT_BYTES ? FFT_BYTES : YT_BYTES;
+  static constexpr int TY_BYTES = RB * H * 4;
+  static constexpr int RED_BYTES = ((NT + 63) / 64) * 4 * 8;
+  static constexpr int BYTES = A_BYTES + TY_BYTES + RED_BYTES;
+};
+
+// Block `blk` handles rows r0 .. r0+2*PAIRS-1 of one slice (blk counted over all slices);
+// its four float64 partial sums go to part_out[0..3].
 template <int P, int PAIRS, int MODE, int NB, bool OBJ>
-__global__ void __launch_bounds__(PAIRS * (P / kE))
-rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
-                const float* __restrict__ xkm1, const float* __restrict__ bvec,
-                const float* __restrict__ gpv, float* __restrict__ out,
-                double* __restrict__ partials, const double* __restrict__ scal,
-                const cpx<float>* __restrict__ tw, int N, int nz, PriorParams pp) {
+TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __restrict__ S2,
+                            const float* __restrict__ xk, const float* __restrict__ xkm1,
+                            const float* __restrict__ bvec, const float* __restrict__ gpv,
+                            float* __restrict__ out, double* __restrict__ part_out, float mu,
+                            float invL, const cpx<float>* __restrict__ tw, int N, int nz,
+                            const PriorParams& pp) {
   using PL = fft::Plan<P, kE>;
+  using LY = RowsInvLds<P, PAIRS, NB>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
-  constexpr int NT = PAIRS * TPF, RB = 2 * PAIRS, H = P / 2;
+  constexpr int NT = LY::NT, RB = LY::RB, H = LY::H;
   constexpr int REG = fft::row_region<P>();
-  constexpr int CW = 64;
-  constexpr int ZD = (NB == 26) ? 3 : 1;
-  constexpr int YT = NB == 0 ? 1 : ZD * (RB + 2) * (CW + 2);
-  constexpr int FFT_BYTES = PAIRS * REG * 8;
-  constexpr int YT_BYTES = YT * 4;
-  constexpr int A_BYTES = FFT_BYTES > YT_BYTES ? FFT_BYTES : YT_BYTES;
-  constexpr int TY_BYTES = RB * H * 4;
-  __shared__ __align__(16) unsigned char smem[A_BYTES + TY_BYTES];
-  __shared__ double sred[((NT + 63) / 64) * 4];
+  constexpr int CW = LY::CW, ZD = LY::ZD, YT = LY::YT;
   cpx<float>* fl = reinterpret_cast<cpx<float>*>(smem);
   float* ytile = reinterpret_cast<float*>(smem);
-  float* tyt = reinterpret_cast<float*>(smem + A_BYTES);
+  float* tyt = reinterpret_cast<float*>(smem + LY::A_BYTES);
+  double* sred = reinterpret_cast<double*>(smem + LY::A_BYTES + LY::TY_BYTES);
 
   const int bps = (N + RB - 1) / RB;
-  const int z = blockIdx.x / bps;
-  const int r0 = (blockIdx.x - z * bps) * RB;
+  const int z = blk / bps;
+  const int r0 = (blk - z * bps) * RB;
   const int t = threadIdx.x, pr = t / TPF, q = t - pr * TPF;
   const int r1 = r0 + 2 * pr;
   const bool active = r1 < N;
@@ -441,8 +484,6 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   if constexpr (MODE != MODE_POWER && NB == 0) {
     // prior gradient precomputed by prior_kernel: point-wise epilogue, no neighbour tile
-    const float mu = (MODE == MODE_FISTA) ? (float)scal[SC_MU] : 0.f;
-    const float invL = (MODE == MODE_FISTA) ? (float)scal[SC_INVL] : 0.f;
     for (int e = t; e < RB * N; e += NT) {
       const int ry = e / N, col = e - ry * N, row = r0 + ry;
       if (row < N) {
@@ -473,8 +514,6 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
       }
     }
   } else {
-    const float mu = (MODE == MODE_FISTA) ? (float)scal[SC_MU] : 0.f;
-    const float invL = (MODE == MODE_FISTA) ? (float)scal[SC_INVL] : 0.f;
     for (int c0 = 0; c0 < N; c0 += CW) {
       for (int e = t; e < YT; e += NT) {
         const int dzi = e / ((RB + 2) * (CW + 2));
@@ -544,7 +583,22 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
       __syncthreads();
     }
   }
-  block_sum4<NT>(acc0, acc1, acc2, acc3, partials + (idx_t)blockIdx.x * 4, sred);
+  block_sum4<NT>(acc0, acc1, acc2, acc3, part_out, sred);
+}
+
+template <int P, int PAIRS, int MODE, int NB, bool OBJ>
+__global__ void __launch_bounds__(PAIRS * (P / kE))
+rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
+                const float* __restrict__ xkm1, const float* __restrict__ bvec,
+                const float* __restrict__ gpv, float* __restrict__ out,
+                double* __restrict__ partials, const double* __restrict__ scal,
+                const cpx<float>* __restrict__ tw, int N, int nz, PriorParams pp) {
+  __shared__ __align__(16) unsigned char smem[RowsInvLds<P, PAIRS, NB>::BYTES];
+  const float mu = (MODE == MODE_FISTA) ? (float)scal[SC_MU] : 0.f;
+  const float invL = (MODE == MODE_FISTA) ? (float)scal[SC_INVL] : 0.f;
+  rows_inv_body<P, PAIRS, MODE, NB, OBJ>(smem, blockIdx.x, S2, xk, xkm1, bvec, gpv, out,
+                                         partials + (idx_t)blockIdx.x * 4, mu, invL, tw, N, nz,
+                                         pp);
 }
 
 // -------------------------------------------------------------------------------- finalize
@@ -606,6 +660,191 @@ finalize_kernel(const double* __restrict__ partials, int nblocks,
     scal[SC_MU] = mu;
     scal[SC_ITER] = (double)(k + 1);
   }
+}
+
+// ------------------------------------------------------------------- batched iteration
+// One persistent launch advances every problem of a batch by one iteration.  Blocks take
+// tiles from a queue ordered by phase (pass R tiles of all problems, then pass C, then pass
+// R'); a pass-C tile of problem j first waits until all pass-R tiles of j are finished, a
+// pass-R' tile until all pass-C tiles of j are.  Every tile waited on sits earlier in the queue
+// and was taken by a block that is already running and never waits on a later tile, so the
+// waits end; each is also bounded and raises ctl[2] instead of spinning forever.  The block
+// finishing the last pass-R' tile of a problem runs that problem's float64 finalize.  The last
+// block to leave resets the queue for the next launch.
+constexpr int BT = kBatchThreads;
+
+template <int P>
+constexpr int bt_tpf() { return P / kE; }
+template <int P>
+constexpr int bt_pairs() { return BT / bt_tpf<P>() < 1 ? 1 : BT / bt_tpf<P>(); }
+template <int P>
+constexpr int bt_tc() { return BT / bt_tpf<P>() < 1 ? 1 : BT / bt_tpf<P>(); }
+
+template <int P>
+constexpr int batch_lds_p() {
+  constexpr int a = rows_fwd_lds<P, bt_pairs<P>()>();
+  constexpr int b = cols_conv_lds<P, bt_tc<P>()>();
+  constexpr int c = RowsInvLds<P, bt_pairs<P>(), 26>::BYTES;
+  constexpr int d = RowsInvLds<P, bt_pairs<P>(), 8>::BYTES;
+  constexpr int m1 = a > b ? a : b;
+  constexpr int m2 = c > d ? c : d;
+  return m1 > m2 ? m1 : m2;
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kBatchLds = cmax(cmax(batch_lds_p<256>(), batch_lds_p<512>()),
+                               cmax(batch_lds_p<1024>(), batch_lds_p<2048>()));
+
+TOMO_DEV void bounded_wait(const int* ctr, int target, int* err) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1 << 22)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Each (P, phase) body is its own non-inlined function so that its registers are allocated
+// on their own rather than across every variant the persistent kernel can dispatch to.
+template <int P>
+__device__ __attribute__((noinline)) void batch_phase_r(unsigned char* smem, int tile,
+                                                        const BatchProb* pb, int ik, int ikm1) {
+  constexpr int PAIRS = bt_pairs<P>();
+  const float mu = (float)pb->scal[SC_MU];
+  rows_fwd_body<P, PAIRS, MODE_FISTA>(smem, tile, pb->x[ik], pb->x[ikm1], mu, 1.f, pb->S1, pb->tw,
+                                      pb->N, pb->nz * (pb->N / 2));
+}
+
+template <int P>
+__device__ __attribute__((noinline)) void batch_phase_c(unsigned char* smem, int tile,
+                                                        const BatchProb* pb) {
+  constexpr int TC = bt_tc<P>();
+  constexpr int ncol = (P / 2) / TC;
+  const int z = tile / ncol;
+  cols_conv_body<P, TC>(smem, tile - z * ncol, z, pb->S1, pb->S2, pb->fk, pb->fkn, pb->tw, pb->N);
+}
+
+template <int P, int NB>
+__device__ __attribute__((noinline)) void batch_phase_rp(unsigned char* smem, int tile,
+                                                         const BatchProb* pb, int ik, int ikm1,
+                                                         int inext) {
+  constexpr int PAIRS = bt_pairs<P>();
+  const float mu = (float)pb->scal[SC_MU];
+  const float invL = (float)pb->scal[SC_INVL];
+  const PriorParams pp = pb->pp;
+  rows_inv_body<P, PAIRS, MODE_FISTA, NB, false>(smem, tile, pb->S2, pb->x[ik], pb->x[ikm1],
+                                                 pb->b, nullptr, pb->x[inext],
+                                                 pb->partials + (idx_t)tile * 4, mu, invL,
+                                                 pb->tw, pb->N, pb->nz, pp);
+}
+
+template <int P>
+TOMO_DEV void batch_tile(unsigned char* smem, int phase, int tile, const BatchProb* pb, int ik,
+                         int ikm1, int inext) {
+  if (phase == 0) batch_phase_r<P>(smem, tile, pb, ik, ikm1);
+  else if (phase == 1) batch_phase_c<P>(smem, tile, pb);
+  else if (pb->neighbours == 26) batch_phase_rp<P, 26>(smem, tile, pb, ik, ikm1, inext);
+  else batch_phase_rp<P, 8>(smem, tile, pb, ik, ikm1, inext);
+}
+
+// Float64 reduction of one problem's partial sums and its momentum / restart update (the same
+// arithmetic as finalize_kernel in FISTA mode), run by one whole block.
+TOMO_DEV void batch_finalize(const BatchProb& pb, double* sh /* [4][BT] */) {
+  const int t = threadIdx.x;
+  double a[4] = {0, 0, 0, 0};
+  for (int b = t; b < pb.nRp; b += BT)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] += pb.partials[(idx_t)b * 4 + i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) sh[i * BT + t] = a[i];
+  __syncthreads();
+  for (int s = BT / 2; s > 0; s >>= 1) {
+    if (t < s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sh[i * BT + t] += sh[i * BT + t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double* scal = pb.scal;
+    const double s0 = sh[0], s1 = sh[BT], s3 = sh[3 * BT];
+    const int k = (int)scal[SC_ITER];
+    const double obj = 0.5 * s0 - s1 + 0.5 * scal[SC_GG];
+    if (pb.hist) pb.hist[k] = obj;
+    scal[SC_LASTOBJ] = obj;
+    const double tk = scal[SC_T];
+    double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+    const bool restart = scal[SC_RESTART_ON] != 0.0 && s3 > 0.0;
+    double mu;
+    if (restart) {
+      tn = 1.0;
+      mu = 0.0;
+      scal[SC_NRESTART] += 1.0;
+    } else {
+      mu = (tk - 1.0) / tn;
+    }
+    if (pb.rhist) pb.rhist[k] = restart ? 1 : 0;
+    if ((!isfinite(s3) || !isfinite(s0) || !isfinite(s1)) && scal[SC_NONFINITE] < 0.0)
+      scal[SC_NONFINITE] = (double)k;
+    scal[SC_T] = tn;
+    scal[SC_MU] = mu;
+    scal[SC_ITER] = (double)(k + 1);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(BT)
+batch_iter_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ items,
+                  int n_items, int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext) {
+  __shared__ __align__(16) unsigned char smem[kBatchLds > 4 * BT * 8 ? kBatchLds : 4 * BT * 8];
+  __shared__ int s_item, s_fin;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= n_items) break;
+    const int2 d = items[it];
+    const int j = d.x & 0xffffff, ph = d.x >> 24, tile = d.y;
+    const BatchProb& pb = probs[j];
+    if (ph == 1) bounded_wait(&cnt[j], pb.nR, &ctl[2]);
+    if (ph == 2) bounded_wait(&cnt[nprob + j], pb.nC, &ctl[2]);
+    switch (pb.P) {
+      case 256: batch_tile<256>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+      case 512: batch_tile<512>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+      case 1024: batch_tile<1024>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+      case 2048: batch_tile<2048>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+      default: break;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();  // publish this tile's results before counting it
+      const int done = atomicAdd(&cnt[ph * nprob + j], 1);
+      s_fin = (ph == 2 && done == pb.nRp - 1) ? 1 : 0;
+      if (s_fin) __threadfence();  // see every other tile's partial sums
+    }
+    __syncthreads();
+    if (s_fin) batch_finalize(pb, reinterpret_cast<double*>(smem));
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int left = atomicAdd(&ctl[1], 1);
+    if (left == (int)gridDim.x - 1) {
+      // every other block has left the loop: reset the queue for the next launch
+      ctl[0] = 0;
+      ctl[1] = 0;
+      for (int i = 0; i < 3 * nprob; ++i) cnt[i] = 0;
+      __threadfence();
+    }
+  }
+}
+
+__global__ void fill_int_kernel(int* x, idx_t n, int v) {
+  const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
 }
 
 // ------------------------------------------------------------------- launch configuration
@@ -712,6 +951,31 @@ int rows_inv_rows_per_block(int P) {
 }
 
 int cols_tile_width(int P) { return col_tc(P); }
+
+bool batch_supports(int P) { return P >= 256 && P <= 2048; }
+
+void batch_tile_counts(int N, int P, int nz, int* nR, int* nC, int* nRp) {
+  const int tpf = P / kE;
+  const int pairs = BT / tpf < 1 ? 1 : BT / tpf;
+  const int tc = pairs;
+  *nR = (nz * (N / 2) + pairs - 1) / pairs;
+  *nC = nz * ((P / 2) / tc);
+  *nRp = nz * ((N + 2 * pairs - 1) / (2 * pairs));
+}
+
+hipError_t launch_batch_iteration(const BatchProb* probs, const int2* items, int n_items,
+                                  int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext,
+                                  int grid, hipStream_t st) {
+  hipLaunchKernelGGL(batch_iter_kernel, dim3(grid), dim3(BT), 0, st, probs, items, n_items, ctl,
+                     cnt, nprob, ik, ikm1, inext);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, v);
+  return hipGetLastError();
+}
 
 #define TOMO_PSWITCH(CALL)          \
   switch (P) {                      \

@@ -3,6 +3,7 @@
 // the kernels of toeplitz_kernels.hip and gridding_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -43,6 +44,7 @@ struct Level {
   double beta_bp = 0.0, beta_psf = 0.0;
   double L = 0.0, lambda = 0.0;
   size_t off_fk = 0, off_fkn = 0, off_b = 0;
+  size_t off_rowptr = 0, off_cidx = 0, off_cw = 0, off_deapod = 0;  // gridding lists
 };
 
 }  // namespace
@@ -68,7 +70,8 @@ struct tomo_plan_s {
   size_t off_g0 = 0, off_wx = 0, off_wy = 0;
   size_t off_scratch = 0, scratch_bytes = 0;
   size_t off_gp = 0, off_ppartials = 0;
-  bool fused_prior = false;
+  size_t off_cnt = 0, off_scan = 0, off_rampf = 0;
+  bool fused_prior = false, grids_ready = false;
   bool tables_ready = false, psf_ready = false;
   std::string err;
 
@@ -153,11 +156,21 @@ void layout(tomo_plan p) {
   const int na = p->g.n_angles;
   p->off_angles = take(na * sizeof(double));
   p->off_atab = take(2 * na * sizeof(double));
+  size_t maxcells = 0;
   for (Level& l : p->lv) {
     l.off_fk = take((size_t)l.P * (l.P / 2) * sizeof(float));
     l.off_fkn = take((size_t)l.P * sizeof(float));
     l.off_b = take((size_t)p->nz * l.n * l.n * sizeof(float));
+    const size_t cells = (size_t)l.M * l.M;
+    const size_t nnz = (size_t)p->g.n_angles * (l.nd - 1) * p->g.kb_width * p->g.kb_width;
+    l.off_rowptr = take((cells + 1) * sizeof(int));
+    l.off_cidx = take(nnz * sizeof(int));
+    l.off_cw = take(nnz * sizeof(float));
+    l.off_deapod = take((size_t)l.n * sizeof(float));
+    maxcells = std::max(maxcells, cells);
   }
+  p->off_cnt = take(maxcells * sizeof(int));
+  p->off_scan = take((maxcells / 4096 + 2) * sizeof(int));
   for (int i = 0; i < 3; ++i) p->off_x[i] = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
   p->off_gp = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
   size_t maxprior = 1;
@@ -167,6 +180,7 @@ void layout(tomo_plan p) {
   p->off_ghat = take((size_t)p->nz * npts_max * sizeof(cpx<float>));
   p->off_dfttab = take((size_t)fin.nd * sizeof(cpx<float>));
   p->off_post = take((size_t)fin.nd * sizeof(cpx<float>));
+  p->off_rampf = take((size_t)fin.nd * sizeof(float));
   const int W = p->g.kb_width;
   p->off_g0 = take(npts_max * sizeof(int2));
   p->off_wx = take(npts_max * W * sizeof(float));
@@ -261,43 +275,67 @@ GridGeom bp_geom(tomo_plan p, const Level& l) {
   return gg;
 }
 
-// out[nz][N_l][N_l] = R*_l g_l (ramp = 0) or FBP (ramp = 1) of level l.
+// Geometry-only gridding data of every level: the cell-sorted contribution lists of the
+// back-projection grid and the deapodisation factors (built once per attached workspace).
+tomo_status ensure_grids(tomo_plan p) {
+  if (p->grids_ready) return TOMO_OK;
+  hipStream_t st = p->stream;
+  for (Level& l : p->lv) {
+    const GridGeom gg = bp_geom(p, l);
+    int2* g0 = p->at<int2>(p->off_g0);
+    float* wx = p->at<float>(p->off_wx);
+    float* wy = p->at<float>(p->off_wy);
+    HIPCHK(p, launch_point_table<float>(p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+    HIPCHK(p, launch_csr_build(p->at<double>(p->off_atab), g0, wx, wy, gg, p->at<int>(p->off_cnt),
+                               p->at<int>(l.off_rowptr), p->at<int>(l.off_cidx),
+                               p->at<float>(l.off_cw), p->at<int>(p->off_scan), st));
+    HIPCHK(p, launch_deapod_table(p->at<float>(l.off_deapod), gg, st));
+  }
+  p->grids_ready = true;
+  return TOMO_OK;
+}
+
+// out[nz][N_l][N_l] = R*_l g_l (ramp = 0) or FBP (ramp = 1) of level l.  With reuse the
+// radial spectrum of the previous call (same level and sinogram) is used again.
 tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sino, float* out,
-                                   int ramp);
+                                   int ramp, bool reuse);
 tomo_status backproject_level(tomo_plan p, const Level& l, const float* sino, float* out,
-                              int ramp) {
+                              int ramp, bool reuse = false) {
   const int ti = tbegin(p, TOMO_T_BACKPROJECT);
-  const tomo_status s = backproject_level_impl(p, l, sino, out, ramp);
+  const tomo_status s = backproject_level_impl(p, l, sino, out, ramp, reuse);
   tend(p, ti);
   return s;
 }
 
 tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sino, float* out,
-                                   int ramp) {
+                                   int ramp, bool reuse) {
   hipStream_t st = p->stream;
+  tomo_status s = ensure_grids(p);
+  if (s != TOMO_OK) return s;
   const GridGeom gg = bp_geom(p, l);
   cpx<float>* ghat = p->at<cpx<float>>(p->off_ghat);
-  cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
-  cpx<float>* post = p->at<cpx<float>>(p->off_post);
-  HIPCHK(p, launch_radial_tables(tab, post, gg, ramp, st));
-  HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
-  int2* g0 = p->at<int2>(p->off_g0);
-  float* wx = p->at<float>(p->off_wx);
-  float* wy = p->at<float>(p->off_wy);
-  HIPCHK(p, launch_point_table<float>(p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+  float* rampf = p->at<float>(p->off_rampf);
+  if (!reuse) {
+    cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
+    cpx<float>* post = p->at<cpx<float>>(p->off_post);
+    HIPCHK(p, launch_radial_tables(tab, post, rampf, gg, 0, st));
+    HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
+  }
   const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
   int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / slice_grid);
   if (chunk < 1) return fail(p, TOMO_ERR_INTERNAL, "scratch too small for one grid slice");
   cpx<float>* grid = p->at<cpx<float>>(p->off_scratch);
   for (int z0 = 0; z0 < p->nz; z0 += chunk) {
     const int zc = std::min(chunk, p->nz - z0);
-    for (int zb = 0; zb < zc; zb += 8) {
-      const int nzb = std::min(8, zc - zb);
-      HIPCHK(p, launch_spread_f32(ghat, grid + (size_t)zb * l.M * l.M, p->at<double>(p->off_atab),
-                                  g0, wx, wy, gg, z0 + zb, nzb, p->nz, st));
+    for (int zb = 0; zb < zc; zb += 64) {
+      const int nzb = std::min(64, zc - zb);
+      HIPCHK(p, launch_gather(ghat, grid + (size_t)zb * l.M * l.M, p->at<int>(l.off_rowptr),
+                              p->at<int>(l.off_cidx), p->at<float>(l.off_cw),
+                              ramp ? rampf : nullptr, gg, p->nz, z0 + zb, nzb, st));
     }
     HIPCHK(p, launch_fft2d_f32(grid, l.M, zc, +1, p->tw32(l.M), st));
-    HIPCHK(p, launch_crop_deapod(grid, out + (size_t)z0 * l.n * l.n, gg, zc, st));
+    HIPCHK(p, launch_crop_deapod(grid, out + (size_t)z0 * l.n * l.n, p->at<float>(l.off_deapod),
+                                 gg, zc, st));
   }
   return TOMO_OK;
 }
@@ -488,7 +526,7 @@ tomo_status validate_geom(const tomo_geometry_t* g) {
   if (!(g->T > 0.0) || !std::isfinite(g->T)) return fail(nullptr, TOMO_ERR_INVALID_ARG, "T must be > 0");
   if (g->neighbours != 8 && g->neighbours != 26)
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "neighbours must be 8 or 26");
-  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_FUSED_PRIOR))
+  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_SPLIT_PRIOR))
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "unknown flag bits 0x%x", g->flags);
   if (g->angles)
     for (int i = 0; i < g->n_angles; ++i)
@@ -526,7 +564,7 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->nz = geom->n_slices;
   p->use_graphs = (geom->flags & TOMO_FLAG_NO_GRAPH) == 0;
-  p->fused_prior = (geom->flags & TOMO_FLAG_FUSED_PRIOR) != 0;
+  p->fused_prior = (geom->flags & TOMO_FLAG_SPLIT_PRIOR) == 0;
   p->n_levels = geom->n_levels == 0 ? 1 : geom->n_levels;
   if (p->g.kb_width == 0) p->g.kb_width = 6;
   if (p->g.kb_oversamp == 0.0) p->g.kb_oversamp = 2.0;
@@ -604,6 +642,7 @@ tomo_status tomo_plan_set_workspace(tomo_plan p, void* dev, size_t bytes) {
   p->ws_bytes = bytes;
   p->tables_ready = false;
   p->psf_ready = false;
+  p->grids_ready = false;
   return TOMO_OK;
 }
 
@@ -613,6 +652,7 @@ tomo_status tomo_precompute_psf(tomo_plan p) {
   if (s != TOMO_OK) return s;
   HIPCHK(p, hipSetDevice(p->device));
   if ((s = ensure_tables(p)) != TOMO_OK) return s;
+  if ((s = ensure_grids(p)) != TOMO_OK) return s;
   for (Level& l : p->lv) {
     const int ti = tbegin(p, TOMO_T_PSF);
     s = psf_level(p, l);
@@ -698,7 +738,7 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
                                    1.0 / l.stride, p->partials(), sc + SC_GG, st));
     if (li == 0) {
       if (opts->init == TOMO_INIT_FBP) {
-        if ((s = backproject_level(p, l, sino, p->xbuf(cur), 1)) != TOMO_OK) return s;
+        if ((s = backproject_level(p, l, sino, p->xbuf(cur), 1, true)) != TOMO_OK) return s;
       } else if (opts->init == TOMO_INIT_ZERO) {
         HIPCHK(p, launch_fill(p->xbuf(cur), (idx_t)vol, 0.0f, st));
       } else {
@@ -794,6 +834,295 @@ tomo_status tomo_lanczos_prolong(const float* in, float* out, int32_t n, int32_t
   if (!in || !out || n < 1 || n_slices < 1) return fail(nullptr, TOMO_ERR_INVALID_ARG, "bad argument");
   hipError_t e = launch_lanczos_prolong(in, out, n, n_slices, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(nullptr, TOMO_ERR_HIP, "prolongation launch: %s", hipGetErrorString(e));
+  return TOMO_OK;
+}
+
+// ============================================================================== batches
+}  // extern "C"
+
+struct tomo_batch_s {
+  std::vector<tomo_plan> plans;
+  hipStream_t stream = nullptr;
+  int device = 0, grid = 0;
+  std::vector<BatchProb> probs;
+  std::vector<int2> items;
+  char* ws = nullptr;
+  size_t need = 0, off_probs = 0, off_items = 0, off_ctl = 0, off_cnt = 0;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_rot = -1;
+  std::string err;
+};
+
+namespace {
+
+tomo_status bfail(tomo_batch b, tomo_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf;
+  g_last_error = buf;
+  return s;
+}
+
+#define BHIPCHK(b, call)                                                                 \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return bfail(b, TOMO_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+// Per-problem setup on the batch stream: PSF (if needed), b, FBP start, scalars.
+tomo_status batch_prepare(tomo_batch bt, int j, const float* sino, int restart) {
+  tomo_plan p = bt->plans[j];
+  hipStream_t keep = p->stream;
+  p->stream = bt->stream;
+  tomo_status s = ensure_tables(p);
+  if (s == TOMO_OK && !p->psf_ready) s = tomo_precompute_psf(p);
+  const Level& l = p->lv[0];
+  if (s == TOMO_OK) s = backproject_level(p, l, sino, p->at<float>(l.off_b), 0);
+  if (s == TOMO_OK) s = backproject_level(p, l, sino, p->xbuf(0), 1, true);
+  hipStream_t st = bt->stream;
+  double* sc = p->scal();
+  hipError_t e = hipSuccess;
+  if (s == TOMO_OK) {
+    e = launch_sumsq_strided(sino, (idx_t)p->nz * p->g.n_angles, l.nd, 1, 1.0, p->partials(),
+                             sc + SC_GG, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_MU, 1, nullptr, 0.0, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / l.L, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_RESTART_ON, 1, nullptr, restart ? 1.0 : 0.0, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_ITER, 1, nullptr, 0.0, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_NRESTART, 1, nullptr, 0.0, st);
+    if (e == hipSuccess) e = launch_set_scalars(sc, SC_NONFINITE, 1, nullptr, -1.0, st);
+    if (e != hipSuccess) s = bfail(bt, TOMO_ERR_HIP, "batch setup launch: %s", hipGetErrorString(e));
+  } else {
+    bfail(bt, s, "problem %d: %s", j, p->err.c_str());
+  }
+  p->stream = keep;
+  return s;
+}
+
+tomo_status batch_launch(tomo_batch bt, int ik, int ikm1, int inext, hipStream_t st) {
+  const int nprob = (int)bt->plans.size();
+  BHIPCHK(bt, launch_batch_iteration(reinterpret_cast<const BatchProb*>(bt->ws + bt->off_probs),
+                                     reinterpret_cast<const int2*>(bt->ws + bt->off_items),
+                                     (int)bt->items.size(), reinterpret_cast<int*>(bt->ws + bt->off_ctl),
+                                     reinterpret_cast<int*>(bt->ws + bt->off_cnt), nprob, ik, ikm1,
+                                     inext, bt->grid, st));
+  return TOMO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tomo_status tomo_batch_create(const tomo_plan* plans, int32_t n, void* hip_stream, tomo_batch* out) {
+  if (!out) return bfail(nullptr, TOMO_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!plans || n < 1 || n > (1 << 20)) return bfail(nullptr, TOMO_ERR_INVALID_ARG, "need 1..2^20 plans");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return bfail(nullptr, TOMO_ERR_NO_DEVICE, "hipGetDevice failed");
+  for (int j = 0; j < n; ++j) {
+    tomo_plan p = plans[j];
+    if (!p) return bfail(nullptr, TOMO_ERR_INVALID_ARG, "plan %d is NULL", j);
+    if (p->n_levels != 1) return bfail(nullptr, TOMO_ERR_INVALID_ARG, "plan %d has several levels", j);
+    if (!p->ws) return bfail(nullptr, TOMO_ERR_INVALID_ARG, "plan %d has no workspace", j);
+    if (!batch_supports(p->lv[0].P))
+      return bfail(nullptr, TOMO_ERR_INVALID_ARG, "plan %d: FFT size %d outside 256..2048", j, p->lv[0].P);
+    if (p->device != dev) return bfail(nullptr, TOMO_ERR_INVALID_ARG, "plan %d is on another device", j);
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return bfail(nullptr, TOMO_ERR_HIP, "hipGetDeviceProperties failed");
+  tomo_batch b = new tomo_batch_s();
+  b->plans.assign(plans, plans + n);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->device = dev;
+  b->grid = prop.multiProcessorCount * 2;  // two resident 256-thread blocks per CU
+  // work list: all pass-R tiles, then pass C, then pass R'; larger transforms first
+  std::vector<int> order(n);
+  for (int j = 0; j < n; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return plans[a]->lv[0].P > plans[c]->lv[0].P; });
+  b->probs.resize(n);
+  for (int j = 0; j < n; ++j) {
+    const Level& l = plans[j]->lv[0];
+    BatchProb& d = b->probs[j];
+    std::memset(&d, 0, sizeof d);
+    d.N = l.n;
+    d.P = l.P;
+    d.nz = plans[j]->nz;
+    d.neighbours = plans[j]->g.neighbours;
+    batch_tile_counts(l.n, l.P, d.nz, &d.nR, &d.nC, &d.nRp);
+  }
+  for (int ph = 0; ph < 3; ++ph)
+    for (int j : order) {
+      const BatchProb& d = b->probs[j];
+      const int cntp = ph == 0 ? d.nR : ph == 1 ? d.nC : d.nRp;
+      for (int t = 0; t < cntp; ++t) b->items.push_back(make_int2(j | (ph << 24), t));
+    }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  b->off_probs = take(n * sizeof(BatchProb));
+  b->off_items = take(b->items.size() * sizeof(int2));
+  b->off_ctl = take(4 * sizeof(int));
+  b->off_cnt = take(3 * (size_t)n * sizeof(int));
+  b->need = off;
+  *out = b;
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_workspace_size(tomo_batch b, size_t* bytes) {
+  if (!b || !bytes) return bfail(b, TOMO_ERR_INVALID_ARG, "NULL argument");
+  *bytes = b->need;
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_set_workspace(tomo_batch b, void* dev, size_t bytes) {
+  if (!b || !dev) return bfail(b, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(dev)) return bfail(b, TOMO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < b->need) return bfail(b, TOMO_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  if (b->gexec) {
+    hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  b->ws = static_cast<char*>(dev);
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(int2),
+                            hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_ctl), 4, 0, b->stream));
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 3 * (idx_t)b->plans.size(), 0,
+                             b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_reconstruct(tomo_batch b, const float* const* sinos, float* const* xs,
+                                   int32_t iters, int32_t restart, tomo_batch_stats_t* stats) {
+  if (!b || !sinos || !xs || iters < 0) return bfail(b, TOMO_ERR_INVALID_ARG, "bad argument");
+  if (!b->ws) return bfail(b, TOMO_ERR_NO_WORKSPACE, "no workspace attached");
+  const int n = (int)b->plans.size();
+  for (int j = 0; j < n; ++j)
+    if (!sinos[j] || !xs[j] || !aligned(sinos[j]) || !aligned(xs[j]))
+      return bfail(b, TOMO_ERR_INVALID_ARG, "problem %d: NULL or misaligned array", j);
+  BHIPCHK(b, hipSetDevice(b->device));
+  tomo_status s;
+  for (int j = 0; j < n; ++j)
+    if ((s = batch_prepare(b, j, sinos[j], restart)) != TOMO_OK) return s;
+  for (int j = 0; j < n; ++j) {
+    tomo_plan p = b->plans[j];
+    const Level& l = p->lv[0];
+    BatchProb& d = b->probs[j];
+    for (int i = 0; i < 3; ++i) d.x[i] = p->xbuf(i);
+    d.b = p->at<float>(l.off_b);
+    d.fk = p->at<float>(l.off_fk);
+    d.fkn = p->at<float>(l.off_fkn);
+    d.S1 = p->S1();
+    d.S2 = p->S2(l);
+    d.partials = p->partials();
+    d.scal = p->scal();
+    d.tw = p->tw32(l.P);
+    d.hist = nullptr;
+    d.rhist = nullptr;
+    d.pp = p->pp;
+  }
+  hipStream_t st = b->stream;
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(), n * sizeof(BatchProb),
+                            hipMemcpyHostToDevice, st));
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_ctl), 4, 0, st));
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 3 * (idx_t)n, 0, st));
+  int ik = 0, ikm1 = 0, inext = 1, k = 0;
+  while (k < iters) {
+    if (k >= 1 && iters - k >= 3) {
+      // steady rotation: replay a captured graph of three persistent launches
+      const int rot = ik * 9 + ikm1 * 3 + inext;
+      if (!b->gstream) {
+        BHIPCHK(b, hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking));
+        BHIPCHK(b, hipEventCreateWithFlags(&b->gev_in, hipEventDisableTiming));
+        BHIPCHK(b, hipEventCreateWithFlags(&b->gev_out, hipEventDisableTiming));
+      }
+      if (!b->gexec || b->graph_rot != rot) {
+        if (b->gexec) hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        hipGraph_t g = nullptr;
+        BHIPCHK(b, hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
+        int a = ik, c = ikm1, d = inext;
+        for (int r = 0; r < 3; ++r) {
+          s = batch_launch(b, a, c, d, b->gstream);
+          if (s != TOMO_OK) break;
+          c = a;
+          a = d;
+          d = 3 - a - c;
+        }
+        const hipError_t e = hipStreamEndCapture(b->gstream, &g);
+        if (s != TOMO_OK) {
+          if (g) hipGraphDestroy(g);
+          return s;
+        }
+        if (e != hipSuccess) return bfail(b, TOMO_ERR_HIP, "batch graph capture: %s", hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e2 != hipSuccess) return bfail(b, TOMO_ERR_HIP, "batch graph instantiate: %s", hipGetErrorString(e2));
+        b->graph_rot = rot;
+      }
+      BHIPCHK(b, hipEventRecord(b->gev_in, st));
+      BHIPCHK(b, hipStreamWaitEvent(b->gstream, b->gev_in, 0));
+      while (iters - k >= 3) {
+        BHIPCHK(b, hipGraphLaunch(b->gexec, b->gstream));
+        k += 3;
+      }
+      BHIPCHK(b, hipEventRecord(b->gev_out, b->gstream));
+      BHIPCHK(b, hipStreamWaitEvent(st, b->gev_out, 0));
+      continue;
+    }
+    if ((s = batch_launch(b, ik, ikm1, inext, st)) != TOMO_OK) return s;
+    ikm1 = ik;
+    ik = inext;
+    inext = 3 - ik - ikm1;
+    ++k;
+  }
+  for (int j = 0; j < n; ++j) {
+    tomo_plan p = b->plans[j];
+    const size_t vol = (size_t)p->nz * p->lv[0].n * p->lv[0].n;
+    BHIPCHK(b, hipMemcpyAsync(xs[j], p->xbuf(ik), vol * sizeof(float), hipMemcpyDeviceToDevice, st));
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    int ctl[4];
+    BHIPCHK(b, hipMemcpyAsync(ctl, b->ws + b->off_ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+    std::vector<double> sv((size_t)n * SC_COUNT);
+    for (int j = 0; j < n; ++j)
+      BHIPCHK(b, hipMemcpyAsync(&sv[(size_t)j * SC_COUNT], b->plans[j]->scal(), SC_COUNT * sizeof(double),
+                                hipMemcpyDeviceToHost, st));
+    BHIPCHK(b, hipStreamSynchronize(st));
+    for (int j = 0; j < n; ++j) {
+      stats->n_restarts += (int32_t)sv[(size_t)j * SC_COUNT + SC_NRESTART];
+      if (sv[(size_t)j * SC_COUNT + SC_NONFINITE] >= 0.0) stats->n_nonfinite += 1;
+    }
+    stats->wait_timeouts = ctl[2] != 0;
+    if (stats->wait_timeouts) return bfail(b, TOMO_ERR_INTERNAL, "a batch tile gave up waiting");
+    if (stats->n_nonfinite) return bfail(b, TOMO_ERR_NONFINITE, "%d problems went non-finite", stats->n_nonfinite);
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_destroy(tomo_batch b) {
+  if (!b) return TOMO_OK;
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->gstream) {
+    hipStreamSynchronize(b->gstream);
+    hipStreamDestroy(b->gstream);
+  }
+  if (b->gev_in) hipEventDestroy(b->gev_in);
+  if (b->gev_out) hipEventDestroy(b->gev_out);
+  delete b;
   return TOMO_OK;
 }
 

@@ -25,7 +25,7 @@ STATUS_NAMES = {
 INIT_FBP, INIT_ZERO, INIT_USER = 0, 1, 2
 T_ROWS_FWD, T_COLS_CONV, T_ROWS_INV, T_FINALIZE, T_BACKPROJECT, T_PSF, T_PRIOR, T_COUNT = range(8)
 FLAG_NO_GRAPH = 1
-FLAG_FUSED_PRIOR = 2
+FLAG_SPLIT_PRIOR = 2
 
 
 class TomoError(RuntimeError):
@@ -61,6 +61,11 @@ class ReconStats(ctypes.Structure):
     ]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("n_nonfinite", ctypes.c_int32), ("n_restarts", ctypes.c_int32),
+                ("wait_timeouts", ctypes.c_int32)]
+
+
 EXPORTS = {
     "tomo_plan_create": ([ctypes.POINTER(Geometry), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "tomo_plan_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -81,6 +86,13 @@ EXPORTS = {
     "tomo_timing_read": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
                          ctypes.c_int),
     "tomo_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "tomo_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
+                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "tomo_batch_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tomo_batch_set_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "tomo_batch_reconstruct": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(BatchStats)], ctypes.c_int),
+    "tomo_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "tomo_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tomo_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
 }
@@ -138,7 +150,7 @@ class Plan:
                  kb_beta: float = 0.0, beta: float = 0.01, p: float = 1.2, q: float = 2.0,
                  sigma: float = 0.1, T: float = 1.0, neighbours: int = 26, stream=None,
                  device: Optional[torch.device] = None, graphs: bool = True,
-                 fused_prior: bool = False):
+                 split_prior: bool = False):
         lib = load_library()
         self._lib = lib
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
@@ -154,7 +166,7 @@ class Plan:
         g.kb_oversamp, g.kb_beta = kb_oversamp, kb_beta
         g.beta, g.p, g.q, g.sigma, g.T = beta, p, q, sigma, T
         g.neighbours = neighbours
-        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_FUSED_PRIOR if fused_prior else 0)
+        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_SPLIT_PRIOR if split_prior else 0)
         self.geometry = g
         self.n, self.n_slices, self.n_angles, self.n_det = n, n_slices, n_angles, n_det
         self.n_levels = n_levels
@@ -253,3 +265,47 @@ def lanczos_prolong(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=
         out = torch.empty((nz, 2 * n, 2 * n), dtype=torch.float32, device=x.device)
     _check(lib.tomo_lanczos_prolong(_ptr(x), _ptr(out), n, nz, _stream_ptr(stream)))
     return out
+
+
+class Batch:
+    """Independent single-level plans advanced together, one persistent launch per iteration."""
+
+    def __init__(self, plans: Sequence[Plan], stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.plans = list(plans)
+        self.device = self.plans[0].device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.tomo_batch_create(arr, len(self.plans), _stream_ptr(self.stream), ctypes.byref(h)))
+        self._h = h
+        sz = ctypes.c_size_t()
+        _check(lib.tomo_batch_workspace_size(self._h, ctypes.byref(sz)))
+        self._ws = torch.empty(sz.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        _check(lib.tomo_batch_set_workspace(self._h, ctypes.c_void_p(base + (-base) % 256), sz.value))
+
+    def reconstruct(self, sinos: Sequence[torch.Tensor], xs: Sequence[torch.Tensor], iters: int,
+                    restart: bool = True):
+        n = len(self.plans)
+        sp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in sinos])
+        xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xs])
+        for t in list(sinos) + list(xs):
+            _ptr(t)
+        st = BatchStats()
+        _check(self._lib.tomo_batch_reconstruct(self._h, sp, xp, int(iters), int(restart), ctypes.byref(st)))
+        return {"n_nonfinite": st.n_nonfinite, "n_restarts": st.n_restarts,
+                "wait_timeouts": st.wait_timeouts}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tomo_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
