@@ -100,10 +100,11 @@ typedef struct {
  * captured three-iteration HIP graphs (which tomo_reconstruct uses for levels with at
  * least 7 iterations, on an internal stream ordered after the plan's stream). */
 #define TOMO_FLAG_NO_GRAPH 1u
-/* tomo_geometry_t.flags: evaluate the qGGMRF gradient in a separate z-marching kernel that
- * evaluates each neighbour pair once, instead of inside the inverse-row epilogue over a
- * neighbour tile (each pair evaluated from both of its voxels).  Same results to rounding. */
-#define TOMO_FLAG_SPLIT_PRIOR 2u
+/* tomo_geometry_t.flags: evaluate the qGGMRF gradient inside the inverse-row epilogue over a
+ * neighbour tile (each pair evaluated from both of its voxels) instead of the default
+ * separate z-marching kernel that evaluates each neighbour pair once.  Same results to
+ * rounding; the default is faster on gfx950. */
+#define TOMO_FLAG_FUSED_PRIOR 2u
 
 /* Options of tomo_reconstruct(). */
 typedef struct {

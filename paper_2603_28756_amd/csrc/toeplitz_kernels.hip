@@ -235,164 +235,186 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
 }
 
 // ---------------------------------------------------------------------------- prior (3D)
-// gp = beta grad Phi(y) with y = x_k + mu (x_k - x_{k-1}), evaluated once per neighbour pair.
-// A block owns a TR x TCc column of voxels and marches through ZC slices, keeping three
-// y planes (with a one-voxel halo) in LDS.  Per plane it evaluates rho' once for each
-// in-plane pair (4 lexicographically positive offsets) and for each pair crossing to the
-// next plane (9 offsets); a pair's value enters its first voxel with + and its second with -
-// (rho' is odd), so every pair inside the tile is evaluated once instead of twice.
-// With OBJ the block also sums rho over the pairs whose first voxel it owns.
-constexpr int PR_TR = 16, PR_TC = 32, PR_ZC = 16, PR_NT = 256;
+// gp = beta grad Phi(y), y = x_k + mu (x_k - x_{k-1}), with every neighbour pair evaluated
+// once.  A block owns a 16 x 16 column of voxels (one per thread) and marches through 16
+// slices, keeping planes z and z+1 (with a one-voxel halo) in LDS.  Per plane each thread
+// evaluates the forward pairs of its voxel: 4 in-plane offsets (0,1), (1,-1), (1,0), (1,1)
+// and the 9 offsets into plane z+1; threads 0..67 also evaluate, for one halo position each,
+// the forward pairs that end inside the tile.  A pair's value enters its first voxel with +
+// and its second with - (rho' is odd).  With OBJ the block also sums rho over the forward
+// pairs of its own voxels.
+constexpr int PR_T = 16, PR_ZC = 16, PR_NT = 256;
+constexpr int PR_H = PR_T + 2, PR_HA = PR_H * PR_H;
 
 template <int NB, bool OBJ>
 __global__ void __launch_bounds__(PR_NT)
 prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
              const double* __restrict__ scal, float* __restrict__ gp,
              double* __restrict__ partials, int N, int nz, int mode_fista, PriorParams pp) {
-  constexpr int TR = PR_TR, TCc = PR_TC, ZC = PR_ZC, NT = PR_NT;
-  constexpr int HR = TR + 2, HC = TCc + 2, HA = HR * HC;
-  constexpr int VPT = TR * TCc / NT;
-  __shared__ float ybuf[3][HA];
-  __shared__ float pin[4][HA];
-  __shared__ float pz[NB == 26 ? 9 : 1][HA];
-  __shared__ double sred[(NT / 64) * 4];
+  constexpr int H = PR_H, HA = PR_HA;
+  __shared__ float Y[2][HA];
+  __shared__ float fin[4][HA];
+  __shared__ float fz[NB == 26 ? 9 : 1][HA];
+  __shared__ double sred[(PR_NT / 64) * 4];
 
   const int t = threadIdx.x;
-  const int c0 = blockIdx.x * TCc, r0 = blockIdx.y * TR, z0 = blockIdx.z * ZC;
-  const int z1 = min(z0 + ZC, nz);
+  const int tr = t >> 4, tc = t & 15;
+  const int s = (tr + 1) * H + tc + 1;  // own position (halo coordinates)
+  const int c0 = blockIdx.x * PR_T, r0 = blockIdx.y * PR_T, z0 = blockIdx.z * PR_ZC;
+  const int z1 = min(z0 + PR_ZC, nz);
   const float mu = mode_fista ? (float)scal[SC_MU] : 0.f;
+  const float w1 = pp.wts[1], w2 = pp.wts[2], w3 = pp.wts[3];
 
+  // Halo work: the forward pairs that start on the halo ring and end inside the tile, as one
+  // item (position, offset) per thread.  In-plane items (98): top row x offsets
+  // (1,-1),(1,0),(1,1); left column x (0,1),(1,1); right column x (1,-1); two corners.
+  // Cross-plane items (196): top row x dy=+1, bottom row x dy=-1, left column x dx=+1,
+  // right column x dx=-1 (3 each), four corners.  Items whose end leaves the tile are idle.
+  int in_pos = -1, in_o = 0;
+  if (t < 48) { in_pos = (t / 3 + 1); in_o = 1 + t % 3; }                   // top row
+  else if (t < 80) { const int k = t - 48; in_pos = (k / 2 + 1) * H; in_o = (k & 1) ? 3 : 0; }
+  else if (t < 96) { in_pos = (t - 80 + 1) * H + H - 1; in_o = 1; }           // right column
+  else if (t == 96) { in_pos = 0; in_o = 3; }                                  // corner (0,0)
+  else if (t == 97) { in_pos = H - 1; in_o = 1; }                              // corner (0,H-1)
+  int x_pos = -1, x_o = 0;
+  {
+    const int k = t;
+    if (k < 48) { x_pos = k / 3 + 1; x_o = 6 + k % 3; }                          // top: dy=+1
+    else if (k < 96) { x_pos = (H - 1) * H + (k - 48) / 3 + 1; x_o = (k - 48) % 3; }   // bottom
+    else if (k < 144) { x_pos = ((k - 96) / 3 + 1) * H; x_o = 3 * ((k - 96) % 3) + 2; } // left
+    else if (k < 192) { x_pos = ((k - 144) / 3 + 1) * H + H - 1; x_o = 3 * ((k - 144) % 3); }
+    else if (k == 192) { x_pos = 0; x_o = 8; }
+    else if (k == 193) { x_pos = H - 1; x_o = 6; }
+    else if (k == 194) { x_pos = (H - 1) * H; x_o = 2; }
+    else if (k == 195) { x_pos = (H - 1) * H + H - 1; x_o = 0; }
+  }
+
+  auto inside = [&](int pos) {
+    const int a = pos / H, b = pos - a * H;
+    const int r = r0 - 1 + a, c = c0 - 1 + b;
+    return r >= 0 && r < N && c >= 0 && c < N;
+  };
+  auto in_tile = [&](int a, int b) { return a >= 1 && a <= PR_T && b >= 1 && b <= PR_T; };
   auto load_plane = [&](int z, float* dst) {
-    for (int e = t; e < HA; e += NT) {
-      const int hr = e / HC, hc = e - hr * HC;
-      const int r = r0 - 1 + hr, c = c0 - 1 + hc;
+    for (int e = t; e < HA; e += PR_NT) {
+      const int a = e / H, b = e - a * H;
+      const int r = r0 - 1 + a, c = c0 - 1 + b;
       float v = 0.f;
       if (r >= 0 && r < N && c >= 0 && c < N) {
         const idx_t o = ((idx_t)z * N + r) * N + c;
-        const float a = xk[o];
-        v = mode_fista ? a + mu * (a - xkm1[o]) : a;
+        const float xa = xk[o];
+        v = mode_fista ? xa + mu * (xa - xkm1[o]) : xa;
       }
       dst[e] = v;
     }
   };
-  auto inside = [&](int hr, int hc) {
-    const int r = r0 - 1 + hr, c = c0 - 1 + hc;
-    return r >= 0 && r < N && c >= 0 && c < N;
-  };
-  auto owned = [&](int hr, int hc) { return hr >= 1 && hr <= TR && hc >= 1 && hc <= TCc; };
-
-  float acc[VPT], accn[VPT];
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) acc[j] = accn[j] = 0.f;
+  const bool own_in = inside(s);
   double phi = 0.0;
 
-  int bp = 0, bc = 1, bn = 2;  // previous / current / next plane buffers
-  load_plane(z0, ybuf[bc]);
-  if (NB == 26 && z0 > 0) load_plane(z0 - 1, ybuf[bp]);
-  __syncthreads();
-
-  // cross-plane pairs between planes (zs, zs+1) held in buffers (b0, b1); contributions
-  // to the upper plane's voxels go to accn (sign -), to the lower plane's to acc (sign +)
-  auto cross = [&](int b0, int b1, bool count_phi, bool lower_is_output) {
-    for (int e = t; e < 9 * HA; e += NT) {
-      const int o = e / HA, pidx = e - o * HA;
+  // forward pairs from plane buffer `src` to plane buffer `dst` (9 offsets (dy, dx))
+  auto cross_fwd = [&](const float* src, const float* dst, bool count_phi) {
+    const float ys = src[s];
+#pragma unroll
+    for (int o = 0; o < 9; ++o) {
       const int dy = o / 3 - 1, dx = o % 3 - 1;
-      const int hr = pidx / HC, hc = pidx - hr * HC;
-      const int qr = hr + dy, qc = hc + dx;
-      float val = 0.f;
-      if (qr >= 0 && qr < HR && qc >= 0 && qc < HC && inside(hr, hc) && inside(qr, qc)) {
-        float rv = 0.f;
-        qggmrf<OBJ>(ybuf[b0][pidx] - ybuf[b1][qr * HC + qc], pp, val, rv);
-        if (OBJ && count_phi && owned(hr, hc))
-          phi += (double)(pp.wts[1 + (dy != 0) + (dx != 0)] * rv);
-      }
-      pz[o][pidx] = val;
+      const int q = s + dy * H + dx;
+      float rp, rv = 0.f;
+      const bool v = own_in && inside(q);
+      qggmrf<OBJ>(v ? ys - dst[q] : 0.f, pp, rp, rv);
+      fz[o][s] = rp;
+      if (OBJ && count_phi) phi += (double)(pp.wts[1 + (dy != 0) + (dx != 0)] * rv);
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = t + j * NT, vr = v / TCc, vc = v - vr * TCc;
-      const int sidx = (vr + 1) * HC + vc + 1;
-      float up = 0.f, dn = 0.f;
-#pragma unroll
-      for (int o = 0; o < 9; ++o) {
-        const int dy = o / 3 - 1, dx = o % 3 - 1;
-        const float w = pp.wts[1 + (dy != 0) + (dx != 0)];
-        if (lower_is_output) up += w * pz[o][sidx];
-        dn += w * pz[o][sidx - (dy * HC + dx)];
+    if (x_pos >= 0) {
+      const int dy = x_o / 3 - 1, dx = x_o % 3 - 1;
+      const int a = x_pos / H, b = x_pos - a * H;
+      if (in_tile(a + dy, b + dx)) {
+        const int q = x_pos + dy * H + dx;
+        float rp, rv;
+        qggmrf<false>(inside(x_pos) && inside(q) ? src[x_pos] - dst[q] : 0.f, pp, rp, rv);
+        fz[x_o][x_pos] = rp;
       }
-      if (lower_is_output) acc[j] += up;
-      accn[j] -= dn;
     }
-    __syncthreads();
+  };
+  // acc gets the plane-z voxel's forward sums; the return value is the plane-(z+1) voxel's
+  // backward sum at the same (row, column)
+  auto cross_gather = [&](float& acc, bool to_acc) {
+    float up = 0.f, dn = 0.f;
+#pragma unroll
+    for (int o = 0; o < 9; ++o) {
+      const int dy = o / 3 - 1, dx = o % 3 - 1;
+      const float w = (dy != 0 && dx != 0) ? w3 : ((dy != 0 || dx != 0) ? w2 : w1);
+      up += w * fz[o][s];
+      dn += w * fz[o][s - dy * H - dx];
+    }
+    if (to_acc) acc += up;
+    return -dn;
   };
 
+  int cur = 0;
+  load_plane(z0, Y[cur]);
+  float acc = 0.f, accn = 0.f;
   if (NB == 26 && z0 > 0) {
-    cross(bp, bc, false, false);
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      acc[j] = accn[j];
-      accn[j] = 0.f;
-    }
+    load_plane(z0 - 1, Y[1 - cur]);
+    __syncthreads();
+    cross_fwd(Y[1 - cur], Y[cur], false);
+    __syncthreads();
+    acc = cross_gather(acc, false);
   }
+  __syncthreads();
 
   for (int z = z0; z < z1; ++z) {
     const bool has_next = NB == 26 && z + 1 < nz;
     if (NB != 26 && z > z0) {
-      // in-plane prior: no plane carries over, reload the current one (the previous step's
-      // readers finished at its last barrier)
-      load_plane(z, ybuf[bc]);
+      load_plane(z, Y[cur]);
       __syncthreads();
     }
-    if (has_next) load_plane(z + 1, ybuf[bn]);
-    // in-plane pairs: offsets (0,1), (1,-1), (1,0), (1,1) in (dy, dx)
-    for (int e = t; e < 4 * HA; e += NT) {
-      const int o = e / HA, pidx = e - o * HA;
-      const int dy = o == 0 ? 0 : 1, dx = o == 0 ? 1 : o - 2;
-      const int hr = pidx / HC, hc = pidx - hr * HC;
-      const int qr = hr + dy, qc = hc + dx;
-      float val = 0.f;
-      if (qr < HR && qc >= 0 && qc < HC && inside(hr, hc) && inside(qr, qc)) {
-        float rv = 0.f;
-        qggmrf<OBJ>(ybuf[bc][pidx] - ybuf[bc][qr * HC + qc], pp, val, rv);
-        if (OBJ && owned(hr, hc)) phi += (double)(pp.wts[1 + (dy != 0 && dx != 0)] * rv);
-      }
-      pin[o][pidx] = val;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = t + j * NT, vr = v / TCc, vc = v - vr * TCc;
-      const int sidx = (vr + 1) * HC + vc + 1;
-      float a = 0.f;
+    if (has_next) load_plane(z + 1, Y[1 - cur]);
+    // in-plane forward pairs
+    {
+      const float* y = Y[cur];
+      const float ys = y[s];
+      constexpr int offs[4] = {1, H - 1, H, H + 1};
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
-        const int dy = o == 0 ? 0 : 1, dx = o == 0 ? 1 : o - 2;
-        const float w = pp.wts[1 + (dy != 0 && dx != 0)];
-        a += w * (pin[o][sidx] - pin[o][sidx - (dy * HC + dx)]);
+        float rp, rv = 0.f;
+        const bool v = own_in && inside(s + offs[o]);
+        qggmrf<OBJ>(v ? ys - y[s + offs[o]] : 0.f, pp, rp, rv);
+        fin[o][s] = rp;
+        if (OBJ) phi += (double)(((o == 0 || o == 2) ? w1 : w2) * rv);
       }
-      acc[j] += a;
+      if (in_pos >= 0) {
+        const int o = in_o;
+        const int dy = o == 0 ? 0 : 1, dx = o == 0 ? 1 : o - 2;
+        const int a = in_pos / H, b = in_pos - a * H;
+        if (in_tile(a + dy, b + dx)) {
+          const int q = in_pos + dy * H + dx;
+          float rp, rv;
+          qggmrf<false>(inside(in_pos) && inside(q) ? y[in_pos] - y[q] : 0.f, pp, rp, rv);
+          fin[o][in_pos] = rp;
+        }
+      }
     }
     __syncthreads();
-    if (has_next) cross(bc, bn, true, true);
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = t + j * NT, vr = v / TCc, vc = v - vr * TCc;
-      const int r = r0 + vr, c = c0 + vc;
-      if (r < N && c < N) gp[((idx_t)z * N + r) * N + c] = pp.beta * acc[j];
-      acc[j] = accn[j];
-      accn[j] = 0.f;
+    {
+      constexpr int offs[4] = {1, H - 1, H, H + 1};
+      acc += w1 * (fin[0][s] - fin[0][s - offs[0]]) + w2 * (fin[1][s] - fin[1][s - offs[1]]) +
+             w1 * (fin[2][s] - fin[2][s - offs[2]]) + w2 * (fin[3][s] - fin[3][s - offs[3]]);
     }
-    if (NB == 26) {
-      const int tmp = bp;
-      bp = bc;
-      bc = bn;
-      bn = tmp;
+    if (has_next) {
+      cross_fwd(Y[cur], Y[1 - cur], true);
+      __syncthreads();
+      accn = cross_gather(acc, true);
     }
+    const int r = r0 + tr, c = c0 + tc;
+    if (r < N && c < N) gp[((idx_t)z * N + r) * N + c] = pp.beta * acc;
+    acc = accn;
+    accn = 0.f;
+    if (NB == 26) cur = 1 - cur;
+    __syncthreads();
   }
   if (partials) {
     const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum4<NT>(phi, 0.0, 0.0, 0.0, partials + (idx_t)bid * 4, sred);
+    block_sum4<PR_NT>(phi, 0.0, 0.0, 0.0, partials + (idx_t)bid * 4, sred);
   }
 }
 
@@ -1019,13 +1041,13 @@ hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj, const
 }
 
 int prior_blocks(int N, int nz) {
-  return ((N + PR_TC - 1) / PR_TC) * ((N + PR_TR - 1) / PR_TR) * ((nz + PR_ZC - 1) / PR_ZC);
+  return ((N + PR_T - 1) / PR_T) * ((N + PR_T - 1) / PR_T) * ((nz + PR_ZC - 1) / PR_ZC);
 }
 
 hipError_t launch_prior(int mode, int neighbours, bool with_obj, const float* xk,
                         const float* xkm1, const double* scal, float* gp, double* partials,
                         int N, int nz, const PriorParams& pp, hipStream_t st) {
-  const dim3 grid((N + PR_TC - 1) / PR_TC, (N + PR_TR - 1) / PR_TR, (nz + PR_ZC - 1) / PR_ZC);
+  const dim3 grid((N + PR_T - 1) / PR_T, (N + PR_T - 1) / PR_T, (nz + PR_ZC - 1) / PR_ZC);
   const int fista = mode == MODE_FISTA ? 1 : 0;
   double* part = with_obj ? partials : nullptr;
   if (neighbours == 26) {

@@ -526,7 +526,7 @@ tomo_status validate_geom(const tomo_geometry_t* g) {
   if (!(g->T > 0.0) || !std::isfinite(g->T)) return fail(nullptr, TOMO_ERR_INVALID_ARG, "T must be > 0");
   if (g->neighbours != 8 && g->neighbours != 26)
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "neighbours must be 8 or 26");
-  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_SPLIT_PRIOR))
+  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_FUSED_PRIOR))
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "unknown flag bits 0x%x", g->flags);
   if (g->angles)
     for (int i = 0; i < g->n_angles; ++i)
@@ -564,7 +564,7 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->nz = geom->n_slices;
   p->use_graphs = (geom->flags & TOMO_FLAG_NO_GRAPH) == 0;
-  p->fused_prior = (geom->flags & TOMO_FLAG_SPLIT_PRIOR) == 0;
+  p->fused_prior = (geom->flags & TOMO_FLAG_FUSED_PRIOR) != 0;
   p->n_levels = geom->n_levels == 0 ? 1 : geom->n_levels;
   if (p->g.kb_width == 0) p->g.kb_width = 6;
   if (p->g.kb_oversamp == 0.0) p->g.kb_oversamp = 2.0;

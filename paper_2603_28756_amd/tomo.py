@@ -25,7 +25,7 @@ STATUS_NAMES = {
 INIT_FBP, INIT_ZERO, INIT_USER = 0, 1, 2
 T_ROWS_FWD, T_COLS_CONV, T_ROWS_INV, T_FINALIZE, T_BACKPROJECT, T_PSF, T_PRIOR, T_COUNT = range(8)
 FLAG_NO_GRAPH = 1
-FLAG_SPLIT_PRIOR = 2
+FLAG_FUSED_PRIOR = 2
 
 
 class TomoError(RuntimeError):
@@ -150,7 +150,7 @@ class Plan:
                  kb_beta: float = 0.0, beta: float = 0.01, p: float = 1.2, q: float = 2.0,
                  sigma: float = 0.1, T: float = 1.0, neighbours: int = 26, stream=None,
                  device: Optional[torch.device] = None, graphs: bool = True,
-                 split_prior: bool = False):
+                 fused_prior: bool = False):
         lib = load_library()
         self._lib = lib
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
@@ -166,7 +166,7 @@ class Plan:
         g.kb_oversamp, g.kb_beta = kb_oversamp, kb_beta
         g.beta, g.p, g.q, g.sigma, g.T = beta, p, q, sigma, T
         g.neighbours = neighbours
-        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_SPLIT_PRIOR if split_prior else 0)
+        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_FUSED_PRIOR if fused_prior else 0)
         self.geometry = g
         self.n, self.n_slices, self.n_angles, self.n_det = n, n_slices, n_angles, n_det
         self.n_levels = n_levels

@@ -73,13 +73,13 @@ def test_backproject_and_fbp(n, nz, na, nd, c):
     assert rel_l2(to_np(out), ofbp.fbp(sino, geom)) < 1e-5
 
 
-@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("nb", [8, 26])
 @pytest.mark.parametrize("n,nz,na,nd,c", CASES[:3] + [(48, 37, 20, 68, None)])
-def test_gradient_and_objective(n, nz, na, nd, c, nb, split):
+def test_gradient_and_objective(n, nz, na, nd, c, nb, fused):
     # nz = 37 spans three z-chunks of the prior kernel with a ragged last chunk
     sino, ang, center, phantom = problem(n, nz, na, nd, seed=n + 3, center=c)
-    plan = make_plan(n, nz, ang, nd, center=center, neighbours=nb, split_prior=split)
+    plan = make_plan(n, nz, ang, nd, center=center, neighbours=nb, fused_prior=fused)
     plan.precompute_psf()
     geom = oracle_geom(n, ang, nd, center)
     _, _, P = plan.level_dims(0)
@@ -109,13 +109,13 @@ def _oracle_fista(sino, ang, nd, center, n, nb, iters, init, restart=True, L=Non
     return solver.fista(prob, x0, iters, L=L, restart=restart)
 
 
-@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("n,nz,na,nd,nb,iters", [(64, 3, 45, 92, 26, 20), (128, 1, 90, 182, 8, 20),
                                                  (100, 2, 30, 142, 26, 12)])
-def test_reconstruct_parity(n, nz, na, nd, nb, iters, split):
+def test_reconstruct_parity(n, nz, na, nd, nb, iters, fused):
     from paper_2603_28756_amd import tomo
     sino, ang, center, _ = problem(n, nz, na, nd, seed=n + 4)
-    plan = make_plan(n, nz, ang, nd, neighbours=nb, split_prior=split)
+    plan = make_plan(n, nz, ang, nd, neighbours=nb, fused_prior=fused)
     x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
     hist = torch.zeros(iters, dtype=torch.float64, device=dev())
     rs = torch.zeros(iters, dtype=torch.int32, device=dev())
