@@ -12,8 +12,12 @@ value = N^2 * n_slices * iterations / (seconds per step)   [gradient voxel-updat
 
 roofline: the kernel class with the largest share of the step is timed live with
 HIP events on the plan's stream over a second pass of the same steps (events turn
-off graph replay, so they are kept out of the timed region); its algorithmic bytes
-per launch divided by its mean launch time is compared with the 8 TB/s HBM peak.
+off graph replay, so they are kept out of the timed region).  For the transform
+passes its algorithmic bytes per launch over its mean launch time are compared with
+the 8 TB/s HBM peak; the prior kernel is bound by vector-ALU issue, so its
+algorithmic VALU lane-operations per launch (transcendentals weighted 4, their issue
+cost) over its mean launch time are compared with the chip's non-packed FP32 VALU
+issue rate, 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
 cpu_baseline: the FP64 oracle's own iteration (Toeplitz product by numpy FFTs,
 prior, update) timed on a bounded slab of the same volume on the host.
 """
@@ -31,8 +35,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-operations per second, packed FP32 unused
 CLASS_NAMES = ["rows_fwd", "cols_conv", "rows_inv", "finalize", "backproject", "psf", "prior"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_volume_64x512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_volume_64x512.txt")
 
 
 def kernel_source_hash() -> str:
@@ -44,6 +49,40 @@ def kernel_source_hash() -> str:
                 h.update(name.encode())
                 h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def read_traffic(cls: str):
+    """HBM bytes per launch of kernel class `cls` from the counter summary, or None.
+
+    The summary holds a `source_hash` line and `kernel <class> ... bytes_per_launch <B>`
+    lines; it is ignored when the kernel sources changed after the counters were taken.
+    """
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src, found = None, {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            tok = line.split()
+            if len(tok) >= 2 and tok[0] == "source_hash":
+                src = tok[1]
+            elif len(tok) >= 2 and tok[0] == "kernel" and "bytes_per_launch" in tok:
+                found[tok[1]] = float(tok[tok.index("bytes_per_launch") + 1])
+    if src != kernel_source_hash():
+        return None
+    return found.get(cls)
+
+
+def prior_lane_ops(n: int, nz: int, neighbours: int) -> float:
+    """Algorithmic VALU lane-operations of one prior launch.
+
+    Per neighbour pair (each evaluated once): the difference, fma, 1 + w, fma and two
+    multiplies (6 full-rate operations) and log2, exp2, reciprocal (3 quarter-rate
+    transcendentals, weight 4) = 18; each pair value enters both of its voxels with one
+    fused multiply-add = 2.  26 neighbours: 13 pairs per voxel -> 260 per voxel;
+    8 neighbours: 4 pairs -> 80.
+    """
+    pairs = 13 if neighbours == 26 else 4
+    return float(n) * n * nz * pairs * (18 + 2)
 
 
 def algorithmic_bytes(cls: str, n: int, nz: int, P: int, fused_prior: bool = False) -> float:
@@ -103,13 +142,17 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fused-prior", action="store_true",
                     help="evaluate the prior in the inverse-row epilogue (comparison variant)")
+    ap.add_argument("--concurrent-prior", action="store_true",
+                    help="launch the prior kernel on its own stream beside the row/column passes")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile schedule instead of the autotuned one")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="only run a plain device copy of known size (counter calibration)")
+                    help="only run a plain copy kernel of known size (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard along the slice axis, see the design notes)", file=sys.stderr)
+              "(this build runs the one-GPU share of a slice-axis sharding)", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -121,7 +164,7 @@ def main() -> int:
         a = torch.ones(n, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(5):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)   # one elementwise kernel: reads a, writes b
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": 4 * n, "copy_calib_bytes_written": 4 * n}))
         return 0
@@ -138,7 +181,8 @@ def main() -> int:
     plan = tomo.Plan(wl.n, wl.n_slices, wl.n_angles, wl.n_det, angles=list(pr["angles"]),
                      n_levels=wl.levels, kb_width=wl.kb_width, kb_oversamp=wl.kb_oversamp,
                      beta=wl.beta, p=wl.p, q=wl.q, sigma=wl.sigma, T=wl.T,
-                     neighbours=wl.neighbours, device=dev, fused_prior=args.fused_prior)
+                     neighbours=wl.neighbours, device=dev, fused_prior=args.fused_prior,
+                     concurrent_prior=args.concurrent_prior)
     x = torch.empty((wl.n_slices, wl.n, wl.n), dtype=torch.float32, device=dev)
     _, _, P = plan.level_dims(wl.levels - 1)
 
@@ -146,6 +190,12 @@ def main() -> int:
         plan.precompute_psf()
         plan.reconstruct(sino, x, iters, init=tomo.INIT_FBP, stats=False)
 
+    # plan-time tile choice (once per geometry, outside the timed steps)
+    tiles, tune_s = None, 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tiles = plan.autotune(reps=5)
+        tune_s = time.perf_counter() - t0
     for _ in range(args.warmup):
         step()
     # one step with every class timed: the breakdown, and which class dominates
@@ -188,13 +238,21 @@ def main() -> int:
                   for i in iter_classes + [tomo.T_FINALIZE]) / total_iters
     name = CLASS_NAMES[hot]
     alg = algorithmic_bytes(name, wl.n, wl.n_slices, P, args.fused_prior)
-    achieved = alg / (mean_hot_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("source_hash") == kernel_source_hash() and name in tr.get("kernels", {}):
-            traffic = tr["kernels"][name]["bytes_per_launch"]
+    traffic = read_traffic(name)
+    if name == "prior":
+        ops = prior_lane_ops(wl.n, wl.n_slices, wl.neighbours)
+        achieved = ops / (mean_hot_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                "unit": "T lane-ops/s (VALU, FP32 non-packed)", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": traffic, "algorithmic_lane_ops_per_launch": ops,
+                "algorithmic_bytes_per_launch": alg,
+                "hbm_frac": alg / (mean_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    else:
+        achieved = alg / (mean_hot_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": alg}
+    roof.update({"mean_launch_ms": mean_hot_ms, "launches_timed": cnt_hot[hot]})
     out = {
         "metric": "gradient voxel-updates/s",
         "value": value,
@@ -213,18 +271,18 @@ def main() -> int:
             "n_det": wl.n_det, "iterations": iters, "pad": P, "kb_width": wl.kb_width,
             "kb_oversamp": wl.kb_oversamp, "neighbours": wl.neighbours, "noise": wl.noise,
             "step": "PSF spectrum + step constant precompute, R*g, FBP start, iterations",
-            "prior": "fused epilogue" if args.fused_prior else "pair-shared kernel",
+            "tiles": ([{k: t[k] for k in ("fwd_pairs", "col_tile", "inv_pairs")} for t in tiles]
+                      if tiles else "default"),
+            "prior": ("fused epilogue" if args.fused_prior else
+                      "pair-shared kernel, " + ("own stream beside the row/column passes"
+                                                if args.concurrent_prior else "in sequence")),
         },
-        "roofline": {
-            "bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg, "mean_launch_ms": mean_hot_ms,
-            "launches_timed": cnt_hot[hot],
-        },
+        "roofline": roof,
         "iteration_ms": iter_ms,
         "iteration_voxel_updates_per_s": wl.n * wl.n * wl.n_slices / (iter_ms * 1e-3),
         "effective_hbm_frac_20B": 20.0 * wl.n * wl.n * wl.n_slices / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "breakdown_one_step": breakdown,
+        "autotune": {"seconds": tune_s, "levels": tiles} if tiles else None,
         "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_cpu_baseline:

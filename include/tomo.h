@@ -105,6 +105,10 @@ typedef struct {
  * separate z-marching kernel that evaluates each neighbour pair once.  Same results to
  * rounding; the default is faster on gfx950. */
 #define TOMO_FLAG_FUSED_PRIOR 2u
+/* tomo_geometry_t.flags: launch the separate prior kernel on an internal stream beside the
+ * forward-row and column passes instead of in sequence on the plan's stream.  Same results;
+ * a few percent faster at large sizes, but kernel durations then overlap. */
+#define TOMO_FLAG_CONCURRENT_PRIOR 4u
 
 /* Options of tomo_reconstruct(). */
 typedef struct {
@@ -232,6 +236,39 @@ tomo_status tomo_timing_enable(tomo_plan plan, uint32_t class_mask);
  * (host int64[TOMO_T_COUNT]); either pointer may be NULL.  Accumulators keep
  * running.  Errors: INVALID_ARG, HIP. */
 tomo_status tomo_timing_read(tomo_plan plan, double* total_ms, int64_t* counts);
+
+/* ---- tile autotuner ------------------------------------------------------------------- */
+/* Tile schedule of the three Toeplitz passes of one level (Sec. 2.1, Eq. 9: the padded 2D
+ * FFT product is carried out as row transforms, column transforms with the PSF-spectrum
+ * multiply, and inverse row transforms).  Each pass has variants 0, 1 (default), 2 that
+ * halve, keep or double the row pairs (passes R, R') or columns (pass C) one workgroup
+ * transforms, within 1024 threads and 128 KiB of LDS; FFT sizes below 256 have the default
+ * only.  All variants give bit-identical transforms. */
+typedef struct {
+  int32_t rows_fwd;       /* variant 0..2 of pass R                                        */
+  int32_t cols_conv;      /* variant 0..2 of pass C                                        */
+  int32_t rows_inv;       /* variant 0..2 of pass R' (separate-prior path only; the fused
+                             and power-iteration forms use the default)                    */
+  int32_t fwd_pairs;      /* out: row pairs per workgroup of pass R                        */
+  int32_t col_tile;       /* out: columns per workgroup of pass C                          */
+  int32_t inv_pairs;      /* out: row pairs per workgroup of pass R'                       */
+  float ms[3][3];         /* out (tomo_autotune): mean launch time [pass R, C, R'][variant]
+                             in milliseconds on the plan's full volume                     */
+} tomo_tiles_t;
+
+/* Time every variant of the three passes on each level at the plan's own shapes (reps
+ * launches each, after one warm-up; reps <= 0 means 5) and keep the fastest per pass and
+ * level.  Synchronises the plan's stream; overwrites the iterate and spectrum scratch of the
+ * workspace (not b, the PSF spectrum or the step constants), so call it before
+ * tomo_reconstruct or between reconstructions.  Captured iteration graphs are rebuilt on the
+ * next reconstruction.  chosen: nullable host [n_levels], receives the choice and timings.
+ * Errors: INVALID_ARG, NO_WORKSPACE, HIP. */
+tomo_status tomo_autotune(tomo_plan plan, int32_t reps, tomo_tiles_t* chosen);
+
+/* Set (tiles != NULL: host [n_levels], only the three variant fields are read) and/or read
+ * back (out != NULL: host [n_levels], variant and shape fields written, ms zero) the tile
+ * schedule.  Errors: INVALID_ARG (variant outside 0..2). */
+tomo_status tomo_tiles(tomo_plan plan, const tomo_tiles_t* tiles, tomo_tiles_t* out);
 
 /* ---- batches of independent problems ------------------------------------------------- */
 typedef struct tomo_batch_s* tomo_batch;

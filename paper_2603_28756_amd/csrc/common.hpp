@@ -33,6 +33,9 @@ struct PriorParams {
   float c_grad;      // (T sigma)^(p-q) / sigma^p  (rho' prefactor for q = 2 form)
   float c_val;       // (T sigma)^p / (p sigma^p)  (rho prefactor)
   float qm1;         // q - 1
+  float lw0;         // (q - p) log2(1 / (T sigma))
+  float qop_m1;      // q / p - 1
+  float c_val2;      // c_val / (T sigma)^2  (rho = c_val2 d^2 / (1 + w))
   float wts[4];      // neighbour weights: [0] unused, [1] axis, [2] face diagonal, [3] body diagonal
   int neighbours;    // 8 or 26
   int quadratic;     // 1 when p == q (w == 1)

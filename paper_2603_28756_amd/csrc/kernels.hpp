@@ -30,21 +30,25 @@ enum ScalarSlot {
 enum Mode { MODE_FISTA = 0, MODE_GRAD = 1, MODE_POWER = 2 };
 
 // Launch geometry of the hot-path kernels for a padded size P (used for partials sizing).
-int rows_inv_rows_per_block(int P);
+// v: tile variant 0, 1 (default), 2 of a transform pass.
+int rows_inv_rows_per_block(int P, int v);
 int cols_tile_width(int P);
+// Resolved block shapes of the variants: row pairs of pass R, columns of pass C, row pairs
+// of pass R' (0 for an unsupported P).
+void tile_shapes(int P, int v_fwd, int v_cc, int v_inv, int* fwd, int* cc, int* inv);
 
 // ---- hot path (float32 data, float64 reductions) --------------------------------------
 // Pass R: y = x_k + mu (x_k - x_{k-1}) (or scale * x_k in power mode) -> row R2C -> S1.
-hipError_t launch_rows_fwd(int P, int mode, const float* xk, const float* xkm1,
+hipError_t launch_rows_fwd(int P, int v, int mode, const float* xk, const float* xkm1,
                            const double* scal, cpx<float>* S1, const cpx<float>* tw,
                            int N, int nz, hipStream_t st);
 // Pass C: column FFT, x FK, inverse column FFT, keep N rows: S1 -> S2.
-hipError_t launch_cols_conv(int P, const cpx<float>* S1, cpx<float>* S2, const float* fk,
+hipError_t launch_cols_conv(int P, int v, const cpx<float>* S1, cpx<float>* S2, const float* fk,
                             const float* fkn, const cpx<float>* tw, int N, int nz, hipStream_t st);
 // Pass R': inverse row C2R + crop + epilogue; writes partial sums [nblocks][4].
 // gpv: prior gradient beta grad Phi(y) from launch_prior, or NULL to evaluate the prior
 // inside the epilogue over a neighbour tile.
-hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj,
+hipError_t launch_rows_inv(int P, int v, int mode, int neighbours, bool with_obj,
                            const cpx<float>* S2, const float* xk, const float* xkm1,
                            const float* b, const float* gpv, float* out, double* partials,
                            const double* scal, const cpx<float>* tw, int N, int nz,

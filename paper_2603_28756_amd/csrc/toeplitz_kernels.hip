@@ -38,6 +38,17 @@ TOMO_DEV void qggmrf(float d, const PriorParams& pp, float& rp, float& rv) {
   if constexpr (VAL) rv = pp.c_val * t * t * r;
 }
 
+// Workgroups of a launch are handed to the 8 XCDs round-robin by linear id, and each XCD has
+// its own L2.  This maps the hardware id to a logical tile id so that every XCD receives one
+// contiguous range of logical ids (a bijection on [0, total)); tiles that share cache lines
+// are then adjacent in logical order and meet in one L2.
+TOMO_DEV int xcd_contiguous(int hw, int total) {
+  constexpr int X = 8;
+  const int q = total / X, r = total % X;
+  const int xcd = hw % X, local = hw / X;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 template <int NT>
 TOMO_DEV void block_sum4(double a0, double a1, double a2, double a3, double* out, double* sbuf) {
   double a[4] = {a0, a1, a2, a3};
@@ -229,9 +240,15 @@ template <int P, int TC>
 __global__ void __launch_bounds__(TC * (P / kE))
 cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
                  const float* __restrict__ fk, const float* __restrict__ fkn,
-                 const cpx<float>* __restrict__ tw, int N) {
+                 const cpx<float>* __restrict__ tw, int N, int nz) {
   __shared__ __align__(16) unsigned char smem[cols_conv_lds<P, TC>()];
-  cols_conv_body<P, TC>(smem, blockIdx.x, blockIdx.y, S1, S2, fk, fkn, tw, N);
+  // Logical order: groups of G adjacent column tiles (which share 128-byte lines of S1, S2
+  // and F K), then slices, then the group index; each XCD thus works on one band of columns
+  // across all slices and holds only that band of F K in its L2.
+  constexpr int NCG = (P / 2) / TC, G = NCG < 8 ? NCG : 8;
+  const int lam = xcd_contiguous(blockIdx.x, NCG * nz);
+  const int rest = lam / G;
+  cols_conv_body<P, TC>(smem, (rest / nz) * G + lam % G, rest % nz, S1, S2, fk, fkn, tw, N);
 }
 
 // ---------------------------------------------------------------------------- prior (3D)
@@ -239,76 +256,132 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
 // once.  A block owns a 16 x 16 column of voxels (one per thread) and marches through 16
 // slices, keeping planes z and z+1 (with a one-voxel halo) in LDS.  Per plane each thread
 // evaluates the forward pairs of its voxel: 4 in-plane offsets (0,1), (1,-1), (1,0), (1,1)
-// and the 9 offsets into plane z+1; threads 0..67 also evaluate, for one halo position each,
-// the forward pairs that end inside the tile.  A pair's value enters its first voxel with +
-// and its second with - (rho' is odd).  With OBJ the block also sums rho over the forward
-// pairs of its own voxels.
+// and the 9 offsets into plane z+1; the forward pairs that start on the halo ring and end
+// inside the tile are spread over the threads as one (position, offset) item each.  A pair's
+// value enters its first voxel with + and its second with - (rho' is odd).  Tiles whose halo
+// ring lies inside the volume run without bounds tests; on the others a pair that leaves the
+// volume gets difference 0 (rho'(0) = 0) from validity masks computed once per thread.  With
+// OBJ the block also sums rho over the forward pairs of its own voxels.
 constexpr int PR_T = 16, PR_ZC = 16, PR_NT = 256;
 constexpr int PR_H = PR_T + 2, PR_HA = PR_H * PR_H;
 
-template <int NB, bool OBJ>
-__global__ void __launch_bounds__(PR_NT)
-prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
-             const double* __restrict__ scal, float* __restrict__ gp,
-             double* __restrict__ partials, int N, int nz, int mode_fista, PriorParams pp) {
-  constexpr int H = PR_H, HA = PR_HA;
-  __shared__ float Y[2][HA];
-  __shared__ float fin[4][HA];
-  __shared__ float fz[NB == 26 ? 9 : 1][HA];
-  __shared__ double sred[(PR_NT / 64) * 4];
+// rho'(d) / c_grad and rho(d) for q = 2, arranged for few instructions:
+//   rho'(d) / c_grad = d r (1 + (q/p - 1) r),  r = 1 / (1 + w),
+//   w = (|d| / (T sigma))^(q-p) = exp2((q-p) log2|d| + lw0),  rho(d) = c_val2 d^2 r.
+// d = 0 gives w = 0 and a zero derivative and value.  QUAD: p = q, w = 1.
+template <bool VAL, bool QUAD>
+TOMO_DEV void qggmrf_unit(float d, const PriorParams& pp, float& rp, float& rv) {
+  float r = 0.5f;
+  if constexpr (!QUAD) {
+    const float w =
+        __builtin_amdgcn_exp2f(__builtin_fmaf(pp.qmp, __builtin_amdgcn_logf(fabsf(d)), pp.lw0));
+    r = __builtin_amdgcn_rcpf(1.f + w);
+  }
+  rp = d * r * __builtin_fmaf(pp.qop_m1, r, 1.f);
+  if constexpr (VAL) rv = pp.c_val2 * d * d * r;
+}
 
+template <int NB>
+struct PriorLds {
+  float Y[2][PR_HA];
+  float fin[4][PR_HA];
+  float fz[NB == 26 ? 9 : 1][PR_HA];
+  double sred[(PR_NT / 64) * 4];
+};
+
+template <int NB, bool OBJ, bool QUAD, bool EDGE>
+TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
+                         const float* __restrict__ xkm1, float* __restrict__ gp,
+                         double* __restrict__ part_out, int N, int nz, int c0, int r0, int z0,
+                         float mu, bool fista, const PriorParams& pp) {
+  constexpr int H = PR_H, HA = PR_HA;
   const int t = threadIdx.x;
   const int tr = t >> 4, tc = t & 15;
   const int s = (tr + 1) * H + tc + 1;  // own position (halo coordinates)
-  const int c0 = blockIdx.x * PR_T, r0 = blockIdx.y * PR_T, z0 = blockIdx.z * PR_ZC;
   const int z1 = min(z0 + PR_ZC, nz);
-  const float mu = mode_fista ? (float)scal[SC_MU] : 0.f;
-  const float w1 = pp.wts[1], w2 = pp.wts[2], w3 = pp.wts[3];
+  // neighbour weights with beta and the rho' prefactor folded in
+  const float kb = pp.beta * pp.c_grad;
+  const float w1 = kb * pp.wts[1], w2 = kb * pp.wts[2], w3 = kb * pp.wts[3];
 
-  // Halo work: the forward pairs that start on the halo ring and end inside the tile, as one
-  // item (position, offset) per thread.  In-plane items (98): top row x offsets
-  // (1,-1),(1,0),(1,1); left column x (0,1),(1,1); right column x (1,-1); two corners.
-  // Cross-plane items (196): top row x dy=+1, bottom row x dy=-1, left column x dx=+1,
-  // right column x dx=-1 (3 each), four corners.  Items whose end leaves the tile are idle.
-  int in_pos = -1, in_o = 0;
-  if (t < 48) { in_pos = (t / 3 + 1); in_o = 1 + t % 3; }                   // top row
-  else if (t < 80) { const int k = t - 48; in_pos = (k / 2 + 1) * H; in_o = (k & 1) ? 3 : 0; }
-  else if (t < 96) { in_pos = (t - 80 + 1) * H + H - 1; in_o = 1; }           // right column
-  else if (t == 96) { in_pos = 0; in_o = 3; }                                  // corner (0,0)
-  else if (t == 97) { in_pos = H - 1; in_o = 1; }                              // corner (0,H-1)
-  int x_pos = -1, x_o = 0;
-  {
-    const int k = t;
-    if (k < 48) { x_pos = k / 3 + 1; x_o = 6 + k % 3; }                          // top: dy=+1
-    else if (k < 96) { x_pos = (H - 1) * H + (k - 48) / 3 + 1; x_o = (k - 48) % 3; }   // bottom
-    else if (k < 144) { x_pos = ((k - 96) / 3 + 1) * H; x_o = 3 * ((k - 96) % 3) + 2; } // left
-    else if (k < 192) { x_pos = ((k - 144) / 3 + 1) * H + H - 1; x_o = 3 * ((k - 144) % 3); }
-    else if (k == 192) { x_pos = 0; x_o = 8; }
-    else if (k == 193) { x_pos = H - 1; x_o = 6; }
-    else if (k == 194) { x_pos = (H - 1) * H; x_o = 2; }
-    else if (k == 195) { x_pos = (H - 1) * H + H - 1; x_o = 0; }
-  }
-
-  auto inside = [&](int pos) {
-    const int a = pos / H, b = pos - a * H;
+  auto inside = [&](int a, int b) {  // halo coordinates -> inside the volume
     const int r = r0 - 1 + a, c = c0 - 1 + b;
     return r >= 0 && r < N && c >= 0 && c < N;
   };
   auto in_tile = [&](int a, int b) { return a >= 1 && a <= PR_T && b >= 1 && b <= PR_T; };
-  auto load_plane = [&](int z, float* dst) {
-    for (int e = t; e < HA; e += PR_NT) {
-      const int a = e / H, b = e - a * H;
-      const int r = r0 - 1 + a, c = c0 - 1 + b;
-      float v = 0.f;
-      if (r >= 0 && r < N && c >= 0 && c < N) {
-        const idx_t o = ((idx_t)z * N + r) * N + c;
-        const float xa = xk[o];
-        v = mode_fista ? xa + mu * (xa - xkm1[o]) : xa;
-      }
-      dst[e] = v;
+
+  // Halo items.  In-plane (98): top row x offsets (1,-1),(1,0),(1,1); left column x (0,1),
+  // (1,1); right column x (1,-1); two corners.  Cross-plane (196): top row x dy=+1, bottom row
+  // x dy=-1, left column x dx=+1, right column x dx=-1 (3 each), four corners.  Items whose
+  // end leaves the tile are idle.
+  int in_pos = -1, in_o = 0;
+  if (t < 48) { in_pos = t / 3 + 1; in_o = 1 + t % 3; }
+  else if (t < 80) { const int k = t - 48; in_pos = (k / 2 + 1) * H; in_o = (k & 1) ? 3 : 0; }
+  else if (t < 96) { in_pos = (t - 80 + 1) * H + H - 1; in_o = 1; }
+  else if (t == 96) { in_pos = 0; in_o = 3; }
+  else if (t == 97) { in_pos = H - 1; in_o = 1; }
+  int x_pos = -1, x_o = 0;
+  if (t < 48) { x_pos = t / 3 + 1; x_o = 6 + t % 3; }
+  else if (t < 96) { x_pos = (H - 1) * H + (t - 48) / 3 + 1; x_o = (t - 48) % 3; }
+  else if (t < 144) { x_pos = ((t - 96) / 3 + 1) * H; x_o = 3 * ((t - 96) % 3) + 2; }
+  else if (t < 192) { x_pos = ((t - 144) / 3 + 1) * H + H - 1; x_o = 3 * ((t - 144) % 3); }
+  else if (t == 192) { x_pos = 0; x_o = 8; }
+  else if (t == 193) { x_pos = H - 1; x_o = 6; }
+  else if (t == 194) { x_pos = (H - 1) * H; x_o = 2; }
+  else if (t == 195) { x_pos = (H - 1) * H + H - 1; x_o = 0; }
+  // resolve the items once: partner position, activity and validity
+  int in_q = 0, x_q = 0;
+  bool in_act = false, x_act = false, in_ok = true, x_ok = true;
+  if (in_pos >= 0) {
+    const int dy = in_o == 0 ? 0 : 1, dx = in_o == 0 ? 1 : in_o - 2;
+    const int a = in_pos / H, b = in_pos - (in_pos / H) * H;
+    in_act = in_tile(a + dy, b + dx);
+    in_q = in_pos + dy * H + dx;
+    if constexpr (EDGE) in_ok = inside(a, b) && inside(a + dy, b + dx);
+  }
+  if (x_pos >= 0) {
+    const int dy = x_o / 3 - 1, dx = x_o % 3 - 1;
+    const int a = x_pos / H, b = x_pos - (x_pos / H) * H;
+    x_act = in_tile(a + dy, b + dx);
+    x_q = x_pos + dy * H + dx;
+    if constexpr (EDGE) x_ok = inside(a, b) && inside(a + dy, b + dx);
+  }
+  // own-pair validity: bits 0..3 in-plane offsets, bits 4..12 offsets into the next plane
+  uint32_t m_own = 0x1fffu;
+  if constexpr (EDGE) {
+    m_own = 0;
+    const int a = tr + 1, b = tc + 1;
+    if (inside(a, b)) {
+      m_own |= (uint32_t)inside(a, b + 1) | ((uint32_t)inside(a + 1, b - 1) << 1) |
+               ((uint32_t)inside(a + 1, b) << 2) | ((uint32_t)inside(a + 1, b + 1) << 3);
+#pragma unroll
+      for (int o = 0; o < 9; ++o) m_own |= (uint32_t)inside(a + o / 3 - 1, b + o % 3 - 1) << (4 + o);
     }
+  }
+  // plane loads: the (at most two) halo positions of this thread, as in-plane offsets
+  const int e1 = t + PR_NT;
+  const bool has_e1 = e1 < HA;
+  int g0, g1 = 0;
+  bool v0 = true, v1 = true;
+  {
+    const int a = t / H, b = t - a * H;
+    g0 = (r0 - 1 + a) * N + (c0 - 1 + b);
+    if constexpr (EDGE) v0 = inside(a, b);
+    if (has_e1) {
+      const int a1 = e1 / H, b1 = e1 - a1 * H;
+      g1 = (r0 - 1 + a1) * N + (c0 - 1 + b1);
+      if constexpr (EDGE) v1 = inside(a1, b1);
+    }
+  }
+  const idx_t plane = (idx_t)N * N;
+  auto yval = [&](idx_t o) {
+    const float xa = xk[o];
+    return fista ? xa + mu * (xa - xkm1[o]) : xa;
   };
-  const bool own_in = inside(s);
+  auto load_plane = [&](int z, float* dst) {
+    const idx_t zb = (idx_t)z * plane;
+    dst[t] = v0 ? yval(zb + g0) : 0.f;
+    if (has_e1) dst[e1] = v1 ? yval(zb + g1) : 0.f;
+  };
   double phi = 0.0;
 
   // forward pairs from plane buffer `src` to plane buffer `dst` (9 offsets (dy, dx))
@@ -317,22 +390,17 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
       const int dy = o / 3 - 1, dx = o % 3 - 1;
-      const int q = s + dy * H + dx;
+      float d = ys - dst[s + dy * H + dx];
+      if constexpr (EDGE) d = (m_own >> (4 + o)) & 1u ? d : 0.f;
       float rp, rv = 0.f;
-      const bool v = own_in && inside(q);
-      qggmrf<OBJ>(v ? ys - dst[q] : 0.f, pp, rp, rv);
-      fz[o][s] = rp;
+      qggmrf_unit<OBJ, QUAD>(d, pp, rp, rv);
+      L.fz[o][s] = rp;
       if (OBJ && count_phi) phi += (double)(pp.wts[1 + (dy != 0) + (dx != 0)] * rv);
     }
-    if (x_pos >= 0) {
-      const int dy = x_o / 3 - 1, dx = x_o % 3 - 1;
-      const int a = x_pos / H, b = x_pos - a * H;
-      if (in_tile(a + dy, b + dx)) {
-        const int q = x_pos + dy * H + dx;
-        float rp, rv;
-        qggmrf<false>(inside(x_pos) && inside(q) ? src[x_pos] - dst[q] : 0.f, pp, rp, rv);
-        fz[x_o][x_pos] = rp;
-      }
+    if (x_act) {
+      float rp, rv;
+      qggmrf_unit<false, QUAD>(x_ok ? src[x_pos] - dst[x_q] : 0.f, pp, rp, rv);
+      L.fz[x_o][x_pos] = rp;
     }
   };
   // acc gets the plane-z voxel's forward sums; the return value is the plane-(z+1) voxel's
@@ -343,79 +411,88 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
     for (int o = 0; o < 9; ++o) {
       const int dy = o / 3 - 1, dx = o % 3 - 1;
       const float w = (dy != 0 && dx != 0) ? w3 : ((dy != 0 || dx != 0) ? w2 : w1);
-      up += w * fz[o][s];
-      dn += w * fz[o][s - dy * H - dx];
+      up = __builtin_fmaf(w, L.fz[o][s], up);
+      dn = __builtin_fmaf(w, L.fz[o][s - dy * H - dx], dn);
     }
     if (to_acc) acc += up;
     return -dn;
   };
 
   int cur = 0;
-  load_plane(z0, Y[cur]);
+  load_plane(z0, L.Y[cur]);
   float acc = 0.f, accn = 0.f;
   if (NB == 26 && z0 > 0) {
-    load_plane(z0 - 1, Y[1 - cur]);
+    load_plane(z0 - 1, L.Y[1 - cur]);
     __syncthreads();
-    cross_fwd(Y[1 - cur], Y[cur], false);
+    cross_fwd(L.Y[1 - cur], L.Y[cur], false);
     __syncthreads();
     acc = cross_gather(acc, false);
   }
   __syncthreads();
 
+  constexpr int offs[4] = {1, H - 1, H, H + 1};
   for (int z = z0; z < z1; ++z) {
     const bool has_next = NB == 26 && z + 1 < nz;
     if (NB != 26 && z > z0) {
-      load_plane(z, Y[cur]);
+      load_plane(z, L.Y[cur]);
       __syncthreads();
     }
-    if (has_next) load_plane(z + 1, Y[1 - cur]);
-    // in-plane forward pairs
+    if (has_next) load_plane(z + 1, L.Y[1 - cur]);
     {
-      const float* y = Y[cur];
+      const float* y = L.Y[cur];
       const float ys = y[s];
-      constexpr int offs[4] = {1, H - 1, H, H + 1};
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
+        float d = ys - y[s + offs[o]];
+        if constexpr (EDGE) d = (m_own >> o) & 1u ? d : 0.f;
         float rp, rv = 0.f;
-        const bool v = own_in && inside(s + offs[o]);
-        qggmrf<OBJ>(v ? ys - y[s + offs[o]] : 0.f, pp, rp, rv);
-        fin[o][s] = rp;
-        if (OBJ) phi += (double)(((o == 0 || o == 2) ? w1 : w2) * rv);
+        qggmrf_unit<OBJ, QUAD>(d, pp, rp, rv);
+        L.fin[o][s] = rp;
+        if (OBJ) phi += (double)(((o == 0 || o == 2) ? pp.wts[1] : pp.wts[2]) * rv);
       }
-      if (in_pos >= 0) {
-        const int o = in_o;
-        const int dy = o == 0 ? 0 : 1, dx = o == 0 ? 1 : o - 2;
-        const int a = in_pos / H, b = in_pos - a * H;
-        if (in_tile(a + dy, b + dx)) {
-          const int q = in_pos + dy * H + dx;
-          float rp, rv;
-          qggmrf<false>(inside(in_pos) && inside(q) ? y[in_pos] - y[q] : 0.f, pp, rp, rv);
-          fin[o][in_pos] = rp;
-        }
+      if (in_act) {
+        float rp, rv;
+        qggmrf_unit<false, QUAD>(in_ok ? y[in_pos] - y[in_q] : 0.f, pp, rp, rv);
+        L.fin[in_o][in_pos] = rp;
       }
     }
     __syncthreads();
-    {
-      constexpr int offs[4] = {1, H - 1, H, H + 1};
-      acc += w1 * (fin[0][s] - fin[0][s - offs[0]]) + w2 * (fin[1][s] - fin[1][s - offs[1]]) +
-             w1 * (fin[2][s] - fin[2][s - offs[2]]) + w2 * (fin[3][s] - fin[3][s - offs[3]]);
-    }
+    acc += w1 * (L.fin[0][s] - L.fin[0][s - offs[0]]) + w2 * (L.fin[1][s] - L.fin[1][s - offs[1]]) +
+           w1 * (L.fin[2][s] - L.fin[2][s - offs[2]]) + w2 * (L.fin[3][s] - L.fin[3][s - offs[3]]);
     if (has_next) {
-      cross_fwd(Y[cur], Y[1 - cur], true);
+      cross_fwd(L.Y[cur], L.Y[1 - cur], true);
       __syncthreads();
       accn = cross_gather(acc, true);
     }
     const int r = r0 + tr, c = c0 + tc;
-    if (r < N && c < N) gp[((idx_t)z * N + r) * N + c] = pp.beta * acc;
+    if (!EDGE || (r < N && c < N)) gp[((idx_t)z * N + r) * N + c] = acc;
     acc = accn;
     accn = 0.f;
     if (NB == 26) cur = 1 - cur;
     __syncthreads();
   }
-  if (partials) {
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum4<PR_NT>(phi, 0.0, 0.0, 0.0, partials + (idx_t)bid * 4, sred);
-  }
+  if (part_out) block_sum4<PR_NT>(phi, 0.0, 0.0, 0.0, part_out, L.sred);
+}
+
+template <int NB, bool OBJ, bool QUAD>
+__global__ void __launch_bounds__(PR_NT)
+prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
+             const double* __restrict__ scal, float* __restrict__ gp,
+             double* __restrict__ partials, int N, int nz, int mode_fista, PriorParams pp) {
+  __shared__ PriorLds<NB> L;
+  // logical tile: x fastest, then y, then the slice chunk; XCD-contiguous so that tiles
+  // sharing halo lines meet in one L2
+  const int ntx = (N + PR_T - 1) / PR_T, nty = ntx;
+  const int lam = xcd_contiguous(blockIdx.x, ntx * nty * ((nz + PR_ZC - 1) / PR_ZC));
+  const int c0 = (lam % ntx) * PR_T, r0 = ((lam / ntx) % nty) * PR_T;
+  const int z0 = (lam / (ntx * nty)) * PR_ZC;
+  const float mu = mode_fista ? (float)scal[SC_MU] : 0.f;
+  double* part = partials ? partials + (idx_t)blockIdx.x * 4 : nullptr;
+  const bool interior = r0 >= 1 && c0 >= 1 && r0 + PR_T + 1 <= N && c0 + PR_T + 1 <= N;
+  if (interior)
+    prior_tile<NB, OBJ, QUAD, false>(L, xk, xkm1, gp, part, N, nz, c0, r0, z0, mu, mode_fista != 0, pp);
+  else
+    prior_tile<NB, OBJ, QUAD, true>(L, xk, xkm1, gp, part, N, nz, c0, r0, z0, mu, mode_fista != 0, pp);
 }
 
 // --------------------------------------------------------------------------------- pass R'
@@ -459,6 +536,30 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
   const int t = threadIdx.x, pr = t / TPF, q = t - pr * TPF;
   const int r1 = r0 + 2 * pr;
   const bool active = r1 < N;
+
+  // Operands of the point-wise epilogue (split-prior path), fetched before the transform so
+  // that their latency overlaps it: thread t owns the float4 groups t + u NT, u < 4, of the
+  // RB x N tile (RB N / 4 <= 4 NT since P >= 2N; otherwise the scalar loop below runs).
+  constexpr bool PF = MODE != MODE_POWER && NB == 0;
+  static_assert(LY::A_BYTES % 16 == 0 && H % 4 == 0, "float4 tile access");
+  const int nq = N >> 2;
+  const bool vec = PF && (N & 3) == 0 && RB * nq <= 4 * NT;
+  float4 pa[4], pb[4], pbv[4], pg[4];
+  if constexpr (PF) {
+    if (vec) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = t + u * NT, ry = e / nq, row = r0 + ry;
+        if (e < RB * nq && row < N) {
+          const idx_t o = ((idx_t)z * N + row) * N + 4 * (e - ry * nq);
+          pa[u] = *reinterpret_cast<const float4*>(xk + o);
+          if constexpr (MODE == MODE_FISTA) pb[u] = *reinterpret_cast<const float4*>(xkm1 + o);
+          pbv[u] = *reinterpret_cast<const float4*>(bvec + o);
+          pg[u] = *reinterpret_cast<const float4*>(gpv + o);
+        }
+      }
+    }
+  }
 
   // ---- C2R of rows r1, r1+1 packed as Z = X1 + i X2 over the full length P
   {
@@ -504,7 +605,44 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
   __syncthreads();
 
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  if constexpr (MODE != MODE_POWER && NB == 0) {
+  if constexpr (PF) {
+   if (vec) {
+    // prior gradient precomputed by prior_kernel: point-wise epilogue on the prefetched groups
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = t + u * NT, ry = e / nq, row = r0 + ry;
+      if (e < RB * nq && row < N) {
+        const int col = 4 * (e - ry * nq);
+        const idx_t o = ((idx_t)z * N + row) * N + col;
+        const float4 ty4 = *reinterpret_cast<const float4*>(tyt + ry * H + col);
+        const float av[4] = {pa[u].x, pa[u].y, pa[u].z, pa[u].w};
+        const float bv[4] = {pbv[u].x, pbv[u].y, pbv[u].z, pbv[u].w};
+        const float gv[4] = {pg[u].x, pg[u].y, pg[u].z, pg[u].w};
+        const float tv[4] = {ty4.x, ty4.y, ty4.z, ty4.w};
+        float km1[4] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE == MODE_FISTA) {
+          km1[0] = pb[u].x; km1[1] = pb[u].y; km1[2] = pb[u].z; km1[3] = pb[u].w;
+        }
+        float res[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float a = av[k];
+          const float ys = (MODE == MODE_FISTA) ? a + mu * (a - km1[k]) : a;
+          const float g = tv[k] - bv[k] + gv[k];
+          if constexpr (MODE == MODE_FISTA) {
+            const float xn = ys - g * invL;
+            res[k] = xn;
+            acc3 += (double)(ys - xn) * (double)(xn - a);
+          } else {
+            res[k] = g;
+          }
+          acc0 += (double)ys * (double)tv[k];
+          acc1 += (double)ys * (double)bv[k];
+        }
+        *reinterpret_cast<float4*>(out + o) = make_float4(res[0], res[1], res[2], res[3]);
+      }
+    }
+   } else {
     // prior gradient precomputed by prior_kernel: point-wise epilogue, no neighbour tile
     for (int e = t; e < RB * N; e += NT) {
       const int ry = e / N, col = e - ry * N, row = r0 + ry;
@@ -526,6 +664,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
         acc1 += (double)ys * (double)bs;
       }
     }
+   }
   } else if constexpr (MODE == MODE_POWER) {
     for (int e = t; e < RB * N; e += NT) {
       const int ry = e / N, col = e - ry * N, row = r0 + ry;
@@ -891,10 +1030,33 @@ constexpr int col_tc(int P) {
   return tc;
 }
 
-template <int P>
-hipError_t rows_fwd_p(int mode, const float* xk, const float* xkm1, const double* scal,
-                      cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st) {
-  constexpr int PAIRS = fwd_pairs(P);
+// Tile variants of the three transform passes, chosen per plan level by the autotuner:
+// variant 0 halves, 1 keeps, 2 doubles the default number of row pairs (passes R, R') or
+// columns (pass C) per block, within 1024 threads and 128 KiB of LDS per block.  Transform
+// sizes below 256 have the default only.  Each row or column is transformed by the same code
+// whatever the grouping, so all variants give identical results.
+constexpr int kLdsCap = 128 * 1024;
+constexpr int vsel(int base, int v) { return v == 0 ? (base > 1 ? base / 2 : 1) : (v == 2 ? 2 * base : base); }
+constexpr int fwd_pairs_v(int P, int v) {
+  int x = P < 256 ? fwd_pairs(P) : vsel(fwd_pairs(P), v);
+  while (x > 1 && (x * (P / kE) > 1024 || x * (P + P / 16) * 8 > kLdsCap)) x /= 2;
+  return x;
+}
+constexpr int col_tc_v(int P, int v) {
+  int x = P < 256 ? col_tc(P) : vsel(col_tc(P), v);
+  while (x > 1 && (x * (P / kE) > 1024 || x * P * 8 > kLdsCap)) x /= 2;
+  return x;
+}
+constexpr int inv_pairs_v(int P, int v) {
+  int x = P < 256 ? inv_pairs(P) : vsel(inv_pairs(P), v);
+  while (x > 1 && (x * (P / kE) > 1024 || x * (P + P / 16) * 8 + x * P * 4 + 1024 > kLdsCap)) x /= 2;
+  return x;
+}
+
+template <int P, int V>
+hipError_t rows_fwd_pv(int mode, const float* xk, const float* xkm1, const double* scal,
+                       cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st) {
+  constexpr int PAIRS = fwd_pairs_v(P, V);
   constexpr int NT = PAIRS * fft::Plan<P, kE>::TPF;
   const int n_pairs = nz * (N / 2);
   const dim3 grid((n_pairs + PAIRS - 1) / PAIRS);
@@ -908,21 +1070,38 @@ hipError_t rows_fwd_p(int mode, const float* xk, const float* xkm1, const double
 }
 
 template <int P>
-hipError_t cols_conv_p(const cpx<float>* S1, cpx<float>* S2, const float* fk, const float* fkn,
-                       const cpx<float>* tw, int N, int nz, hipStream_t st) {
-  constexpr int TC = col_tc(P);
+hipError_t rows_fwd_p(int v, int mode, const float* xk, const float* xkm1, const double* scal,
+                      cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st) {
+  if (v == 0) return rows_fwd_pv<P, 0>(mode, xk, xkm1, scal, S1, tw, N, nz, st);
+  if (v == 2) return rows_fwd_pv<P, 2>(mode, xk, xkm1, scal, S1, tw, N, nz, st);
+  return rows_fwd_pv<P, 1>(mode, xk, xkm1, scal, S1, tw, N, nz, st);
+}
+
+template <int P, int V>
+hipError_t cols_conv_pv(const cpx<float>* S1, cpx<float>* S2, const float* fk, const float* fkn,
+                        const cpx<float>* tw, int N, int nz, hipStream_t st) {
+  constexpr int TC = col_tc_v(P, V);
   constexpr int NT = TC * fft::Plan<P, kE>::TPF;
-  const dim3 grid((P / 2) / TC, nz);
-  hipLaunchKernelGGL((cols_conv_kernel<P, TC>), grid, dim3(NT), 0, st, S1, S2, fk, fkn, tw, N);
+  const dim3 grid(((P / 2) / TC) * nz);
+  hipLaunchKernelGGL((cols_conv_kernel<P, TC>), grid, dim3(NT), 0, st, S1, S2, fk, fkn, tw, N,
+                     nz);
   return hipGetLastError();
 }
 
-template <int P, int MODE, int NB, bool OBJ>
+template <int P>
+hipError_t cols_conv_p(int v, const cpx<float>* S1, cpx<float>* S2, const float* fk,
+                       const float* fkn, const cpx<float>* tw, int N, int nz, hipStream_t st) {
+  if (v == 0) return cols_conv_pv<P, 0>(S1, S2, fk, fkn, tw, N, nz, st);
+  if (v == 2) return cols_conv_pv<P, 2>(S1, S2, fk, fkn, tw, N, nz, st);
+  return cols_conv_pv<P, 1>(S1, S2, fk, fkn, tw, N, nz, st);
+}
+
+template <int P, int MODE, int NB, bool OBJ, int V = 1>
 hipError_t rows_inv_launch(const cpx<float>* S2, const float* xk, const float* xkm1,
                            const float* b, const float* gpv, float* out, double* partials,
                            const double* scal, const cpx<float>* tw, int N, int nz,
                            const PriorParams& pp, int* nblocks, hipStream_t st) {
-  constexpr int PAIRS = inv_pairs(P);
+  constexpr int PAIRS = inv_pairs_v(P, V);
   constexpr int NT = PAIRS * fft::Plan<P, kE>::TPF;
   constexpr int RB = 2 * PAIRS;
   const int nb = nz * ((N + RB - 1) / RB);
@@ -933,18 +1112,28 @@ hipError_t rows_inv_launch(const cpx<float>* S2, const float* xk, const float* x
 }
 
 template <int P>
-hipError_t rows_inv_p(int mode, int nbh, bool obj, const cpx<float>* S2, const float* xk,
+hipError_t rows_inv_p(int v, int mode, int nbh, bool obj, const cpx<float>* S2, const float* xk,
                       const float* xkm1, const float* b, const float* gpv, float* out,
                       double* partials, const double* scal, const cpx<float>* tw, int N, int nz,
                       const PriorParams& pp, int* nblocks, hipStream_t st) {
 #define TOMO_INV(MODE, NB, OBJ)                                                                 \
   return rows_inv_launch<P, MODE, NB, OBJ>(S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, nz, \
                                            pp, nblocks, st)
+#define TOMO_INV_V(MODE, V)                                                                      \
+  return rows_inv_launch<P, MODE, 0, false, V>(S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, \
+                                               nz, pp, nblocks, st)
   if (mode == MODE_POWER) TOMO_INV(MODE_POWER, 8, false);
-  if (gpv) {  // prior gradient precomputed
-    if (mode == MODE_GRAD) TOMO_INV(MODE_GRAD, 0, false);
-    TOMO_INV(MODE_FISTA, 0, false);
+  if (gpv) {  // prior gradient precomputed: the tile variant applies
+    if (mode == MODE_GRAD) {
+      if (v == 0) TOMO_INV_V(MODE_GRAD, 0);
+      if (v == 2) TOMO_INV_V(MODE_GRAD, 2);
+      TOMO_INV_V(MODE_GRAD, 1);
+    }
+    if (v == 0) TOMO_INV_V(MODE_FISTA, 0);
+    if (v == 2) TOMO_INV_V(MODE_FISTA, 2);
+    TOMO_INV_V(MODE_FISTA, 1);
   }
+#undef TOMO_INV_V
   if (mode == MODE_GRAD) {
     if (nbh == 26) { if (obj) TOMO_INV(MODE_GRAD, 26, true); TOMO_INV(MODE_GRAD, 26, false); }
     if (obj) TOMO_INV(MODE_GRAD, 8, true);
@@ -958,18 +1147,31 @@ hipError_t rows_inv_p(int mode, int nbh, bool obj, const cpx<float>* S2, const f
 
 }  // namespace
 
-int rows_inv_rows_per_block(int P) {
+int rows_inv_rows_per_block(int P, int v) {
   switch (P) {
-    case 32: return 2 * inv_pairs(32);
-    case 64: return 2 * inv_pairs(64);
-    case 128: return 2 * inv_pairs(128);
-    case 256: return 2 * inv_pairs(256);
-    case 512: return 2 * inv_pairs(512);
-    case 1024: return 2 * inv_pairs(1024);
-    case 2048: return 2 * inv_pairs(2048);
-    case 4096: return 2 * inv_pairs(4096);
+    case 32: return 2 * inv_pairs_v(32, v);
+    case 64: return 2 * inv_pairs_v(64, v);
+    case 128: return 2 * inv_pairs_v(128, v);
+    case 256: return 2 * inv_pairs_v(256, v);
+    case 512: return 2 * inv_pairs_v(512, v);
+    case 1024: return 2 * inv_pairs_v(1024, v);
+    case 2048: return 2 * inv_pairs_v(2048, v);
+    case 4096: return 2 * inv_pairs_v(4096, v);
   }
   return 2;
+}
+
+void tile_shapes(int P, int v_fwd, int v_cc, int v_inv, int* fwd, int* cc, int* inv) {
+  *fwd = *cc = *inv = 0;
+  switch (P) {
+#define SHAPES(PP)                                                                          \
+    case PP:                                                                                \
+      *fwd = fwd_pairs_v(PP, v_fwd); *cc = col_tc_v(PP, v_cc); *inv = inv_pairs_v(PP, v_inv); \
+      break;
+    SHAPES(32) SHAPES(64) SHAPES(128) SHAPES(256) SHAPES(512) SHAPES(1024) SHAPES(2048)
+    SHAPES(4096)
+#undef SHAPES
+  }
 }
 
 int cols_tile_width(int P) { return col_tc(P); }
@@ -1012,29 +1214,30 @@ hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st) {
   }                                 \
   return hipErrorInvalidValue;
 
-hipError_t launch_rows_fwd(int P, int mode, const float* xk, const float* xkm1,
+hipError_t launch_rows_fwd(int P, int v, int mode, const float* xk, const float* xkm1,
                            const double* scal, cpx<float>* S1, const cpx<float>* tw, int N,
                            int nz, hipStream_t st) {
-#define CALL(PP) rows_fwd_p<PP>(mode, xk, xkm1, scal, S1, tw, N, nz, st)
+#define CALL(PP) rows_fwd_p<PP>(v, mode, xk, xkm1, scal, S1, tw, N, nz, st)
   TOMO_PSWITCH(CALL)
 #undef CALL
 }
 
-hipError_t launch_cols_conv(int P, const cpx<float>* S1, cpx<float>* S2, const float* fk,
+hipError_t launch_cols_conv(int P, int v, const cpx<float>* S1, cpx<float>* S2, const float* fk,
                             const float* fkn, const cpx<float>* tw, int N, int nz,
                             hipStream_t st) {
-#define CALL(PP) cols_conv_p<PP>(S1, S2, fk, fkn, tw, N, nz, st)
+#define CALL(PP) cols_conv_p<PP>(v, S1, S2, fk, fkn, tw, N, nz, st)
   TOMO_PSWITCH(CALL)
 #undef CALL
 }
 
-hipError_t launch_rows_inv(int P, int mode, int neighbours, bool with_obj, const cpx<float>* S2,
+hipError_t launch_rows_inv(int P, int v, int mode, int neighbours, bool with_obj,
+                           const cpx<float>* S2,
                            const float* xk, const float* xkm1, const float* b, const float* gpv,
                            float* out, double* partials, const double* scal,
                            const cpx<float>* tw, int N, int nz, const PriorParams& pp,
                            int* nblocks_out, hipStream_t st) {
 #define CALL(PP)                                                                              \
-  rows_inv_p<PP>(mode, neighbours, with_obj, S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, \
+  rows_inv_p<PP>(v, mode, neighbours, with_obj, S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, \
                  nz, pp, nblocks_out, st)
   TOMO_PSWITCH(CALL)
 #undef CALL
@@ -1044,27 +1247,31 @@ int prior_blocks(int N, int nz) {
   return ((N + PR_T - 1) / PR_T) * ((N + PR_T - 1) / PR_T) * ((nz + PR_ZC - 1) / PR_ZC);
 }
 
+template <int NB, bool OBJ, bool QUAD>
+void prior_launch(dim3 grid, hipStream_t st, const float* xk, const float* xkm1,
+                  const double* scal, float* gp, double* part, int N, int nz, int fista,
+                  const PriorParams& pp) {
+  hipLaunchKernelGGL((prior_kernel<NB, OBJ, QUAD>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
+                     part, N, nz, fista, pp);
+}
+
 hipError_t launch_prior(int mode, int neighbours, bool with_obj, const float* xk,
                         const float* xkm1, const double* scal, float* gp, double* partials,
                         int N, int nz, const PriorParams& pp, hipStream_t st) {
-  const dim3 grid((N + PR_T - 1) / PR_T, (N + PR_T - 1) / PR_T, (nz + PR_ZC - 1) / PR_ZC);
+  const dim3 grid(prior_blocks(N, nz));
   const int fista = mode == MODE_FISTA ? 1 : 0;
   double* part = with_obj ? partials : nullptr;
+  const bool quad = pp.quadratic != 0;
+#define PRIOR_CALL(NB, OBJ, QUAD) \
+  prior_launch<NB, OBJ, QUAD>(grid, st, xk, xkm1, scal, gp, part, N, nz, fista, pp)
   if (neighbours == 26) {
-    if (with_obj)
-      hipLaunchKernelGGL((prior_kernel<26, true>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
-                         part, N, nz, fista, pp);
-    else
-      hipLaunchKernelGGL((prior_kernel<26, false>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
-                         part, N, nz, fista, pp);
+    if (with_obj) { if (quad) PRIOR_CALL(26, true, true); else PRIOR_CALL(26, true, false); }
+    else { if (quad) PRIOR_CALL(26, false, true); else PRIOR_CALL(26, false, false); }
   } else {
-    if (with_obj)
-      hipLaunchKernelGGL((prior_kernel<8, true>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
-                         part, N, nz, fista, pp);
-    else
-      hipLaunchKernelGGL((prior_kernel<8, false>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
-                         part, N, nz, fista, pp);
+    if (with_obj) { if (quad) PRIOR_CALL(8, true, true); else PRIOR_CALL(8, true, false); }
+    else { if (quad) PRIOR_CALL(8, false, true); else PRIOR_CALL(8, false, false); }
   }
+#undef PRIOR_CALL
   return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct Level {
   double L = 0.0, lambda = 0.0;
   size_t off_fk = 0, off_fkn = 0, off_b = 0;
   size_t off_rowptr = 0, off_cidx = 0, off_cw = 0, off_deapod = 0;  // gridding lists
+  int v_fwd = 1, v_cc = 1, v_inv = 1;  // tile variants of passes R, C, R'
 };
 
 }  // namespace
@@ -78,6 +79,10 @@ struct tomo_plan_s {
   // iteration graphs: replayed on an internal stream ordered against `stream` by events
   hipStream_t gstream = nullptr;
   hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  // prior kernel on its own stream, concurrent with the forward-row and column passes
+  bool concurrent_prior = false;
+  hipStream_t pstream = nullptr;
+  hipEvent_t pev_fork = nullptr, pev_join = nullptr;
   struct GraphKey { int level, ik, nz; double* hist; int32_t* rhist; bool obj; };
   struct GraphEnt { GraphKey key; hipGraphExec_t exec; };
   std::vector<GraphEnt> graphs;
@@ -143,7 +148,7 @@ void layout(tomo_plan p) {
   p->off_scal = take(SC_COUNT * sizeof(double));
   size_t maxblocks = 512;
   for (const Level& l : p->lv) {
-    const int rb = rows_inv_rows_per_block(l.P);
+    const int rb = rows_inv_rows_per_block(l.P, 0);  // smallest variant: most blocks
     const size_t nb = (size_t)p->nz * ((l.n + rb - 1) / rb);
     if (nb > maxblocks) maxblocks = nb;
   }
@@ -218,16 +223,27 @@ hipEvent_t take_event(tomo_plan p) {
 }
 
 // Opens a timed region for kernel class `cls` when it is enabled; returns the pending index.
-int tbegin(tomo_plan p, int cls) {
+int tbegin(tomo_plan p, int cls, hipStream_t s) {
   if (!(p->tmask & (1u << cls))) return -1;
   hipEvent_t a = take_event(p), b = take_event(p);
   if (!a || !b) return -1;
-  hipEventRecord(a, p->stream);
+  hipEventRecord(a, s);
   p->pending.push_back({a, b, cls});
   return (int)p->pending.size() - 1;
 }
-void tend(tomo_plan p, int idx) {
-  if (idx >= 0) hipEventRecord(p->pending[idx].b, p->stream);
+int tbegin(tomo_plan p, int cls) { return tbegin(p, cls, p->stream); }
+void tend(tomo_plan p, int idx, hipStream_t s) {
+  if (idx >= 0) hipEventRecord(p->pending[idx].b, s);
+}
+void tend(tomo_plan p, int idx) { tend(p, idx, p->stream); }
+
+// Stream and events of the concurrent prior kernel, created once per plan (before any capture).
+tomo_status ensure_prior_stream(tomo_plan p) {
+  if (!p->concurrent_prior || p->fused_prior || p->pstream) return TOMO_OK;
+  HIPCHK(p, hipStreamCreateWithFlags(&p->pstream, hipStreamNonBlocking));
+  HIPCHK(p, hipEventCreateWithFlags(&p->pev_fork, hipEventDisableTiming));
+  HIPCHK(p, hipEventCreateWithFlags(&p->pev_join, hipEventDisableTiming));
+  return TOMO_OK;
 }
 
 tomo_status tresolve(tomo_plan p) {
@@ -342,7 +358,9 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
 
 // One application of the Toeplitz passes on level l (and, outside power mode, of the prior
 // kernel unless the fused-prior epilogue is selected).  *nprior receives the number of prior
-// partial sums the finalize must add (0 when none).
+// partial sums the finalize must add (0 when none).  The prior kernel reads only x_k, x_{k-1}
+// and mu, so with the concurrent flag it runs on its own stream beside the forward-row and
+// column passes; the inverse-row pass, the only reader of its output, waits for it.
 tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const float* xk,
                             const float* xkm1, const float* b, float* out, bool obj,
                             int* nblocks, int* nprior = nullptr) {
@@ -351,23 +369,36 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
   cpx<float>* S2 = p->S2(l);
   const float* gpv = nullptr;
   if (nprior) *nprior = 0;
+  const bool conc = mode != MODE_POWER && !p->fused_prior && p->concurrent_prior;
   if (mode != MODE_POWER && !p->fused_prior) {
-    const int tp = tbegin(p, TOMO_T_PRIOR);
+    hipStream_t ps = st;
+    if (conc) {
+      tomo_status s = ensure_prior_stream(p);
+      if (s != TOMO_OK) return s;
+      ps = p->pstream;
+      HIPCHK(p, hipEventRecord(p->pev_fork, st));
+      HIPCHK(p, hipStreamWaitEvent(ps, p->pev_fork, 0));
+    }
+    const int tp = tbegin(p, TOMO_T_PRIOR, ps);
     HIPCHK(p, launch_prior(mode, p->g.neighbours, obj, xk, xkm1, p->scal(), p->at<float>(p->off_gp),
-                           p->at<double>(p->off_ppartials), l.n, nz, p->pp, st));
-    tend(p, tp);
+                           p->at<double>(p->off_ppartials), l.n, nz, p->pp, ps));
+    tend(p, tp, ps);
+    if (conc) HIPCHK(p, hipEventRecord(p->pev_join, ps));
     gpv = p->at<float>(p->off_gp);
     if (nprior && obj) *nprior = prior_blocks(l.n, nz);
   }
-  int ti = tbegin(p, TOMO_T_ROWS_FWD);
-  HIPCHK(p, launch_rows_fwd(l.P, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz, st));
+  // per-class timing covers the iteration and gradient launches, not the power iteration
+  const bool timed = mode != MODE_POWER;
+  int ti = timed ? tbegin(p, TOMO_T_ROWS_FWD) : -1;
+  HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz, st));
   tend(p, ti);
-  ti = tbegin(p, TOMO_T_COLS_CONV);
-  HIPCHK(p, launch_cols_conv(l.P, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
+  ti = timed ? tbegin(p, TOMO_T_COLS_CONV) : -1;
+  HIPCHK(p, launch_cols_conv(l.P, l.v_cc, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
                              p->tw32(l.P), l.n, nz, st));
   tend(p, ti);
-  ti = tbegin(p, TOMO_T_ROWS_INV);
-  HIPCHK(p, launch_rows_inv(l.P, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
+  if (conc) HIPCHK(p, hipStreamWaitEvent(st, p->pev_join, 0));
+  ti = timed ? tbegin(p, TOMO_T_ROWS_INV) : -1;
+  HIPCHK(p, launch_rows_inv(l.P, l.v_inv, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
                             p->partials(), p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks, st));
   tend(p, ti);
   return TOMO_OK;
@@ -463,6 +494,7 @@ tomo_status get_graph(tomo_plan p, int level, int ik, int ikm1, int inext, const
     HIPCHK(p, hipEventCreateWithFlags(&p->gev_out, hipEventDisableTiming));
   }
   const Level& l = p->lv[level];
+  if (tomo_status ps = ensure_prior_stream(p); ps != TOMO_OK) return ps;
   hipGraph_t graph = nullptr;
   HIPCHK(p, hipStreamBeginCapture(p->gstream, hipStreamCaptureModeRelaxed));
   tomo_status s = TOMO_OK;
@@ -526,7 +558,7 @@ tomo_status validate_geom(const tomo_geometry_t* g) {
   if (!(g->T > 0.0) || !std::isfinite(g->T)) return fail(nullptr, TOMO_ERR_INVALID_ARG, "T must be > 0");
   if (g->neighbours != 8 && g->neighbours != 26)
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "neighbours must be 8 or 26");
-  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_FUSED_PRIOR))
+  if (g->flags & ~(uint32_t)(TOMO_FLAG_NO_GRAPH | TOMO_FLAG_FUSED_PRIOR | TOMO_FLAG_CONCURRENT_PRIOR))
     return fail(nullptr, TOMO_ERR_INVALID_ARG, "unknown flag bits 0x%x", g->flags);
   if (g->angles)
     for (int i = 0; i < g->n_angles; ++i)
@@ -565,6 +597,7 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   p->nz = geom->n_slices;
   p->use_graphs = (geom->flags & TOMO_FLAG_NO_GRAPH) == 0;
   p->fused_prior = (geom->flags & TOMO_FLAG_FUSED_PRIOR) != 0;
+  p->concurrent_prior = (geom->flags & TOMO_FLAG_CONCURRENT_PRIOR) != 0;
   p->n_levels = geom->n_levels == 0 ? 1 : geom->n_levels;
   if (p->g.kb_width == 0) p->g.kb_width = 6;
   if (p->g.kb_oversamp == 0.0) p->g.kb_oversamp = 2.0;
@@ -610,6 +643,9 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   pp.c_grad = (float)(std::pow(T * sg, pe - q) / std::pow(sg, pe));
   pp.c_val = (float)(std::pow(T * sg, pe) / (pe * std::pow(sg, pe)));
   pp.qm1 = (float)(q - 1.0);
+  pp.lw0 = (float)((q - pe) * std::log2(1.0 / (T * sg)));
+  pp.qop_m1 = (float)(q / pe - 1.0);
+  pp.c_val2 = (float)(std::pow(T * sg, pe) / (pe * std::pow(sg, pe)) / ((T * sg) * (T * sg)));
   const double r1 = 1.0, r2 = 1.0 / std::sqrt(2.0), r3 = 1.0 / std::sqrt(3.0);
   const double sum = geom->neighbours == 26 ? 6 * r1 + 12 * r2 + 8 * r3 : 4 * r1 + 4 * r2;
   pp.wts[0] = 0.f;
@@ -1151,6 +1187,122 @@ tomo_status tomo_timing_read(tomo_plan p, double* total_ms, int64_t* counts) {
   return TOMO_OK;
 }
 
+namespace {
+void fill_tiles(const Level& l, tomo_tiles_t* o) {
+  o->rows_fwd = l.v_fwd;
+  o->cols_conv = l.v_cc;
+  o->rows_inv = l.v_inv;
+  tile_shapes(l.P, l.v_fwd, l.v_cc, l.v_inv, &o->fwd_pairs, &o->col_tile, &o->inv_pairs);
+}
+void drop_graphs(tomo_plan p) {
+  if (p->graphs.empty()) return;
+  if (p->gstream) hipStreamSynchronize(p->gstream);
+  for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+}
+}  // namespace
+
+tomo_status tomo_tiles(tomo_plan p, const tomo_tiles_t* tiles, tomo_tiles_t* out) {
+  if (!p) return fail(nullptr, TOMO_ERR_INVALID_ARG, "plan is NULL");
+  if (tiles) {
+    for (int i = 0; i < p->n_levels; ++i) {
+      const tomo_tiles_t& t = tiles[i];
+      if (t.rows_fwd < 0 || t.rows_fwd > 2 || t.cols_conv < 0 || t.cols_conv > 2 ||
+          t.rows_inv < 0 || t.rows_inv > 2)
+        return fail(p, TOMO_ERR_INVALID_ARG, "tile variant of level %d outside 0..2", i);
+    }
+    drop_graphs(p);
+    for (int i = 0; i < p->n_levels; ++i) {
+      p->lv[i].v_fwd = tiles[i].rows_fwd;
+      p->lv[i].v_cc = tiles[i].cols_conv;
+      p->lv[i].v_inv = tiles[i].rows_inv;
+    }
+  }
+  if (out)
+    for (int i = 0; i < p->n_levels; ++i) {
+      std::memset(&out[i], 0, sizeof out[i]);
+      fill_tiles(p->lv[i], &out[i]);
+    }
+  return TOMO_OK;
+}
+
+tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
+  if (!p) return fail(nullptr, TOMO_ERR_INVALID_ARG, "plan is NULL");
+  if (reps > 1000) return fail(p, TOMO_ERR_INVALID_ARG, "reps = %d too large", reps);
+  if (reps <= 0) reps = 5;
+  if (tomo_status s = check_ws(p); s != TOMO_OK) return s;
+  hipStream_t st = p->stream;
+  drop_graphs(p);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(p, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(p, TOMO_ERR_HIP, "event create failed");
+  }
+  tomo_status s = TOMO_OK;
+  for (int li = 0; li < p->n_levels && s == TOMO_OK; ++li) {
+    Level& l = p->lv[li];
+    const idx_t vol = (idx_t)p->nz * l.n * l.n;
+    float* x = p->xbuf(0);
+    float* bb = p->xbuf(1);
+    float* out = p->xbuf(2);
+    float* gp = p->at<float>(p->off_gp);
+    cpx<float>* S1 = p->S1();
+    cpx<float>* S2 = p->S2(l);
+    const float* fk = p->at<float>(l.off_fk);
+    const float* fkn = p->at<float>(l.off_fkn);
+    // defined inputs: the timings do not depend on the values
+    if (launch_set_scalars(p->scal(), SC_MU, 1, nullptr, 0.0, st) != hipSuccess ||
+        launch_fill(x, vol, 1.0f, st) != hipSuccess || launch_fill(bb, vol, 0.5f, st) != hipSuccess ||
+        launch_fill(gp, vol, 0.0f, st) != hipSuccess) {
+      s = fail(p, TOMO_ERR_HIP, "autotune fill failed");
+      break;
+    }
+    float ms[3][3] = {};
+    for (int pass = 0; pass < 3 && s == TOMO_OK; ++pass) {
+      for (int v = 0; v < 3 && s == TOMO_OK; ++v) {
+        auto launch = [&]() -> hipError_t {
+          int nb = 0;
+          if (pass == 0)
+            return launch_rows_fwd(l.P, v, MODE_FISTA, x, x, p->scal(), S1, p->tw32(l.P), l.n,
+                                   p->nz, st);
+          if (pass == 1)
+            return launch_cols_conv(l.P, v, S1, S2, fk, fkn, p->tw32(l.P), l.n, p->nz, st);
+          return launch_rows_inv(l.P, v, MODE_GRAD, p->g.neighbours, false, S2, x, x, bb, gp, out,
+                                 p->partials(), p->scal(), p->tw32(l.P), l.n, p->nz, p->pp, &nb, st);
+        };
+        hipError_t e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) s = fail(p, TOMO_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+        ms[pass][v] = t / reps;
+      }
+    }
+    if (s != TOMO_OK) break;
+    auto best = [&](int pass) {
+      int b = 1;  // the default wins ties
+      for (int v = 0; v < 3; ++v)
+        if (ms[pass][v] < ms[pass][b]) b = v;
+      return b;
+    };
+    l.v_fwd = best(0);
+    l.v_cc = best(1);
+    l.v_inv = best(2);
+    if (chosen) {
+      std::memset(&chosen[li], 0, sizeof chosen[li]);
+      fill_tiles(l, &chosen[li]);
+      std::memcpy(chosen[li].ms, ms, sizeof ms);
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return s;
+}
+
 tomo_status tomo_plan_destroy(tomo_plan p) {
   if (!p) return TOMO_OK;
   if (!p->pending.empty()) hipStreamSynchronize(p->stream);
@@ -1164,6 +1316,12 @@ tomo_status tomo_plan_destroy(tomo_plan p) {
     hipStreamSynchronize(p->gstream);
     hipStreamDestroy(p->gstream);
   }
+  if (p->pstream) {
+    hipStreamSynchronize(p->pstream);
+    hipStreamDestroy(p->pstream);
+  }
+  if (p->pev_fork) hipEventDestroy(p->pev_fork);
+  if (p->pev_join) hipEventDestroy(p->pev_join);
   if (p->gev_in) hipEventDestroy(p->gev_in);
   if (p->gev_out) hipEventDestroy(p->gev_out);
   delete p;

@@ -26,6 +26,7 @@ INIT_FBP, INIT_ZERO, INIT_USER = 0, 1, 2
 T_ROWS_FWD, T_COLS_CONV, T_ROWS_INV, T_FINALIZE, T_BACKPROJECT, T_PSF, T_PRIOR, T_COUNT = range(8)
 FLAG_NO_GRAPH = 1
 FLAG_FUSED_PRIOR = 2
+FLAG_CONCURRENT_PRIOR = 4
 
 
 class TomoError(RuntimeError):
@@ -66,6 +67,17 @@ class BatchStats(ctypes.Structure):
                 ("wait_timeouts", ctypes.c_int32)]
 
 
+class Tiles(ctypes.Structure):
+    _fields_ = [("rows_fwd", ctypes.c_int32), ("cols_conv", ctypes.c_int32), ("rows_inv", ctypes.c_int32),
+                ("fwd_pairs", ctypes.c_int32), ("col_tile", ctypes.c_int32), ("inv_pairs", ctypes.c_int32),
+                ("ms", (ctypes.c_float * 3) * 3)]
+
+    def as_dict(self) -> dict:
+        return {"rows_fwd": self.rows_fwd, "cols_conv": self.cols_conv, "rows_inv": self.rows_inv,
+                "fwd_pairs": self.fwd_pairs, "col_tile": self.col_tile, "inv_pairs": self.inv_pairs,
+                "ms": [[float(self.ms[i][j]) for j in range(3)] for i in range(3)]}
+
+
 EXPORTS = {
     "tomo_plan_create": ([ctypes.POINTER(Geometry), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "tomo_plan_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -85,6 +97,8 @@ EXPORTS = {
     "tomo_timing_enable": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
     "tomo_timing_read": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
                          ctypes.c_int),
+    "tomo_autotune": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Tiles)], ctypes.c_int),
+    "tomo_tiles": ([ctypes.c_void_p, ctypes.POINTER(Tiles), ctypes.POINTER(Tiles)], ctypes.c_int),
     "tomo_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "tomo_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -150,7 +164,7 @@ class Plan:
                  kb_beta: float = 0.0, beta: float = 0.01, p: float = 1.2, q: float = 2.0,
                  sigma: float = 0.1, T: float = 1.0, neighbours: int = 26, stream=None,
                  device: Optional[torch.device] = None, graphs: bool = True,
-                 fused_prior: bool = False):
+                 fused_prior: bool = False, concurrent_prior: bool = False):
         lib = load_library()
         self._lib = lib
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
@@ -166,7 +180,8 @@ class Plan:
         g.kb_oversamp, g.kb_beta = kb_oversamp, kb_beta
         g.beta, g.p, g.q, g.sigma, g.T = beta, p, q, sigma, T
         g.neighbours = neighbours
-        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_FUSED_PRIOR if fused_prior else 0)
+        g.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_FUSED_PRIOR if fused_prior else 0) | (
+            FLAG_CONCURRENT_PRIOR if concurrent_prior else 0)
         self.geometry = g
         self.n, self.n_slices, self.n_angles, self.n_det = n, n_slices, n_angles, n_det
         self.n_levels = n_levels
@@ -248,6 +263,24 @@ class Plan:
         cnt = (ctypes.c_int64 * T_COUNT)()
         _check(self._lib.tomo_timing_read(self._h, ms, cnt), self._h)
         return list(ms), list(cnt)
+
+    def autotune(self, reps: int = 5) -> list:
+        """Time the tile variants of the three passes per level and keep the fastest."""
+        out = (Tiles * self.n_levels)()
+        _check(self._lib.tomo_autotune(self._h, reps, out), self._h)
+        return [t.as_dict() for t in out]
+
+    def tiles(self, set_to: Optional[Sequence[dict]] = None) -> list:
+        """Set (list of {rows_fwd, cols_conv, rows_inv} per level) and return the schedule."""
+        arg = None
+        if set_to is not None:
+            arg = (Tiles * self.n_levels)()
+            for i, d in enumerate(set_to):
+                arg[i].rows_fwd, arg[i].cols_conv, arg[i].rows_inv = (
+                    int(d["rows_fwd"]), int(d["cols_conv"]), int(d["rows_inv"]))
+        out = (Tiles * self.n_levels)()
+        _check(self._lib.tomo_tiles(self._h, arg, out), self._h)
+        return [t.as_dict() for t in out]
 
     def level_dims(self, level: int):
         n, nd, pad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -43,11 +43,13 @@ def oracle_geom(n, angles, n_det, center=None):
 
 
 def make_plan(n, nz, angles, n_det, center=None, neighbours=26, beta=0.01, p=1.2, sigma=0.1,
-              T=1.0, kb_width=8, n_levels=1, pad=0, graphs=True, fused_prior=False):
+              T=1.0, kb_width=8, n_levels=1, pad=0, graphs=True, fused_prior=False,
+              concurrent_prior=False):
     from paper_2603_28756_amd import tomo
     return tomo.Plan(n, nz, len(angles), n_det, angles=list(angles), center=center, pad=pad,
                      n_levels=n_levels, kb_width=kb_width, beta=beta, p=p, sigma=sigma, T=T,
-                     neighbours=neighbours, graphs=graphs, fused_prior=fused_prior)
+                     neighbours=neighbours, graphs=graphs, fused_prior=fused_prior,
+                     concurrent_prior=concurrent_prior)
 
 
 def oracle_prior(neighbours=26, p=1.2, sigma=0.1, T=1.0):

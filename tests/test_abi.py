@@ -65,7 +65,7 @@ def _geom(tomo, **kw):
     dict(n_det=2), dict(pad=100), dict(pad=64), dict(n_levels=7), dict(n_levels=3, n=40),
     dict(n_levels=2, n_det=90), dict(kb_width=1), dict(kb_width=17), dict(kb_oversamp=1.0),
     dict(beta=-1.0), dict(p=0.9), dict(p=2.5), dict(q=1.5), dict(sigma=0.0), dict(T=-1.0),
-    dict(neighbours=6), dict(flags=4), dict(center=math.inf),
+    dict(neighbours=6), dict(flags=8), dict(center=math.inf),
 ])
 def test_invalid_geometry_rejected_on_host(bad):
     tomo, lib = _lib()

@@ -1,0 +1,76 @@
+"""Tile autotuner of the three Toeplitz passes (through the C ABI).
+
+Every tile variant transforms each row or column with the same code, so the gradient
+must be bit-identical for all 27 variant combinations; the float64 objective (block
+partial sums grouped differently) agrees to rounding.  The autotuner must return a
+schedule consistent with its own timings, and a reconstruction with the tuned schedule
+must match the default schedule's.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import dev, make_plan, problem, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,nz,nb", [(128, 5, 26), (512, 2, 26), (96, 3, 8)])
+def test_all_tile_variants_bit_identical(n, nz, nb):
+    na = 30
+    nd = int(round(n * 2 ** 0.5)) // 2 * 2
+    sino, ang, center, phantom = problem(n, nz, na, nd, seed=n + nz)
+    plan = make_plan(n, nz, ang, nd, neighbours=nb, kb_width=6)
+    plan.precompute_psf()
+    rng = np.random.default_rng(3)
+    x = to_dev(phantom + 0.05 * rng.standard_normal(phantom.shape))
+    b = to_dev(0.3 * rng.standard_normal(phantom.shape))
+    ref = torch.empty_like(x)
+    obj_ref = torch.zeros(1, dtype=torch.float64, device=dev())
+    plan.gradient(x, b, ref, obj_ref)
+    base = plan.tiles()[0]
+    assert (base["rows_fwd"], base["cols_conv"], base["rows_inv"]) == (1, 1, 1)
+    shapes = set()
+    for v in itertools.product(range(3), repeat=3):
+        t = plan.tiles([{"rows_fwd": v[0], "cols_conv": v[1], "rows_inv": v[2]}])[0]
+        assert (t["rows_fwd"], t["cols_conv"], t["rows_inv"]) == v
+        shapes.add((t["fwd_pairs"], t["col_tile"], t["inv_pairs"]))
+        g = torch.empty_like(x)
+        obj = torch.zeros(1, dtype=torch.float64, device=dev())
+        plan.gradient(x, b, g, obj)
+        torch.cuda.synchronize()
+        assert torch.equal(g, ref), v
+        assert abs(obj.item() - obj_ref.item()) <= 1e-12 * abs(obj_ref.item()), v
+    if n >= 128:  # FFT size >= 256: the variants differ
+        assert len(shapes) > 1
+    with pytest.raises(RuntimeError):
+        plan.tiles([{"rows_fwd": 3, "cols_conv": 1, "rows_inv": 1}])
+
+
+def test_autotune_schedule_and_reconstruction():
+    from paper_2603_28756_amd import tomo
+    n, nz, na, nd, iters = 256, 4, 45, 364, 12
+    sino, ang, center, _ = problem(n, nz, na, nd, seed=17)
+    g = to_dev(sino)
+    outs = []
+    for tune in (False, True):
+        plan = make_plan(n, nz, ang, nd, neighbours=26, kb_width=6)
+        plan.precompute_psf()
+        if tune:
+            sched = plan.autotune(reps=3)
+            assert len(sched) == 1
+            s = sched[0]
+            for key, row in (("rows_fwd", 0), ("cols_conv", 1), ("rows_inv", 2)):
+                ms = s["ms"][row]
+                assert all(m > 0 for m in ms)
+                assert ms[s[key]] <= min(ms) + 1e-9
+            assert s["fwd_pairs"] > 0 and s["col_tile"] > 0 and s["inv_pairs"] > 0
+            assert plan.tiles()[0]["rows_fwd"] == s["rows_fwd"]
+        x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
+        st = plan.reconstruct(g, x, [iters], init=tomo.INIT_FBP)
+        outs.append((x.clone(), st["n_restarts"]))
+    (x0, r0), (x1, r1) = outs
+    assert r0 == r1
+    assert rel_l2(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-6

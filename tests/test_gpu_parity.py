@@ -12,6 +12,8 @@ import numpy as np
 import pytest
 import torch
 
+import synth
+
 from oracle import fbp as ofbp
 from oracle import hierarchy, radon, solver, toeplitz
 from oracle import prior as qg
@@ -102,6 +104,38 @@ def test_gradient_and_objective(n, nz, na, nd, c, nb, fused):
     assert abs(float(to_np(obj)[0]) - obj_ref) / scale < 1e-5
 
 
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("p", [1.2, 2.0])
+@pytest.mark.parametrize("nb", [8, 26])
+@pytest.mark.parametrize("n,nz", [(16, 1), (48, 37), (80, 18)])
+def test_prior_dominated_gradient(n, nz, nb, p, fused):
+    # beta = 1e3 makes beta grad Phi the bulk of the gradient, so this checks the prior kernel
+    # (interior tiles, edge tiles, ragged z-chunks; p < q and the quadratic p = q = 2) to 1e-5.
+    na, nd = 24, synth.detector_bins_for(n)
+    sino, ang, center, phantom = problem(n, nz, na, nd, seed=n + nz)
+    beta = 1e3
+    plan = make_plan(n, nz, ang, nd, neighbours=nb, beta=beta, p=p, fused_prior=fused)
+    plan.precompute_psf()
+    geom = oracle_geom(n, ang, nd, center)
+    _, _, P = plan.level_dims(0)
+    fk = toeplitz.psf_spectrum(geom, P)
+    rng = np.random.default_rng(n * nz)
+    x = (phantom + 0.1 * rng.standard_normal(phantom.shape)).astype(np.float32).astype(np.float64)
+    b = np.zeros_like(x)
+    grad = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
+    obj = torch.zeros(1, dtype=torch.float64, device=dev())
+    plan.gradient(to_dev(x), to_dev(b), grad, obj)
+    pr = oracle_prior(nb, p=p)
+    tx = toeplitz.apply(x, fk, n)
+    gphi = qg.gradient(x, pr)
+    ref = tx + beta * gphi
+    norm = np.linalg.norm(tx) + beta * np.linalg.norm(gphi)
+    assert beta * np.linalg.norm(gphi) > 10 * np.linalg.norm(tx)
+    assert np.linalg.norm(to_np(grad) - ref) / norm < 1e-5
+    obj_ref = 0.5 * float(np.vdot(x, tx)) + beta * qg.value(x, pr)
+    assert abs(float(to_np(obj)[0]) - obj_ref) / abs(obj_ref) < 1e-5
+
+
 def _oracle_fista(sino, ang, nd, center, n, nb, iters, init, restart=True, L=None, beta=0.01):
     geom = oracle_geom(n, ang, nd, center)
     prob = solver.build(geom, sino, oracle_prior(nb), beta)
@@ -185,14 +219,16 @@ def test_not_ready_before_psf():
 
 def test_graph_replay_matches_direct_launches():
     # The iteration loop replays captured 3-iteration graphs; every replay must equal the
-    # directly launched iterations bit for bit, also after unrelated eager work between calls.
+    # directly launched iterations bit for bit, also after unrelated eager work between calls,
+    # with the prior kernel on its own stream or in sequence.
     from paper_2603_28756_amd import tomo
     n, nz, na, nd, iters = 64, 2, 30, 92, 20
     sino, ang, center, _ = problem(n, nz, na, nd, seed=21)
     g = to_dev(sino)
     outs = []
-    for graphs in (False, True, True):
-        plan = make_plan(n, nz, ang, nd, neighbours=26, graphs=graphs)
+    # (graphs, concurrent prior): the prior kernel in sequence or on its own stream
+    for graphs, conc in ((False, False), (False, True), (True, True), (True, False)):
+        plan = make_plan(n, nz, ang, nd, neighbours=26, graphs=graphs, concurrent_prior=conc)
         for rep in range(2):
             x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
             hist = torch.zeros(iters, dtype=torch.float64, device=dev())
