@@ -258,7 +258,7 @@ typedef struct {
 
 /* Time every variant of the three passes on each level at the plan's own shapes (reps
  * launches each, after one warm-up; reps <= 0 means 5) and keep the fastest per pass and
- * level.  Synchronises the plan's stream; overwrites the iterate and spectrum scratch of the
+ * level (a variant replaces the default only when at least 3% faster).  Synchronises the plan's stream; overwrites the iterate and spectrum scratch of the
  * workspace (not b, the PSF spectrum or the step constants), so call it before
  * tomo_reconstruct or between reconstructions.  Captured iteration graphs are rebuilt on the
  * next reconstruction.  chosen: nullable host [n_levels], receives the choice and timings.

@@ -1283,10 +1283,12 @@ tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
       }
     }
     if (s != TOMO_OK) break;
+    // a variant replaces the default only when at least 3% faster, so that timing noise
+    // does not flip schedules between runs
     auto best = [&](int pass) {
-      int b = 1;  // the default wins ties
+      int b = 1;
       for (int v = 0; v < 3; ++v)
-        if (ms[pass][v] < ms[pass][b]) b = v;
+        if (v != 1 && ms[pass][v] < 0.97f * ms[pass][1] && ms[pass][v] < ms[pass][b]) b = v;
       return b;
     };
     l.v_fwd = best(0);

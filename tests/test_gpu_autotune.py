@@ -65,7 +65,9 @@ def test_autotune_schedule_and_reconstruction():
             for key, row in (("rows_fwd", 0), ("cols_conv", 1), ("rows_inv", 2)):
                 ms = s["ms"][row]
                 assert all(m > 0 for m in ms)
-                assert ms[s[key]] <= min(ms) + 1e-9
+                assert ms[s[key]] <= min(ms) + 1e-9 or s[key] == 1
+                if s[key] != 1:
+                    assert ms[s[key]] < 0.97 * ms[1]
             assert s["fwd_pairs"] > 0 and s["col_tile"] > 0 and s["inv_pairs"] > 0
             assert plan.tiles()[0]["rows_fwd"] == s["rows_fwd"]
         x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
