@@ -19,5 +19,6 @@ prior      qGGMRF potential, value and gradient over 8 or 26 neighbours (Sec. 2,
 fbp        ramp-filtered back-projection initial estimate (Sec. 2.2, Eqs. 12-14)
 solver     objective, gradient, Lipschitz constant and FISTA with restart (Sec. 2, Eqs. 5-6, 10-11)
 hierarchy  sinogram subsampling, Lanczos-3 prolongation, coarse-to-fine solve (Sec. 2.3)
+unet       learned start: U-Net forward, backward, loss and Adam step (Sec. 2.2, 3.2 extension)
 """
-from . import geometry, radon, toeplitz, prior, fbp, solver, hierarchy  # noqa: F401
+from . import geometry, radon, toeplitz, prior, fbp, solver, hierarchy, unet  # noqa: F401
