@@ -1,0 +1,613 @@
+// Kernels of the learned start: a 2D U-Net in bfloat16 with float32 accumulation on the
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16), its backward pass and an Adam update.
+//
+// Tensors are NHWC ([batch][row][column][channel]) bfloat16 stored as uint16_t; a tensor
+// argument is a pointer to its first channel plus `ld`, the channel count of the buffer
+// it lives in (a skip concatenation is a channel range of a wider buffer).
+//
+// MFMA 16x16x32 bf16 operand layout (lane l of a wave): A (16 x 32) row l%16, k values
+// 8*(l/16) .. 8*(l/16)+7; B (32 x 16) column l%16, the same k values; D (16 x 16) rows
+// 4*(l/16) .. +3 of column l%16.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "nn_kernels.hpp"
+
+namespace tomo {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest, ties to even (NaN kept quiet)
+TOMO_DEV uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+TOMO_DEV float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+TOMO_DEV u16x8 ld8(const uint16_t* p) { return *reinterpret_cast<const u16x8*>(p); }
+TOMO_DEV void st8(uint16_t* p, u16x8 v) { *reinterpret_cast<u16x8*>(p) = v; }
+TOMO_DEV f32x4 mfma(u16x8 a, u16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ 3x3 conv, forward
+// y[p, co] = act(bias[co] + sum_{tap, ci} w[co][tap][ci] x[p + tap, ci]) (zero padding), then
+// multiplied by (mask[p, co] > 0) when a mask is given (the ReLU derivative of the forward
+// activation when this kernel computes an input gradient).  A block computes 64 pixels of
+// one image row (16 per wave) x COT output channels.
+constexpr int CV_PX = 64;
+
+template <int COT, bool RELU, bool BIAS, bool MASK>
+__global__ void __launch_bounds__(256)
+conv3x3_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
+               const float* __restrict__ bias, uint16_t* __restrict__ y, int ldy,
+               const uint16_t* __restrict__ mask, int ldm, int cin, int H, int W, int ntx) {
+  constexpr int NT = COT / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tx = blockIdx.x % ntx, cot = blockIdx.x / ntx;
+  const int row = blockIdx.y;
+  const size_t img = (size_t)blockIdx.z * H * W;
+  const int px = tx * CV_PX + wave * 16 + (lane & 15);
+  const int kq = (lane >> 4) * 8;
+  const int co0 = cot * COT;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const size_t wstride = (size_t)16 * 9 * cin;  // between 16-channel output groups
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = row + tap / 3 - 1, xx = px + tap % 3 - 1;
+    const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const uint16_t* xa = x + (ok ? (img + (size_t)yy * W + xx) * ldx : 0) + kq;
+    const uint16_t* wb = w + ((size_t)(co0 + (lane & 15)) * 9 + tap) * cin + kq;
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (ok) a = ld8(xa + c0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma(a, ld8(wb + t * wstride + c0), acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = co0 + 16 * t + (lane & 15);
+    const float bv = BIAS ? bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = tx * CV_PX + wave * 16 + 4 * (lane >> 4) + i;
+      if (p < W) {
+        const size_t pix = img + (size_t)row * W + p;
+        float v = acc[t][i] + bv;
+        if (RELU) v = fmaxf(v, 0.f);
+        if (MASK && !(bf2f(mask[pix * ldm + co]) > 0.f)) v = 0.f;
+        y[pix * ldy + co] = f2bf(v);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ 3x3 conv, weights
+// part[s][co][n] = sum over the pixels of split s of dz[p, co] x[p + tap(n), ci(n)],
+// n = tap * cin + ci; partb[s][co] = sum over the same pixels of dz[p, co].  A block owns a
+// 64 x 64 tile of (co, n) and one pixel split; 32-pixel steps are staged through LDS
+// transposed so that the K dimension (pixels) is contiguous for the matrix-core operands.
+constexpr int WG_K = 32, WG_PAD = 8;
+
+__global__ void __launch_bounds__(256)
+conv3x3_wgrad_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* __restrict__ x,
+                     int ldx, float* __restrict__ part, float* __restrict__ partb, int cin,
+                     int cout, int H, int W, int npx, int px_per_split) {
+  __shared__ __align__(16) uint16_t sa[64][WG_K + WG_PAD];  // [co][pixel]
+  __shared__ __align__(16) uint16_t sb[64][WG_K + WG_PAD];  // [n][pixel]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int n0 = blockIdx.x * 64, co0 = blockIdx.y * 64, s = blockIdx.z;
+  const int nn = 9 * cin;
+  const int pb = s * px_per_split, pe = min(npx, pb + px_per_split);
+  const int cw = (wave & 1) * 32, nw = (wave >> 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int pl = t >> 3, cg = (t & 7) * 8;
+  // this thread's column group of the x tile: tap and channel are fixed over the loop
+  const int n = n0 + cg;
+  const int tap = n < nn ? n / cin : 0, ci = n - tap * cin;
+  const int ky = tap / 3 - 1, kx = tap % 3 - 1;
+  float bsum = 0.f;
+  const int HW = H * W;
+  for (int p0 = pb; p0 < pe; p0 += WG_K) {
+    const int p = p0 + pl;
+    u16x8 va = {0, 0, 0, 0, 0, 0, 0, 0}, vb = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (p < pe) {
+      if (co0 + cg < cout) va = ld8(dz + (size_t)p * ldz + co0 + cg);
+      if (n < nn) {
+        const int b = p / HW, rem = p - b * HW, yy = rem / W + ky, xx = rem - (rem / W) * W + kx;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          vb = ld8(x + ((size_t)b * HW + (size_t)yy * W + xx) * ldx + ci);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      sa[cg + j][pl] = va[j];
+      sb[cg + j][pl] = vb[j];
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t < 64) {
+#pragma unroll 8
+      for (int k = 0; k < WG_K; ++k) bsum += bf2f(sa[t][k]);
+    }
+    const int kq = (lane >> 4) * 8;
+    u16x8 a[2], bb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = ld8(&sa[cw + 16 * i + (lane & 15)][kq]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bb[j] = ld8(&sb[nw + 16 * j + (lane & 15)][kq]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], bb[j], acc[i][j]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + nw + 16 * j + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + cw + 16 * i + 4 * (lane >> 4) + r;
+        if (co < cout && col < nn) part[((size_t)s * cout + co) * nn + col] = acc[i][j][r];
+      }
+    }
+  if (blockIdx.x == 0 && t < 64 && co0 + t < cout) partb[(size_t)s * cout + co0 + t] = bsum;
+}
+
+// out[i] = sum_s part[s][i] (fixed order), optionally accumulated into out
+__global__ void sum_splits_kernel(const float* __restrict__ part, int nsplit, size_t n,
+                                  float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float a = 0.f;
+  for (int s = 0; s < nsplit; ++s) a += part[(size_t)s * n + i];
+  out[i] = a;
+}
+
+// ------------------------------------------------- first layer (one input channel), fp32
+// y[p, co] = relu(b[co] + sum_tap w[co][tap] u[p + tap]), u = fbp * inv_s; a thread makes
+// 8 channels of one pixel.
+__global__ void conv_in_kernel(const float* __restrict__ fbp, float inv_s,
+                               const float* __restrict__ w, const float* __restrict__ bias,
+                               uint16_t* __restrict__ y, int cout, int H, int W, int npx) {
+  const int g8 = cout / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)npx * g8) return;
+  const int p = (int)(idx / g8), c0 = (int)(idx - (size_t)p * g8) * 8;
+  const int HW = H * W, b = p / HW, rem = p - b * HW, r = rem / W, c = rem - r * W;
+  float u[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = r + tap / 3 - 1, xx = c + tap % 3 - 1;
+    u[tap] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                 ? fbp[(size_t)b * HW + (size_t)yy * W + xx] * inv_s : 0.f;
+  }
+  u16x8 out;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    float a = bias[c0 + j];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) a = fmaf(w[(c0 + j) * 9 + tap], u[tap], a);
+    out[j] = f2bf(fmaxf(a, 0.f));
+  }
+  st8(y + (size_t)p * cout + c0, out);
+}
+
+// part[blk][co*10 + k] (k < 9: weight of tap k, k = 9: bias) over the pixels of block blk
+__global__ void __launch_bounds__(256)
+conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ fbp, float inv_s,
+                     float* __restrict__ part, int cout, int H, int W, int npx, int px_per_blk) {
+  extern __shared__ float sacc[];  // [256 threads][10]
+  const int t = threadIdx.x;
+  const int pb = blockIdx.x * px_per_blk, pe = min(npx, pb + px_per_blk);
+  const int HW = H * W;
+  // thread t: channel co = t % cout, pixel lane t / cout
+  const int lanes = 256 / cout;
+  const int co = t % cout, pl = t / cout;
+  float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (pl < lanes) {
+    for (int p = pb + pl; p < pe; p += lanes) {
+      const float d = bf2f(dz[(size_t)p * cout + co]);
+      const int b = p / HW, rem = p - b * HW, r = rem / W, c = rem - r * W;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int yy = r + tap / 3 - 1, xx = c + tap % 3 - 1;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          acc[tap] = fmaf(d, fbp[(size_t)b * HW + (size_t)yy * W + xx] * inv_s, acc[tap]);
+      }
+      acc[9] += d;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 10; ++k) sacc[t * 10 + k] = acc[k];
+  __syncthreads();
+  for (int o = t; o < cout * 10; o += 256) {
+    const int c = o / 10, k = o - c * 10;
+    float a = 0.f;
+    for (int l = 0; l < lanes; ++l) a += sacc[(l * cout + c) * 10 + k];
+    part[(size_t)blockIdx.x * cout * 10 + o] = a;
+  }
+}
+
+// dw[co][tap] = sum_blk part[blk][co*10 + tap], db[co] = sum_blk part[blk][co*10 + 9]
+__global__ void conv_in_reduce_kernel(const float* __restrict__ part, int nblk, int cout,
+                                      float* __restrict__ dw, float* __restrict__ db) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= cout * 10) return;
+  float a = 0.f;
+  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * cout * 10 + o];
+  const int co = o / 10, k = o - co * 10;
+  if (k < 9) dw[co * 9 + k] = a;
+  else db[co] = a;
+}
+
+// ------------------------------------------------------------ pooling and upsampling
+// out[b, i, j, c] = mean of in[b, 2i+a, 2j+e, c]; 8 channels per thread
+__global__ void avgpool2_kernel(const uint16_t* __restrict__ in, int ldi, uint16_t* __restrict__ out,
+                                int ldo, int C, int B, int H, int W) {
+  const int h = H / 2, w = W / 2, g8 = C / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * h * w * g8) return;
+  const size_t q = idx / g8;
+  const int c0 = (int)(idx - q * g8) * 8;
+  const int b = (int)(q / ((size_t)h * w)), rem = (int)(q - (size_t)b * h * w), i = rem / w, j = rem - i * w;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const u16x8 v = ld8(in + (((size_t)b * H + 2 * i + a) * W + 2 * j + e) * ldi + c0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] += bf2f(v[k]);
+    }
+  u16x8 o;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) o[k] = f2bf(0.25f * s[k]);
+  st8(out + q * ldo + c0, o);
+}
+
+// dE[b, 2i+a, 2j+e, c] += 0.25 dP[b, i, j, c] where E > 0 (E: the pooled activation)
+__global__ void avgpool2_back_kernel(const uint16_t* __restrict__ dp, int ldp,
+                                     const uint16_t* __restrict__ e_act, int lde,
+                                     uint16_t* __restrict__ de, int ldd, int C, int B, int H, int W) {
+  const int h = H / 2, w = W / 2, g8 = C / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * H * W * g8) return;
+  const size_t q = idx / g8;
+  const int c0 = (int)(idx - q * g8) * 8;
+  const int b = (int)(q / ((size_t)H * W)), rem = (int)(q - (size_t)b * H * W), r = rem / W, c = rem - r * W;
+  const u16x8 g = ld8(dp + (((size_t)b * h + r / 2) * w + c / 2) * ldp + c0);
+  const u16x8 ev = ld8(e_act + q * lde + c0);
+  u16x8 d = ld8(de + q * ldd + c0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (bf2f(ev[k]) > 0.f) d[k] = f2bf(bf2f(d[k]) + 0.25f * bf2f(g[k]));
+  st8(de + q * ldd + c0, d);
+}
+
+// out[b, r, c, :C] = in[b, r/2, c/2, :C]
+__global__ void up2_kernel(const uint16_t* __restrict__ in, int ldi, uint16_t* __restrict__ out,
+                           int ldo, int C, int B, int H, int W) {
+  const int g8 = C / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * H * W * g8) return;
+  const size_t q = idx / g8;
+  const int c0 = (int)(idx - q * g8) * 8;
+  const int b = (int)(q / ((size_t)H * W)), rem = (int)(q - (size_t)b * H * W), r = rem / W, c = rem - r * W;
+  st8(out + q * ldo + c0, ld8(in + (((size_t)b * (H / 2) + r / 2) * (W / 2) + c / 2) * ldi + c0));
+}
+
+// out[b, i, j, :C] = sum_{a, e} in[b, 2i+a, 2j+e, :C]
+__global__ void up2_back_kernel(const uint16_t* __restrict__ in, int ldi, uint16_t* __restrict__ out,
+                                int ldo, int C, int B, int H, int W) {
+  const int h = H / 2, w = W / 2, g8 = C / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * h * w * g8) return;
+  const size_t q = idx / g8;
+  const int c0 = (int)(idx - q * g8) * 8;
+  const int b = (int)(q / ((size_t)h * w)), rem = (int)(q - (size_t)b * h * w), i = rem / w, j = rem - i * w;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const u16x8 v = ld8(in + (((size_t)b * H + 2 * i + a) * W + 2 * j + e) * ldi + c0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] += bf2f(v[k]);
+    }
+  u16x8 o;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) o[k] = f2bf(s[k]);
+  st8(out + q * ldo + c0, o);
+}
+
+// ---------------------------------------------------------------------------- head, loss
+// r = hb + sum_c hw[c] D[p, c]; x0 = fbp + s r
+__global__ void head_kernel(const uint16_t* __restrict__ d, const float* __restrict__ hw,
+                            const float* __restrict__ hb, const float* __restrict__ fbp, float s,
+                            float* __restrict__ r, float* __restrict__ x0, int C, int npx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  float a = hb[0];
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    const u16x8 v = ld8(d + (size_t)p * C + c0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a = fmaf(hw[c0 + k], bf2f(v[k]), a);
+  }
+  if (r) r[p] = a;
+  if (x0) x0[p] = fbp[p] + s * a;
+}
+
+// dr = 2 (r - (target - fbp)/s) / npx; dD[p, c] = hw[c] dr (D > 0); per block: sum of the
+// squared residual (float64), sum dr, sum dr D[:, c] -> part[blk][C + 2]
+__global__ void __launch_bounds__(256)
+head_back_kernel(const float* __restrict__ r, const float* __restrict__ fbp,
+                 const float* __restrict__ target, float inv_s, const uint16_t* __restrict__ d,
+                 const float* __restrict__ hw, uint16_t* __restrict__ dd, double* __restrict__ part,
+                 int C, int npx) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  const int p = blockIdx.x * 256 + t;
+  double sq = 0.0;
+  float dr = 0.f;
+  if (p < npx) {
+    const float diff = r[p] - (target[p] - fbp[p]) * inv_s;
+    sq = (double)diff * diff;
+    dr = 2.f * diff / (float)npx;
+  }
+  // gradient of the last activation
+  for (int c0 = 0; c0 < C && p < npx; c0 += 8) {
+    const u16x8 v = ld8(d + (size_t)p * C + c0);
+    u16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = f2bf(bf2f(v[k]) > 0.f ? hw[c0 + k] * dr : 0.f);
+    st8(dd + (size_t)p * C + c0, o);
+  }
+  // block sums: [0] squared residual, [1] dr, [2 + c] dr D[:, c]
+  for (int k = -2; k < C; ++k) {
+    double v = 0.0;
+    if (p < npx) {
+      if (k == -2) v = sq;
+      else if (k == -1) v = dr;
+      else v = (double)dr * bf2f(d[(size_t)p * C + k]);
+    }
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) sh[t] += sh[t + o];
+      __syncthreads();
+    }
+    if (t == 0) part[(size_t)blockIdx.x * (C + 2) + (k + 2)] = sh[0];
+    __syncthreads();
+  }
+}
+
+// fixed-order sums of head_back partials: loss (mean), head weight and bias gradients
+__global__ void head_reduce_kernel(const double* __restrict__ part, int nblk, int C, int npx,
+                                   float* __restrict__ ghw, float* __restrict__ ghb,
+                                   double* __restrict__ loss) {
+  const int k = threadIdx.x;
+  if (k >= C + 2) return;
+  double a = 0.0;
+  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * (C + 2) + k];
+  if (k == 0) {
+    if (loss) *loss = a / npx;
+  } else if (k == 1) {
+    if (ghb) ghb[0] = (float)a;
+  } else if (ghw) {
+    ghw[k - 2] = (float)a;
+  }
+}
+
+// ---------------------------------------------------------------------- optimiser, weights
+__global__ void adam_kernel(float* __restrict__ th, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, size_t n, float lr,
+                            float b1, float b2, float c1, float c2, float eps) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// wbf[co][tap][ci] = bf16(w[co][tap][ci]); wflip[ci][tap][co] = bf16(w[co][8 - tap][ci])
+__global__ void weight_prep_kernel(const float* __restrict__ w, uint16_t* __restrict__ wbf,
+                                   uint16_t* __restrict__ wflip, int cin, int cout) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t n = (size_t)cout * 9 * cin;
+  if (i >= n) return;
+  const int co = (int)(i / (9 * (size_t)cin)), rem = (int)(i - (size_t)co * 9 * cin);
+  const int tap = rem / cin, ci = rem - tap * cin;
+  const uint16_t h = f2bf(w[i]);
+  wbf[i] = h;
+  if (wflip) wflip[((size_t)ci * 9 + (8 - tap)) * cout + co] = h;
+}
+
+__global__ void f32_to_bf16_kernel(const float* __restrict__ in, uint16_t* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f2bf(in[i]);
+}
+
+unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ launchers
+hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float* bias,
+                      uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
+                      int B, int H, int W, bool relu, hipStream_t st) {
+  if (cin % 32 || cout % 32 || ldx % 8 || ldy < cout || B < 1 || H < 1 || W < 1)
+    return hipErrorInvalidValue;
+  const int ntx = (W + CV_PX - 1) / CV_PX;
+  const int cot = cout % 64 == 0 ? 64 : 32;
+  const dim3 grid(ntx * (cout / cot), H, B);
+#define CV(COT, R, BI, M)                                                                   \
+  hipLaunchKernelGGL((conv3x3_kernel<COT, R, BI, M>), grid, dim3(256), 0, st, x, ldx, w, bias, \
+                     y, ldy, mask, ldm, cin, H, W, ntx)
+  const bool bi = bias != nullptr, m = mask != nullptr;
+  if (cot == 64) {
+    if (relu && bi && !m) CV(64, true, true, false);
+    else if (!relu && !bi && m) CV(64, false, false, true);
+    else if (!relu && !bi && !m) CV(64, false, false, false);
+    else if (!relu && bi && !m) CV(64, false, true, false);
+    else return hipErrorInvalidValue;
+  } else {
+    if (relu && bi && !m) CV(32, true, true, false);
+    else if (!relu && !bi && m) CV(32, false, false, true);
+    else if (!relu && !bi && !m) CV(32, false, false, false);
+    else if (!relu && bi && !m) CV(32, false, true, false);
+    else return hipErrorInvalidValue;
+  }
+#undef CV
+  return hipGetLastError();
+}
+
+WgradPlan nn_wgrad_plan(int cin, int cout, int npx) {
+  WgradPlan pl;
+  pl.ntn = (9 * cin + 63) / 64;
+  pl.ntc = (cout + 63) / 64;
+  // about 2048 blocks, at least 256 pixels per split, a multiple of the 32-pixel step
+  int ns = 2048 / (pl.ntn * pl.ntc);
+  if (ns < 1) ns = 1;
+  int per = (npx + ns - 1) / ns;
+  if (per < 256) per = 256;
+  per = (per + WG_K - 1) / WG_K * WG_K;
+  pl.px_per_split = per;
+  pl.nsplit = (npx + per - 1) / per;
+  pl.scratch_floats = (size_t)pl.nsplit * cout * (9 * cin + 1);
+  return pl;
+}
+
+hipError_t nn_conv3x3_wgrad(const uint16_t* dz, int ldz, const uint16_t* x, int ldx, float* dw,
+                            float* db, int cin, int cout, int B, int H, int W, float* scratch,
+                            size_t scratch_floats, hipStream_t st) {
+  if (cin % 32 || cout % 32 || ldz % 8 || ldx % 8) return hipErrorInvalidValue;
+  const int npx = B * H * W;
+  const WgradPlan pl = nn_wgrad_plan(cin, cout, npx);
+  if (pl.scratch_floats > scratch_floats) return hipErrorInvalidValue;
+  float* part = scratch;
+  float* partb = scratch + (size_t)pl.nsplit * cout * 9 * cin;
+  hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(pl.ntn, pl.ntc, pl.nsplit), dim3(256), 0, st, dz,
+                     ldz, x, ldx, part, partb, cin, cout, H, W, npx, pl.px_per_split);
+  const size_t nw = (size_t)cout * 9 * cin;
+  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, st, part,
+                     pl.nsplit, nw, dw);
+  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(cout, 256)), dim3(256), 0, st, partb,
+                     pl.nsplit, (size_t)cout, db);
+  return hipGetLastError();
+}
+
+hipError_t nn_conv_in(const float* fbp, float inv_s, const float* w, const float* bias,
+                      uint16_t* y, int cout, int B, int H, int W, hipStream_t st) {
+  if (cout % 8) return hipErrorInvalidValue;
+  const size_t n = (size_t)B * H * W * (cout / 8);
+  hipLaunchKernelGGL(conv_in_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, fbp, inv_s, w,
+                     bias, y, cout, H, W, B * H * W);
+  return hipGetLastError();
+}
+
+int nn_conv_in_wgrad_blocks(int npx) { return (npx + 4095) / 4096; }
+
+hipError_t nn_conv_in_wgrad(const uint16_t* dz, const float* fbp, float inv_s, float* dw,
+                            float* db, int cout, int B, int H, int W, float* scratch,
+                            size_t scratch_floats, hipStream_t st) {
+  if (cout > 256 || 256 % cout) return hipErrorInvalidValue;
+  const int npx = B * H * W, nb = nn_conv_in_wgrad_blocks(npx);
+  if ((size_t)nb * cout * 10 > scratch_floats) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(conv_in_wgrad_kernel, dim3(nb), dim3(256), 256 * 10 * sizeof(float), st, dz,
+                     fbp, inv_s, scratch, cout, H, W, npx, 4096);
+  hipLaunchKernelGGL(conv_in_reduce_kernel, dim3(blocks_for((size_t)cout * 10, 256)), dim3(256), 0,
+                     st, scratch, nb, cout, dw, db);
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool2(const uint16_t* in, int ldi, uint16_t* out, int ldo, int C, int B, int H,
+                       int W, hipStream_t st) {
+  const size_t n = (size_t)B * (H / 2) * (W / 2) * (C / 8);
+  hipLaunchKernelGGL(avgpool2_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, in, ldi, out, ldo,
+                     C, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool2_back(const uint16_t* dp, int ldp, const uint16_t* e, int lde, uint16_t* de,
+                            int ldd, int C, int B, int H, int W, hipStream_t st) {
+  const size_t n = (size_t)B * H * W * (C / 8);
+  hipLaunchKernelGGL(avgpool2_back_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, dp, ldp, e,
+                     lde, de, ldd, C, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t nn_up2(const uint16_t* in, int ldi, uint16_t* out, int ldo, int C, int B, int H, int W,
+                  hipStream_t st) {
+  const size_t n = (size_t)B * H * W * (C / 8);
+  hipLaunchKernelGGL(up2_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, in, ldi, out, ldo, C,
+                     B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t nn_up2_back(const uint16_t* in, int ldi, uint16_t* out, int ldo, int C, int B, int H,
+                       int W, hipStream_t st) {
+  const size_t n = (size_t)B * (H / 2) * (W / 2) * (C / 8);
+  hipLaunchKernelGGL(up2_back_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, in, ldi, out, ldo,
+                     C, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t nn_head(const uint16_t* d, const float* hw, const float* hb, const float* fbp, float s,
+                   float* r, float* x0, int C, int npx, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel, dim3(blocks_for(npx, 256)), dim3(256), 0, st, d, hw, hb, fbp, s, r,
+                     x0, C, npx);
+  return hipGetLastError();
+}
+
+int nn_head_back_blocks(int npx) { return (npx + 255) / 256; }
+
+hipError_t nn_head_back(const float* r, const float* fbp, const float* target, float inv_s,
+                        const uint16_t* d, const float* hw, uint16_t* dd, double* part, float* ghw,
+                        float* ghb, double* loss, int C, int npx, hipStream_t st) {
+  if (C + 2 > 1024) return hipErrorInvalidValue;
+  const int nb = nn_head_back_blocks(npx);
+  hipLaunchKernelGGL(head_back_kernel, dim3(nb), dim3(256), 0, st, r, fbp, target, inv_s, d, hw, dd,
+                     part, C, npx);
+  hipLaunchKernelGGL(head_reduce_kernel, dim3(1), dim3(((C + 2 + 63) / 64) * 64), 0, st, part, nb, C,
+                     npx, ghw, ghb, loss);
+  return hipGetLastError();
+}
+
+hipError_t nn_adam(float* th, const float* g, float* m, float* v, size_t n, float lr, float b1,
+                   float b2, float c1, float c2, float eps, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, th, g, m, v, n, lr, b1,
+                     b2, c1, c2, eps);
+  return hipGetLastError();
+}
+
+hipError_t nn_weight_prep(const float* w, uint16_t* wbf, uint16_t* wflip, int cin, int cout,
+                          hipStream_t st) {
+  const size_t n = (size_t)cout * 9 * cin;
+  hipLaunchKernelGGL(weight_prep_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, w, wbf, wflip,
+                     cin, cout);
+  return hipGetLastError();
+}
+
+hipError_t nn_f32_to_bf16(const float* in, uint16_t* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace tomo

@@ -107,6 +107,30 @@ EXPORTS = {
     "tomo_batch_reconstruct": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                 ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(BatchStats)], ctypes.c_int),
     "tomo_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_create": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "tomo_unet_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tomo_unet_set_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "tomo_unet_num_params": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "tomo_unet_set_params": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_get_params": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_float],
+                          ctypes.c_int),
+    "tomo_unet_loss_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
+                             ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
+    "tomo_nn_conv3x3": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
+                        ctypes.c_int),
+    "tomo_nn_wgrad_scratch": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+                              ctypes.c_int),
+    "tomo_nn_conv3x3_wgrad": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "tomo_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tomo_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
 }
@@ -342,3 +366,132 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- learned start
+def _unet_check(status: int, h):
+    if status != TOMO_OK:
+        lib = load_library()
+        raise TomoError(status, lib.tomo_unet_last_error(h).decode())
+
+
+def _bf16_ptr(t: torch.Tensor) -> int:
+    if t.dtype != torch.bfloat16 or t.device.type != "cuda":
+        raise TypeError("expected a bfloat16 device tensor")
+    return t.data_ptr()
+
+
+class UNet:
+    """U-Net learned start (include/tomo_nn.h): parameters, forward, loss/gradient, Adam."""
+
+    def __init__(self, height: int, width: int, levels: int = 4, base: int = 32, max_batch: int = 1,
+                 device=None, stream=None):
+        self._lib = load_library()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.height, self.width, self.levels, self.base, self.max_batch = height, width, levels, base, max_batch
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        _unet_check(self._lib.tomo_unet_create(levels, base, max_batch, height, width, ctypes.c_void_p(st),
+                                               ctypes.byref(h)), None)
+        self._h = h
+        nbytes = ctypes.c_size_t()
+        _unet_check(self._lib.tomo_unet_workspace_size(h, ctypes.byref(nbytes)), h)
+        self._ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        _unet_check(self._lib.tomo_unet_set_workspace(h, ctypes.c_void_p(self._ws.data_ptr()), nbytes.value), h)
+        n = ctypes.c_int64()
+        _unet_check(self._lib.tomo_unet_num_params(h, ctypes.byref(n)), h)
+        self.n_params = n.value
+        self._loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._lib is not None:
+            self._lib.tomo_unet_destroy(self._h)
+            self._h = None
+
+    def set_params(self, theta: torch.Tensor):
+        t = theta.to(device=self.device, dtype=torch.float32).contiguous()
+        if t.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {t.numel()}")
+        _unet_check(self._lib.tomo_unet_set_params(self._h, ctypes.c_void_p(t.data_ptr())), self._h)
+        torch.cuda.synchronize(self.device)
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _unet_check(self._lib.tomo_unet_get_params(self._h, ctypes.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    def _img(self, t: torch.Tensor) -> torch.Tensor:
+        if t.dtype != torch.float32 or t.device.type != "cuda" or not t.is_contiguous():
+            raise TypeError("images must be contiguous float32 device tensors")
+        if tuple(t.shape[-2:]) != (self.height, self.width):
+            raise ValueError("image size differs from the network's")
+        return t
+
+    def forward(self, fbp: torch.Tensor, scale: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        fbp = self._img(fbp)
+        b = fbp.numel() // (self.height * self.width)
+        out = torch.empty_like(fbp) if out is None else self._img(out)
+        _unet_check(self._lib.tomo_unet_forward(self._h, ctypes.c_void_p(fbp.data_ptr()),
+                                                ctypes.c_void_p(out.data_ptr()), b, float(scale)), self._h)
+        return out
+
+    def loss_grad(self, fbp: torch.Tensor, target: torch.Tensor, scale: float):
+        fbp, target = self._img(fbp), self._img(target)
+        b = fbp.numel() // (self.height * self.width)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _unet_check(self._lib.tomo_unet_loss_grad(self._h, ctypes.c_void_p(fbp.data_ptr()),
+                                                  ctypes.c_void_p(target.data_ptr()), b, float(scale),
+                                                  ctypes.c_void_p(g.data_ptr()),
+                                                  ctypes.c_void_p(self._loss.data_ptr())), self._h)
+        return float(self._loss.item()), g
+
+    def train_step(self, fbp: torch.Tensor, target: torch.Tensor, scale: float, lr: float,
+                   loss_out: Optional[torch.Tensor] = None):
+        """One Adam step; the batch loss (before the step) goes to loss_out[0] (float64) if given."""
+        fbp, target = self._img(fbp), self._img(target)
+        b = fbp.numel() // (self.height * self.width)
+        lp = loss_out.data_ptr() if loss_out is not None else self._loss.data_ptr()
+        _unet_check(self._lib.tomo_unet_train_step(self._h, ctypes.c_void_p(fbp.data_ptr()),
+                                                   ctypes.c_void_p(target.data_ptr()), b, float(scale),
+                                                   float(lr), ctypes.c_void_p(lp)), self._h)
+
+
+def nn_conv3x3(x: torch.Tensor, w: torch.Tensor, bias: Optional[torch.Tensor], cin: int, cout: int,
+               relu: bool = False, mask: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+               x_ld: Optional[int] = None, out_ld: Optional[int] = None, mask_ld: Optional[int] = None,
+               stream=None) -> torch.Tensor:
+    """3x3 convolution of NHWC bfloat16 x ([B, H, W, ld], channels 0..cin-1) by w [cout, 3, 3, cin] (bf16)."""
+    lib = load_library()
+    B, H, W = x.shape[0], x.shape[1], x.shape[2]
+    ldx = x_ld if x_ld is not None else x.shape[3]
+    if out is None:
+        out = torch.empty((B, H, W, cout), dtype=torch.bfloat16, device=x.device)
+    ldy = out_ld if out_ld is not None else out.shape[3]
+    ldm = (mask_ld if mask_ld is not None else mask.shape[3]) if mask is not None else 0
+    st = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+    status = lib.tomo_nn_conv3x3(ctypes.c_void_p(_bf16_ptr(x)), ldx, ctypes.c_void_p(_bf16_ptr(w)),
+                                 _ptr(bias), ctypes.c_void_p(_bf16_ptr(out)), ldy,
+                                 ctypes.c_void_p(_bf16_ptr(mask)) if mask is not None else None, ldm,
+                                 cin, cout, B, H, W, int(relu), ctypes.c_void_p(st))
+    _unet_check(status, None)
+    return out
+
+
+def nn_conv3x3_wgrad(dz: torch.Tensor, x: torch.Tensor, cin: int, cout: int, dz_ld: Optional[int] = None,
+                     x_ld: Optional[int] = None, stream=None):
+    """(dw [cout, 3, 3, cin], db [cout]) float32 for NHWC bfloat16 dz and x."""
+    lib = load_library()
+    B, H, W = x.shape[0], x.shape[1], x.shape[2]
+    ldz = dz_ld if dz_ld is not None else dz.shape[3]
+    ldx = x_ld if x_ld is not None else x.shape[3]
+    n = ctypes.c_size_t()
+    _unet_check(lib.tomo_nn_wgrad_scratch(cin, cout, B * H * W, ctypes.byref(n)), None)
+    scratch = torch.empty(max(n.value, 1), dtype=torch.float32, device=x.device)
+    dw = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device=x.device)
+    db = torch.empty(cout, dtype=torch.float32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+    _unet_check(lib.tomo_nn_conv3x3_wgrad(ctypes.c_void_p(_bf16_ptr(dz)), ldz, ctypes.c_void_p(_bf16_ptr(x)), ldx,
+                                          ctypes.c_void_p(dw.data_ptr()), ctypes.c_void_p(db.data_ptr()), cin, cout,
+                                          B, H, W, ctypes.c_void_p(scratch.data_ptr()), n.value,
+                                          ctypes.c_void_p(st)), None)
+    return dw, db

@@ -11,7 +11,8 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "tomo.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
 def _lib():
@@ -22,14 +23,15 @@ def _lib():
 
 
 def _declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^(?:tomo_status|const char\*)\s+(tomo_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_entry_points():
     names = _declared()
     for required in ("tomo_plan_create", "tomo_precompute_psf", "tomo_gradient", "tomo_reconstruct",
-                     "tomo_backproject", "tomo_plan_destroy"):
+                     "tomo_backproject", "tomo_plan_destroy", "tomo_autotune", "tomo_unet_create",
+                     "tomo_unet_train_step", "tomo_unet_forward", "tomo_nn_conv3x3"):
         assert required in names
 
 
@@ -103,3 +105,37 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(tomo, "_lib", None)
     with pytest.raises(ImportError):
         tomo.load_library()
+
+
+@pytest.mark.parametrize("args", [
+    (0, 32, 1, 64, 64), (7, 32, 1, 64, 64), (4, 16, 1, 64, 64), (4, 48, 1, 64, 64), (4, 32, 0, 64, 64),
+    (4, 32, 1, 60, 64), (4, 32, 1, 64, 4), (6, 64, 1, 64, 64),
+])
+def test_unet_create_rejects_bad_shapes(args):
+    _, lib = _lib()
+    h = ctypes.c_void_p(123)
+    assert lib.tomo_unet_create(*args, None, ctypes.byref(h)) == 1
+    assert h.value is None
+    assert lib.tomo_unet_last_error(None).decode()
+
+
+def test_unet_create_without_gpu_reports_no_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    _, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.tomo_unet_create(4, 32, 2, 64, 64, None, ctypes.byref(h)) == 2
+
+
+def test_nn_entry_points_validate_on_host():
+    _, lib = _lib()
+    p = ctypes.c_void_p(256)
+    # cin not a multiple of 32, NULL arrays, misaligned pointers: rejected before any launch
+    assert lib.tomo_nn_conv3x3(p, 48, p, None, p, 32, None, 0, 48, 32, 1, 4, 4, 0, None) == 1
+    assert lib.tomo_nn_conv3x3(None, 32, p, None, p, 32, None, 0, 32, 32, 1, 4, 4, 0, None) == 1
+    assert lib.tomo_nn_conv3x3(ctypes.c_void_p(258), 32, p, None, p, 32, None, 0, 32, 32, 1, 4, 4, 0, None) == 1
+    assert lib.tomo_nn_conv3x3(p, 32, p, None, p, 32, None, 0, 32, 32, 1, 4, 4, 1, None) == 1  # ReLU needs bias
+    n = ctypes.c_size_t()
+    assert lib.tomo_nn_wgrad_scratch(32, 64, 1000, ctypes.byref(n)) == 0 and n.value > 0
+    assert lib.tomo_nn_wgrad_scratch(30, 64, 1000, ctypes.byref(n)) == 1
