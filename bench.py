@@ -132,6 +132,66 @@ def cpu_baseline(wl, prob_np, iters: int = 3, slices: int = 4) -> dict:
             "host_cpus": os.cpu_count()}
 
 
+def run_learned(args) -> int:
+    """Time to a 1e-4 relative objective gap from the U-Net start against the FBP start.
+
+    2000 training and 64 held-out 512^2 slices (ellipses + Gaussian texture, 60 angles,
+    1% noise); training targets are the method's own reconstructions (300 iterations from
+    FBP); the U-Net (4 levels, 32 base channels) is trained on the GPU; both starts are run
+    on the held-out slices (solved together) and timed.  One JSON line.
+    """
+    import numpy as np
+    import synth
+    wl = synth.WORKLOADS["learned_init_512"]
+    n_train = args.train_slices
+    t0 = time.perf_counter()
+    # sinograms are made before the GPU is touched (forked workers)
+    train_s = synth.textured_batch(n_train, wl.n, wl.n_angles, wl.n_det, wl.noise, wl.seed, workers=8)
+    test_s = synth.textured_batch(wl.n_slices, wl.n, wl.n_angles, wl.n_det, wl.noise, wl.seed + 10 ** 6,
+                                  workers=8)
+    data_s = time.perf_counter() - t0
+    print(f"sinograms: {data_s:.1f} s", file=sys.stderr, flush=True)
+    import torch
+    from paper_2603_28756_amd import learned, tomo
+    dev = torch.device("cuda", 0)
+    pr = learned.Problem(wl.n, wl.n_angles, wl.n_det, synth.uniform_angles(wl.n_angles), beta=wl.beta,
+                         p=wl.p, kb_width=wl.kb_width, neighbours=wl.neighbours)
+    t0 = time.perf_counter()
+    fbp, tgt = learned.fbp_and_targets(pr, train_s, args.target_iters, dev)
+    target_s = time.perf_counter() - t0
+    print(f"targets: {target_s:.1f} s", file=sys.stderr, flush=True)
+    scale = float(torch.sqrt(torch.mean(fbp * fbp)).item())
+    net = tomo.UNet(wl.n, wl.n, levels=4, base=32, max_batch=args.batch)
+    net.set_params(learned.init_params(4, 32, 7, dev))
+    t0 = time.perf_counter()
+    losses = learned.train(net, fbp, tgt, scale, args.epochs, args.batch, args.lr, seed=7)
+    torch.cuda.synchronize()
+    train_s_time = time.perf_counter() - t0
+    print(f"training: {train_s_time:.1f} s, loss {np.mean(losses[:20]):.3e} -> {np.mean(losses[-20:]):.3e}",
+          file=sys.stderr, flush=True)
+    del fbp, tgt
+    res = learned.compare_starts(pr, test_s, net, scale, dev, long_iters=2000, net_batch=args.batch)
+    step_flop = 3 * 85.0e9 * args.batch  # forward + backward of one batch at 512^2
+    out = {
+        "metric": "time to 1e-4 relative objective gap, U-Net start (FBP start alongside)",
+        "value": res["ms"]["total_unet"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": res["ms"]["total_unet"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 network, f32 reconstruction", "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "n_angles": wl.n_angles, "n_det": wl.n_det,
+                   "noise": wl.noise, "train_slices": n_train, "test_slices": wl.n_slices,
+                   "target_iterations": args.target_iters, "unet": {"levels": 4, "base": 32},
+                   "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "neighbours": wl.neighbours},
+        "result": res,
+        "training": {"seconds": train_s_time, "steps": int(len(losses)),
+                     "ms_per_step": 1e3 * train_s_time / max(1, len(losses)),
+                     "approx_tflops": step_flop / (train_s_time / max(1, len(losses))) / 1e12,
+                     "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:]))},
+        "prep_seconds": {"sinograms": data_s, "targets": target_s},
+    }
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +204,11 @@ def main() -> int:
                     help="evaluate the prior in the inverse-row epilogue (comparison variant)")
     ap.add_argument("--concurrent-prior", action="store_true",
                     help="launch the prior kernel on its own stream beside the row/column passes")
+    ap.add_argument("--train-slices", type=int, default=2000, help="learned start: training slices")
+    ap.add_argument("--target-iters", type=int, default=300, help="learned start: target iterations")
+    ap.add_argument("--epochs", type=int, default=10, help="learned start: training epochs")
+    ap.add_argument("--batch", type=int, default=8, help="learned start: mini-batch")
+    ap.add_argument("--lr", type=float, default=1e-3, help="learned start: Adam learning rate")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile schedule instead of the autotuned one")
     ap.add_argument("--copy-calib", action="store_true",
@@ -154,6 +219,9 @@ def main() -> int:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(this build runs the one-GPU share of a slice-axis sharding)", file=sys.stderr)
         return 2
+
+    if args.workload == "learned_init_512":
+        return run_learned(args)
 
     import numpy as np
     import torch

@@ -18,6 +18,8 @@ from .phantoms import (  # noqa: F401
     ellipsoid_sinogram,
     gaussian_blob,
     gaussian_blob_sinogram,
+    textured_slice,
+    textured_batch,
     add_noise,
     make_problem,
 )

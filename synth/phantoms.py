@@ -27,7 +27,7 @@ __all__ = [
     "Workload", "WORKLOADS", "detector_bins_for", "uniform_angles", "ellipse_params",
     "ellipsoid_params", "rasterize_ellipses", "ellipse_sinogram", "ellipsoid_volume",
     "ellipsoid_sinogram", "gaussian_blob", "gaussian_blob_sinogram", "add_noise",
-    "make_problem",
+    "make_problem", "textured_slice", "textured_batch",
 ]
 
 
@@ -165,6 +165,68 @@ def gaussian_blob_sinogram(n_det: int, angles: np.ndarray, x0: float, y0: float,
     return math.sqrt(2.0 * math.pi) * s * np.exp(-((t[None, :] - tc) ** 2) / (2.0 * s * s))
 
 
+# ----------------------------------------------------------------------------- texture
+def blob_params(rng: np.random.Generator, count: int, n: int) -> np.ndarray:
+    """Texture blobs, one row each: (x0, y0, s, amplitude) in pixel units.
+
+    Draw order per blob: centre uniform in the disc of radius 0.75 N/2, width U[1.5, 6]
+    pixels, amplitude U[0.03, 0.12] with a random sign.
+    """
+    out = np.empty((count, 4), dtype=np.float64)
+    for k in range(count):
+        r = 0.75 * (n / 2.0) * math.sqrt(rng.uniform(0.0, 1.0))
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        s = rng.uniform(1.5, 6.0)
+        amp = rng.uniform(0.03, 0.12) * (1.0 if rng.uniform() < 0.5 else -1.0)
+        out[k] = (r * math.cos(ang), r * math.sin(ang), s, amp)
+    return out
+
+
+def textured_slice(n: int, n_angles: int, n_det: int, noise: float, seed: int,
+                   n_ellipses: int = 10, n_blobs: int = 48, raster: bool = True) -> dict:
+    """One slice: random ellipses plus a texture of small Gaussian blobs, its analytic
+    sinogram (chord lengths plus blob line integrals, no inverse crime) and noise."""
+    rng = rng_for(seed)
+    angles = uniform_angles(n_angles)
+    prm = ellipse_params(rng, n_ellipses)
+    blobs = blob_params(rng, n_blobs, n)
+    img = rasterize_ellipses(prm, n) if raster else None
+    g = ellipse_sinogram(prm, n, angles, n_det)
+    c = n / 2.0
+    cx = np.arange(n, dtype=np.float64) - c
+    t = np.arange(n_det, dtype=np.float64) - n_det / 2.0
+    th = angles[None, :, None]
+    x0, y0, sb, amp = (blobs[:, k][:, None, None] for k in range(4))
+    tc = x0 * np.cos(th) + y0 * np.sin(th)
+    g = g + np.sum(amp * math.sqrt(2.0 * math.pi) * sb * np.exp(-((t[None, None, :] - tc) ** 2) / (2.0 * sb * sb)),
+                   axis=0)
+    for bx, by, bs, ba in (blobs if raster else ()):
+        img += ba * np.exp(-((cx[None, :] - bx) ** 2 + (cx[:, None] - by) ** 2) / (2.0 * bs * bs))
+    return {"phantom": img, "sino": add_noise(g, rng, noise), "angles": angles}
+
+
+def _textured_sino(args):
+    n, na, nd, noise, seed = args
+    return textured_slice(n, na, nd, noise, seed, raster=False)["sino"].astype(np.float32)
+
+
+def textured_batch(count: int, n: int, n_angles: int, n_det: int, noise: float, seed0: int,
+                   workers: int = 1) -> np.ndarray:
+    """Sinograms [count, n_angles, n_det] (float32) of slices seeded seed0, seed0+1, ..."""
+    jobs = [(n, n_angles, n_det, noise, seed0 + k) for k in range(count)]
+    # worker processes are forked, which is only safe before the parent touches a GPU;
+    # afterwards (or when asked for one worker) the slices are made in this process
+    import sys
+    torch_mod = sys.modules.get("torch")
+    gpu_up = torch_mod is not None and torch_mod.cuda.is_initialized()
+    if workers <= 1 or gpu_up:
+        return np.stack([_textured_sino(j) for j in jobs])
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=min(workers, 8), mp_context=mp.get_context("fork")) as ex:
+        return np.stack(list(ex.map(_textured_sino, jobs, chunksize=8)))
+
+
 # ----------------------------------------------------------------------------- noise
 def add_noise(g: np.ndarray, rng: np.random.Generator, frac: float) -> np.ndarray:
     """g + sigma_n * N(0,1), sigma_n = frac * max(g) over the whole array."""
@@ -216,6 +278,13 @@ WORKLOADS = {
         description="64 slices of 512^2, 20 ellipsoids, 180 angles x 724 bins, 1% noise, "
                     "PSF spectrum 1024^2, KB width 6 oversampling 2, 100 iterations, "
                     "26-neighbour qGGMRF"),
+    "learned_init_512": Workload(
+        "learned_init_512", n=512, n_slices=64, n_angles=60, n_det=724, noise=0.01, seed=100000,
+        n_objects=10, iterations=(400,), neighbours=8,
+        description="learned start: 2000 training and 64 held-out 512^2 slices (10 ellipses + "
+                    "48 Gaussian texture blobs), 60 angles x 724 bins, 1% noise, 8-neighbour "
+                    "qGGMRF p=1.2 beta=0.01; time to 1e-4 relative objective gap, U-Net start "
+                    "against FBP start"),
     "hier_32x2048": Workload(
         "hier_32x2048", n=2048, n_slices=32, n_angles=91, n_det=2896, noise=0.02, seed=3,
         n_objects=20, iterations=(40, 20, 10), neighbours=26, levels=3,
