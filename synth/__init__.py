@@ -20,6 +20,7 @@ from .phantoms import (  # noqa: F401
     gaussian_blob_sinogram,
     textured_slice,
     textured_batch,
+    uneven_problems,
     add_noise,
     make_problem,
 )

@@ -27,7 +27,7 @@ __all__ = [
     "Workload", "WORKLOADS", "detector_bins_for", "uniform_angles", "ellipse_params",
     "ellipsoid_params", "rasterize_ellipses", "ellipse_sinogram", "ellipsoid_volume",
     "ellipsoid_sinogram", "gaussian_blob", "gaussian_blob_sinogram", "add_noise",
-    "make_problem", "textured_slice", "textured_batch",
+    "make_problem", "textured_slice", "textured_batch", "uneven_problems",
 ]
 
 
@@ -225,6 +225,29 @@ def textured_batch(count: int, n: int, n_angles: int, n_det: int, noise: float, 
     import multiprocessing as mp
     with cf.ProcessPoolExecutor(max_workers=min(workers, 8), mp_context=mp.get_context("fork")) as ex:
         return np.stack(list(ex.map(_textured_sino, jobs, chunksize=8)))
+
+
+# ----------------------------------------------------------------------------- uneven batch
+def uneven_problems(count: int, seed: int, sizes=(128, 192, 256, 384, 512, 768, 1024),
+                    angle_range=(30, 360), noise_range=(0.01, 0.05), n_objects: int = 10) -> list:
+    """Independent single-slice problems of uneven size: per problem, draw N uniformly from
+    `sizes`, the angle count uniformly from the integers in angle_range and the noise
+    fraction uniformly from noise_range; 10 random ellipses; n_det = round(N sqrt 2), even.
+    Returns dicts with n, n_angles, n_det, noise, angles and the float32 sinogram
+    [1, n_angles, n_det]."""
+    rng = rng_for(seed)
+    out = []
+    for _ in range(count):
+        n = int(sizes[rng.integers(0, len(sizes))])
+        na = int(rng.integers(angle_range[0], angle_range[1] + 1))
+        noise = float(rng.uniform(*noise_range))
+        nd = detector_bins_for(n)
+        angles = uniform_angles(na)
+        prm = ellipse_params(rng, n_objects)
+        g = add_noise(ellipse_sinogram(prm, n, angles, nd), rng, noise)
+        out.append({"n": n, "n_angles": na, "n_det": nd, "noise": noise, "angles": angles,
+                    "sino": g[None].astype(np.float32)})
+    return out
 
 
 # ----------------------------------------------------------------------------- noise
