@@ -45,7 +45,7 @@ extern "C" {
 typedef struct tomo_unet_s* tomo_unet;
 
 /* Create a network for images of height x width (multiples of 2^(levels-1)) and batches
- * up to max_batch.  levels 1..6; base_channels a multiple of 32 with
+ * up to max_batch.  levels 1..6; base_channels a multiple of 32, at most 256, with
  * base_channels 2^(levels-1) <= 1024.  Errors: INVALID_ARG, NO_DEVICE. */
 tomo_status tomo_unet_create(int32_t levels, int32_t base_channels, int32_t max_batch,
                              int32_t height, int32_t width, void* hip_stream, tomo_unet* out);

@@ -318,9 +318,10 @@ tomo_status tomo_unet_create(int32_t levels, int32_t base_channels, int32_t max_
   if (!out) return nfail(nullptr, TOMO_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (levels < 1 || levels > 6) return nfail(nullptr, TOMO_ERR_INVALID_ARG, "levels %d outside 1..6", levels);
-  if (base_channels < 32 || base_channels % 32 || (base_channels << (levels - 1)) > 1024)
-    return nfail(nullptr, TOMO_ERR_INVALID_ARG, "base channels %d: a multiple of 32, at most 1024 at the bottom",
-                 base_channels);
+  if (base_channels < 32 || base_channels > 256 || base_channels % 32 ||
+      (base_channels << (levels - 1)) > 1024)
+    return nfail(nullptr, TOMO_ERR_INVALID_ARG,
+                 "base channels %d: a multiple of 32 in 32..256, at most 1024 at the bottom", base_channels);
   if (max_batch < 1) return nfail(nullptr, TOMO_ERR_INVALID_ARG, "max_batch must be >= 1");
   const int div = 1 << (levels - 1);
   if (height < div || width < div || height % div || width % div)

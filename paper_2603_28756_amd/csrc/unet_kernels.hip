@@ -90,6 +90,102 @@ conv3x3_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restri
   }
 }
 
+// 3x3 conv on 2D pixel tiles staged through LDS.  A block owns a tile 16 pixels wide and
+// 4*RPW rows high (wave w: rows w*RPW .. w*RPW+RPW-1) x BN output channels.  For each chunk
+// of 32 input channels it stages (a) the input tile with a one-pixel halo, 64 bytes per
+// pixel, and (b) the weights of all 9 taps for its BN channels, then every wave runs
+// 9 taps x RPW rows x BN/16 MFMAs reading both operands from LDS (each 16-pixel A fragment
+// and each 16-channel B fragment is one contiguous kilobyte: no bank conflicts).
+template <int BN, int RPW>
+struct ConvTile {
+  static constexpr int TW = 16, TH = 4 * RPW, HW_ = TW + 2, HH = TH + 2;
+  static constexpr int A_PIX = HH * HW_;                 // halo pixels
+  static constexpr int A_BYTES = A_PIX * 64;              // 32 bf16 channels per pixel
+  static constexpr int B_BYTES = 9 * BN * 64;             // [tap][co][32 channels]
+  static constexpr int BYTES = A_BYTES + B_BYTES;
+};
+
+template <int BN, int RPW, bool RELU, bool BIAS, bool MASK>
+__global__ void __launch_bounds__(256)
+conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
+                    const float* __restrict__ bias, uint16_t* __restrict__ y, int ldy,
+                    const uint16_t* __restrict__ mask, int ldm, int cin, int H, int W, int ntx,
+                    int nty) {
+  using T = ConvTile<BN, RPW>;
+  constexpr int NJ = BN / 16;
+  __shared__ __align__(16) unsigned char smem[T::BYTES];
+  uint16_t* sa = reinterpret_cast<uint16_t*>(smem);
+  uint16_t* sb = reinterpret_cast<uint16_t*>(smem + T::A_BYTES);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  int bx = blockIdx.x;
+  const int tx = bx % ntx;
+  bx /= ntx;
+  const int ty = bx % nty;
+  const int cot = bx / nty;
+  const int x0 = tx * T::TW, y0 = ty * T::TH, co0 = cot * BN;
+  const size_t img = (size_t)blockIdx.y * H * W;
+  const int kq = (lane >> 4) * 8, lc = lane & 15;
+  f32x4 acc[RPW][NJ];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < cin; c0 += 32) {
+    // stage the input halo tile: A_PIX pixels x 4 chunks of 8 channels
+    for (int e = t; e < T::A_PIX * 4; e += 256) {
+      const int pix = e >> 2, q = (e & 3) * 8;
+      const int hy = pix / T::HW_, hx = pix - hy * T::HW_;
+      const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = ld8(x + (img + (size_t)gy * W + gx) * ldx + c0 + q);
+      st8(sa + pix * 32 + q, v);
+    }
+    // stage the weights of the 9 taps: [tap][co][32]
+    for (int e = t; e < 9 * BN * 4; e += 256) {
+      const int q = (e & 3) * 8, rest = e >> 2;
+      const int co = rest % BN, tap = rest / BN;
+      st8(sb + (tap * BN + co) * 32 + q, ld8(w + ((size_t)(co0 + co) * 9 + tap) * cin + c0 + q));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      u16x8 b[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = ld8(sb + (tap * BN + j * 16 + lc) * 32 + kq);
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const u16x8 a = ld8(sa + ((wave * RPW + r + ky) * T::HW_ + lc + kx) * 32 + kq);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[r][j] = mfma(a, b[j], acc[r][j]);
+      }
+    }
+    __syncthreads();
+  }
+  // lane holds pixels x0 + 4*(lane>>4) + i of row y0 + wave*RPW + r, channel co0 + 16j + lc
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int gy = y0 + wave * RPW + r;
+    if (gy >= H) continue;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int co = co0 + 16 * j + lc;
+      const float bv = BIAS ? bias[co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gx = x0 + 4 * (lane >> 4) + i;
+        if (gx < W) {
+          const size_t pix = img + (size_t)gy * W + gx;
+          float v = acc[r][j][i] + bv;
+          if (RELU) v = fmaxf(v, 0.f);
+          if (MASK && !(bf2f(mask[pix * ldm + co]) > 0.f)) v = 0.f;
+          y[pix * ldy + co] = f2bf(v);
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ 3x3 conv, weights
 // part[s][co][n] = sum over the pixels of split s of dz[p, co] x[p + tap(n), ci(n)],
 // n = tap * cin + ci; partb[s][co] = sum over the same pixels of dz[p, co].  A block owns a
@@ -179,14 +275,18 @@ __global__ void sum_splits_kernel(const float* __restrict__ part, int nsplit, si
 
 // ------------------------------------------------- first layer (one input channel), fp32
 // y[p, co] = relu(b[co] + sum_tap w[co][tap] u[p + tap]), u = fbp * inv_s; a thread makes
-// 8 channels of one pixel.
-__global__ void conv_in_kernel(const float* __restrict__ fbp, float inv_s,
-                               const float* __restrict__ w, const float* __restrict__ bias,
-                               uint16_t* __restrict__ y, int cout, int H, int W, int npx) {
-  const int g8 = cout / 8;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)npx * g8) return;
-  const int p = (int)(idx / g8), c0 = (int)(idx - (size_t)p * g8) * 8;
+// all channels of one pixel (weights and biases from LDS).
+constexpr int CIN_MAXC = 256;
+__global__ void __launch_bounds__(256)
+conv_in_kernel(const float* __restrict__ fbp, float inv_s, const float* __restrict__ w,
+               const float* __restrict__ bias, uint16_t* __restrict__ y, int cout, int H, int W,
+               int npx) {
+  __shared__ float sw[CIN_MAXC * 10];
+  for (int e = threadIdx.x; e < cout * 10; e += blockDim.x)
+    sw[e] = (e % 10) < 9 ? w[(e / 10) * 9 + e % 10] : bias[e / 10];
+  __syncthreads();
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
   const int HW = H * W, b = p / HW, rem = p - b * HW, r = rem / W, c = rem - r * W;
   float u[9];
 #pragma unroll
@@ -195,15 +295,18 @@ __global__ void conv_in_kernel(const float* __restrict__ fbp, float inv_s,
     u[tap] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
                  ? fbp[(size_t)b * HW + (size_t)yy * W + xx] * inv_s : 0.f;
   }
-  u16x8 out;
+  for (int c0 = 0; c0 < cout; c0 += 8) {
+    u16x8 out;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    float a = bias[c0 + j];
+    for (int j = 0; j < 8; ++j) {
+      const float* wj = sw + (c0 + j) * 10;
+      float a = wj[9];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) a = fmaf(w[(c0 + j) * 9 + tap], u[tap], a);
-    out[j] = f2bf(fmaxf(a, 0.f));
+      for (int tap = 0; tap < 9; ++tap) a = fmaf(wj[tap], u[tap], a);
+      out[j] = f2bf(fmaxf(a, 0.f));
+    }
+    st8(y + (size_t)p * cout + c0, out);
   }
-  st8(y + (size_t)p * cout + c0, out);
 }
 
 // part[blk][co*10 + k] (k < 9: weight of tap k, k = 9: bias) over the pixels of block blk
@@ -395,14 +498,23 @@ head_back_kernel(const float* __restrict__ r, const float* __restrict__ fbp,
   }
 }
 
-// fixed-order sums of head_back partials: loss (mean), head weight and bias gradients
-__global__ void head_reduce_kernel(const double* __restrict__ part, int nblk, int C, int npx,
-                                   float* __restrict__ ghw, float* __restrict__ ghb,
-                                   double* __restrict__ loss) {
-  const int k = threadIdx.x;
-  if (k >= C + 2) return;
+// fixed-order sums of head_back partials (block k sums column k): loss (mean), head weight
+// and bias gradients
+__global__ void __launch_bounds__(256)
+head_reduce_kernel(const double* __restrict__ part, int nblk, int C, int npx,
+                   float* __restrict__ ghw, float* __restrict__ ghb, double* __restrict__ loss) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x, t = threadIdx.x;
   double a = 0.0;
-  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * (C + 2) + k];
+  for (int b = t; b < nblk; b += 256) a += part[(size_t)b * (C + 2) + k];
+  sh[t] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) sh[t] += sh[t + o];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  a = sh[0];
   if (k == 0) {
     if (loss) *loss = a / npx;
   } else if (k == 1) {
@@ -454,26 +566,27 @@ hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float
                       int B, int H, int W, bool relu, hipStream_t st) {
   if (cin % 32 || cout % 32 || ldx % 8 || ldy < cout || B < 1 || H < 1 || W < 1)
     return hipErrorInvalidValue;
-  const int ntx = (W + CV_PX - 1) / CV_PX;
-  const int cot = cout % 64 == 0 ? 64 : 32;
-  const dim3 grid(ntx * (cout / cot), H, B);
-#define CV(COT, R, BI, M)                                                                   \
-  hipLaunchKernelGGL((conv3x3_kernel<COT, R, BI, M>), grid, dim3(256), 0, st, x, ldx, w, bias, \
-                     y, ldy, mask, ldm, cin, H, W, ntx)
   const bool bi = bias != nullptr, m = mask != nullptr;
-  if (cot == 64) {
-    if (relu && bi && !m) CV(64, true, true, false);
-    else if (!relu && !bi && m) CV(64, false, false, true);
-    else if (!relu && !bi && !m) CV(64, false, false, false);
-    else if (!relu && bi && !m) CV(64, false, true, false);
-    else return hipErrorInvalidValue;
+  const int ntx = (W + 15) / 16;
+  // 64 output channels per block when they divide cout, else 32; 4 rows per wave
+#define CV(BN, RPW, R, BI, M)                                                                   \
+  do {                                                                                          \
+    const int nty = (H + 4 * RPW - 1) / (4 * RPW);                                              \
+    hipLaunchKernelGGL((conv3x3_tile_kernel<BN, RPW, R, BI, M>), dim3(ntx * nty * (cout / BN), B), \
+                       dim3(256), 0, st, x, ldx, w, bias, y, ldy, mask, ldm, cin, H, W, ntx, nty); \
+  } while (0)
+#define CV_FORMS(BN, RPW)                                      \
+  if (relu && bi && !m) CV(BN, RPW, true, true, false);        \
+  else if (!relu && !bi && m) CV(BN, RPW, false, false, true); \
+  else if (!relu && !bi && !m) CV(BN, RPW, false, false, false); \
+  else if (!relu && bi && !m) CV(BN, RPW, false, true, false); \
+  else return hipErrorInvalidValue;
+  if (cout % 64 == 0) {
+    CV_FORMS(64, 4)
   } else {
-    if (relu && bi && !m) CV(32, true, true, false);
-    else if (!relu && !bi && m) CV(32, false, false, true);
-    else if (!relu && !bi && !m) CV(32, false, false, false);
-    else if (!relu && bi && !m) CV(32, false, true, false);
-    else return hipErrorInvalidValue;
+    CV_FORMS(32, 4)
   }
+#undef CV_FORMS
 #undef CV
   return hipGetLastError();
 }
@@ -515,8 +628,8 @@ hipError_t nn_conv3x3_wgrad(const uint16_t* dz, int ldz, const uint16_t* x, int 
 
 hipError_t nn_conv_in(const float* fbp, float inv_s, const float* w, const float* bias,
                       uint16_t* y, int cout, int B, int H, int W, hipStream_t st) {
-  if (cout % 8) return hipErrorInvalidValue;
-  const size_t n = (size_t)B * H * W * (cout / 8);
+  if (cout % 8 || cout > CIN_MAXC) return hipErrorInvalidValue;
+  const size_t n = (size_t)B * H * W;
   hipLaunchKernelGGL(conv_in_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, fbp, inv_s, w,
                      bias, y, cout, H, W, B * H * W);
   return hipGetLastError();
@@ -585,8 +698,8 @@ hipError_t nn_head_back(const float* r, const float* fbp, const float* target, f
   const int nb = nn_head_back_blocks(npx);
   hipLaunchKernelGGL(head_back_kernel, dim3(nb), dim3(256), 0, st, r, fbp, target, inv_s, d, hw, dd,
                      part, C, npx);
-  hipLaunchKernelGGL(head_reduce_kernel, dim3(1), dim3(((C + 2 + 63) / 64) * 64), 0, st, part, nb, C,
-                     npx, ghw, ghb, loss);
+  hipLaunchKernelGGL(head_reduce_kernel, dim3(C + 2), dim3(256), 0, st, part, nb, C, npx, ghw, ghb,
+                     loss);
   return hipGetLastError();
 }
 

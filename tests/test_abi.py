@@ -109,7 +109,7 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("args", [
     (0, 32, 1, 64, 64), (7, 32, 1, 64, 64), (4, 16, 1, 64, 64), (4, 48, 1, 64, 64), (4, 32, 0, 64, 64),
-    (4, 32, 1, 60, 64), (4, 32, 1, 64, 4), (6, 64, 1, 64, 64),
+    (4, 32, 1, 60, 64), (4, 32, 1, 64, 4), (6, 64, 1, 64, 64), (1, 288, 1, 64, 64),
 ])
 def test_unet_create_rejects_bad_shapes(args):
     _, lib = _lib()
