@@ -12,9 +12,15 @@ namespace tomo {
 // 3x3 convolution, zero padding: y = act(bias + conv(x, w)) (* (mask > 0) when mask != NULL).
 // w: bfloat16 [cout][3][3][cin].  Supported forms: ReLU with bias, plain with bias, plain
 // without bias (optionally masked).
+// With xu != NULL (ReLU form only) the input is the concatenation [up2(xu), x]: channels
+// 0..cu-1 come from xu (half resolution, channel stride ldu), the rest from x.  With
+// pool != NULL (ReLU form, even H and W) the 2x2 average of the output is also written to
+// pool (half resolution, channel stride ldp).
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float* bias,
                       uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
-                      int B, int H, int W, bool relu, hipStream_t st);
+                      int B, int H, int W, bool relu, hipStream_t st,
+                      const uint16_t* xu = nullptr, int ldu = 0, int cu = 0,
+                      uint16_t* pool = nullptr, int ldp = 0);
 
 struct WgradPlan {
   int ntn = 0, ntc = 0, nsplit = 0, px_per_split = 0;

@@ -189,7 +189,9 @@ tomo_status prep_weights(tomo_unet u) {
   return TOMO_OK;
 }
 
-tomo_status forward(tomo_unet u, const float* fbp, float* x0, int B, float s) {
+// keep_cat: materialise the concatenation buffers (the backward pass reads them); without
+// it the decoder convolutions read the upsampled half of their input directly.
+tomo_status forward(tomo_unet u, const float* fbp, float* x0, int B, float s, bool keep_cat) {
   hipStream_t st = u->stream;
   const float* th = u->theta();
   const int L = u->L;
@@ -199,10 +201,7 @@ tomo_status forward(tomo_unet u, const float* fbp, float* x0, int B, float s) {
   for (int l = 0; l < L; ++l) {
     const auto& v = u->lv[l];
     if (l > 0) {
-      int lde;
-      const uint16_t* ep = u->E(l - 1, &lde);
-      const auto& vp = u->lv[l - 1];
-      NCHK(u, nn_avgpool2(ep, lde, u->at<uint16_t>(v.P), u->ch(l - 1), u->ch(l - 1), B, vp.h, vp.w, st));
+      // P_l was written by the epilogue of the conv that produced E_{l-1}
       const auto& c = cv[2 * l];
       NCHK(u, nn_conv3x3(u->at<uint16_t>(v.P), u->ch(l - 1), u->at<uint16_t>(c.wbf), th + c.b,
                          u->at<uint16_t>(v.Ea), v.c, nullptr, 0, c.cin, c.cout, B, v.h, v.w, true, st));
@@ -210,17 +209,25 @@ tomo_status forward(tomo_unet u, const float* fbp, float* x0, int B, float s) {
     int lde;
     uint16_t* ep = u->E(l, &lde);
     const auto& c = cv[2 * l + 1];
+    uint16_t* pnext = l + 1 < L ? u->at<uint16_t>(u->lv[l + 1].P) : nullptr;
     NCHK(u, nn_conv3x3(u->at<uint16_t>(v.Ea), v.c, u->at<uint16_t>(c.wbf), th + c.b, ep, lde,
-                       nullptr, 0, c.cin, c.cout, B, v.h, v.w, true, st));
+                       nullptr, 0, c.cin, c.cout, B, v.h, v.w, true, st, nullptr, 0, 0, pnext, v.c));
   }
   int k = 2 * L;
   for (int l = L - 2; l >= 0; --l, k += 2) {
     const auto& v = u->lv[l];
     const int cu = u->ch(l + 1), ld = u->catld(l);
-    NCHK(u, nn_up2(u->D(l + 1), cu, u->at<uint16_t>(v.cat), ld, cu, B, v.h, v.w, st));
     const auto& ca = cv[k];
-    NCHK(u, nn_conv3x3(u->at<uint16_t>(v.cat), ld, u->at<uint16_t>(ca.wbf), th + ca.b,
-                       u->at<uint16_t>(v.Da), v.c, nullptr, 0, ca.cin, ca.cout, B, v.h, v.w, true, st));
+    if (keep_cat) {
+      NCHK(u, nn_up2(u->D(l + 1), cu, u->at<uint16_t>(v.cat), ld, cu, B, v.h, v.w, st));
+      NCHK(u, nn_conv3x3(u->at<uint16_t>(v.cat), ld, u->at<uint16_t>(ca.wbf), th + ca.b,
+                         u->at<uint16_t>(v.Da), v.c, nullptr, 0, ca.cin, ca.cout, B, v.h, v.w, true, st));
+    } else {
+      int lde;
+      const uint16_t* ep = u->E(l, &lde);
+      NCHK(u, nn_conv3x3(ep, lde, u->at<uint16_t>(ca.wbf), th + ca.b, u->at<uint16_t>(v.Da), v.c,
+                         nullptr, 0, ca.cin, ca.cout, B, v.h, v.w, true, st, u->D(l + 1), cu, cu));
+    }
     const auto& cb = cv[k + 1];
     NCHK(u, nn_conv3x3(u->at<uint16_t>(v.Da), v.c, u->at<uint16_t>(cb.wbf), th + cb.b,
                        u->at<uint16_t>(v.D), v.c, nullptr, 0, cb.cin, cb.cout, B, v.h, v.w, true, st));
@@ -389,14 +396,14 @@ tomo_status tomo_unet_get_params(tomo_unet u, float* theta) {
 tomo_status tomo_unet_forward(tomo_unet u, const float* fbp, float* x0, int32_t batch, float scale) {
   if (tomo_status s = ready(u, true); s != TOMO_OK) return s;
   if (tomo_status s = check_call(u, fbp, x0, batch, scale); s != TOMO_OK) return s;
-  return forward(u, fbp, x0, batch, scale);
+  return forward(u, fbp, x0, batch, scale, false);
 }
 
 tomo_status tomo_unet_loss_grad(tomo_unet u, const float* fbp, const float* target, int32_t batch,
                                 float scale, float* grad, double* loss) {
   if (tomo_status s = ready(u, true); s != TOMO_OK) return s;
   if (tomo_status s = check_call(u, fbp, target, batch, scale); s != TOMO_OK) return s;
-  tomo_status s = forward(u, fbp, nullptr, batch, scale);
+  tomo_status s = forward(u, fbp, nullptr, batch, scale, true);
   if (s == TOMO_OK) s = backward(u, fbp, target, batch, scale, loss ? loss : u->at<double>(u->off_loss));
   if (s == TOMO_OK && grad)
     NCHK(u, hipMemcpyAsync(grad, u->grad(), u->n_params * 4, hipMemcpyDeviceToDevice, u->stream));
@@ -408,7 +415,7 @@ tomo_status tomo_unet_train_step(tomo_unet u, const float* fbp, const float* tar
   if (tomo_status s = ready(u, true); s != TOMO_OK) return s;
   if (tomo_status s = check_call(u, fbp, target, batch, scale); s != TOMO_OK) return s;
   if (!(lr > 0.f) || !std::isfinite(lr)) return nfail(u, TOMO_ERR_INVALID_ARG, "learning rate must be > 0");
-  tomo_status s = forward(u, fbp, nullptr, batch, scale);
+  tomo_status s = forward(u, fbp, nullptr, batch, scale, true);
   if (s == TOMO_OK) s = backward(u, fbp, target, batch, scale, loss ? loss : u->at<double>(u->off_loss));
   if (s != TOMO_OK) return s;
   u->step += 1;

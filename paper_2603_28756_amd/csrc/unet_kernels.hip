@@ -105,12 +105,17 @@ struct ConvTile {
   static constexpr int BYTES = A_BYTES + B_BYTES;
 };
 
-template <int BN, int RPW, bool RELU, bool BIAS, bool MASK>
+// UPCAT: the input is the concatenation [up2(xu), x]: channels below cu are read from the
+// half-resolution tensor xu at (row/2, column/2), the others from x (channel c - cu).
+// POOL: also write the 2x2 average of the (bfloat16-rounded) output to pool (channel
+// stride ldp, half resolution); every 2x2 block lies in one lane (4 rows x 4 columns).
+template <int BN, int RPW, bool RELU, bool BIAS, bool MASK, bool UPCAT, bool POOL>
 __global__ void __launch_bounds__(256)
 conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
                     const float* __restrict__ bias, uint16_t* __restrict__ y, int ldy,
                     const uint16_t* __restrict__ mask, int ldm, int cin, int H, int W, int ntx,
-                    int nty) {
+                    int nty, const uint16_t* __restrict__ xu, int ldu, int cu,
+                    uint16_t* __restrict__ pool, int ldp) {
   using T = ConvTile<BN, RPW>;
   constexpr int NJ = BN / 16;
   __shared__ __align__(16) unsigned char smem[T::BYTES];
@@ -137,7 +142,12 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
       const int hy = pix / T::HW_, hx = pix - hy * T::HW_;
       const int gy = y0 + hy - 1, gx = x0 + hx - 1;
       u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = ld8(x + (img + (size_t)gy * W + gx) * ldx + c0 + q);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        if (UPCAT && c0 < cu)
+          v = ld8(xu + (((size_t)blockIdx.y * (H / 2) + gy / 2) * (W / 2) + gx / 2) * ldu + c0 + q);
+        else
+          v = ld8(x + (img + (size_t)gy * W + gx) * ldx + c0 - (UPCAT ? cu : 0) + q);
+      }
       st8(sa + pix * 32 + q, v);
     }
     // stage the weights of the 9 taps: [tap][co][32]
@@ -163,10 +173,10 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
     __syncthreads();
   }
   // lane holds pixels x0 + 4*(lane>>4) + i of row y0 + wave*RPW + r, channel co0 + 16j + lc
+  uint16_t ob[RPW][NJ][4];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int gy = y0 + wave * RPW + r;
-    if (gy >= H) continue;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int co = co0 + 16 * j + lc;
@@ -174,12 +184,35 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gx = x0 + 4 * (lane >> 4) + i;
-        if (gx < W) {
+        ob[r][j][i] = 0;
+        if (gy < H && gx < W) {
           const size_t pix = img + (size_t)gy * W + gx;
           float v = acc[r][j][i] + bv;
           if (RELU) v = fmaxf(v, 0.f);
           if (MASK && !(bf2f(mask[pix * ldm + co]) > 0.f)) v = 0.f;
-          y[pix * ldy + co] = f2bf(v);
+          ob[r][j][i] = f2bf(v);
+          y[pix * ldy + co] = ob[r][j][i];
+        }
+      }
+    }
+  }
+  if constexpr (POOL) {
+    const int h2 = H / 2, w2 = W / 2;
+#pragma unroll
+    for (int r = 0; r < RPW; r += 2) {
+      const int py = (y0 + wave * RPW + r) / 2;
+      if (py >= h2) continue;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int co = co0 + 16 * j + lc;
+#pragma unroll
+        for (int i = 0; i < 4; i += 2) {
+          const int px2 = (x0 + 4 * (lane >> 4) + i) / 2;
+          if (px2 < w2) {
+            const float sm = bf2f(ob[r][j][i]) + bf2f(ob[r][j][i + 1]) + bf2f(ob[r + 1][j][i]) +
+                             bf2f(ob[r + 1][j][i + 1]);
+            pool[(((size_t)blockIdx.y * h2 + py) * w2 + px2) * ldp + co] = f2bf(0.25f * sm);
+          }
         }
       }
     }
@@ -563,23 +596,31 @@ unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 // ------------------------------------------------------------------------------ launchers
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float* bias,
                       uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
-                      int B, int H, int W, bool relu, hipStream_t st) {
+                      int B, int H, int W, bool relu, hipStream_t st, const uint16_t* xu, int ldu,
+                      int cu, uint16_t* pool, int ldp) {
   if (cin % 32 || cout % 32 || ldx % 8 || ldy < cout || B < 1 || H < 1 || W < 1)
     return hipErrorInvalidValue;
-  const bool bi = bias != nullptr, m = mask != nullptr;
+  if (xu && (cu % 32 || cu <= 0 || cu >= cin || ldu % 8 || H % 2 || W % 2)) return hipErrorInvalidValue;
+  if (pool && (H % 2 || W % 2 || ldp < cout || ldp % 8 || !relu || !bias || mask))
+    return hipErrorInvalidValue;
+  const bool bi = bias != nullptr, m = mask != nullptr, up = xu != nullptr, pl = pool != nullptr;
   const int ntx = (W + 15) / 16;
   // 64 output channels per block when they divide cout, else 32; 4 rows per wave
-#define CV(BN, RPW, R, BI, M)                                                                   \
-  do {                                                                                          \
-    const int nty = (H + 4 * RPW - 1) / (4 * RPW);                                              \
-    hipLaunchKernelGGL((conv3x3_tile_kernel<BN, RPW, R, BI, M>), dim3(ntx * nty * (cout / BN), B), \
-                       dim3(256), 0, st, x, ldx, w, bias, y, ldy, mask, ldm, cin, H, W, ntx, nty); \
+#define CV(BN, RPW, R, BI, M, U, PO)                                                              \
+  do {                                                                                            \
+    const int nty = (H + 4 * RPW - 1) / (4 * RPW);                                                \
+    hipLaunchKernelGGL((conv3x3_tile_kernel<BN, RPW, R, BI, M, U, PO>),                            \
+                       dim3(ntx * nty * (cout / BN), B), dim3(256), 0, st, x, ldx, w, bias, y, ldy, \
+                       mask, ldm, cin, H, W, ntx, nty, xu, ldu, cu, pool, ldp);                   \
   } while (0)
-#define CV_FORMS(BN, RPW)                                      \
-  if (relu && bi && !m) CV(BN, RPW, true, true, false);        \
-  else if (!relu && !bi && m) CV(BN, RPW, false, false, true); \
-  else if (!relu && !bi && !m) CV(BN, RPW, false, false, false); \
-  else if (!relu && bi && !m) CV(BN, RPW, false, true, false); \
+#define CV_FORMS(BN, RPW)                                                        \
+  if (relu && bi && !m && up && !pl) CV(BN, RPW, true, true, false, true, false); \
+  else if (up) return hipErrorInvalidValue;                                      \
+  else if (relu && bi && !m && pl) CV(BN, RPW, true, true, false, false, true);  \
+  else if (relu && bi && !m) CV(BN, RPW, true, true, false, false, false);       \
+  else if (!relu && !bi && m) CV(BN, RPW, false, false, true, false, false);     \
+  else if (!relu && !bi && !m) CV(BN, RPW, false, false, false, false, false);   \
+  else if (!relu && bi && !m) CV(BN, RPW, false, true, false, false, false);     \
   else return hipErrorInvalidValue;
   if (cout % 64 == 0) {
     CV_FORMS(64, 4)
