@@ -375,16 +375,34 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
   for (int cs = wave * G + g; cs < CB; cs += 4 * G) {
     const idx_t cell = cell0 + cs;
     float ar = 0.f, ai = 0.f;
-    if (cell < cells) {
+    if (cell < cells && zi < nzb) {
       const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
-      for (int k = k0; k < k1; ++k) {
-        const int pp = idx[k];
-        float w = wts[k];
-        if (lscale) w *= lscale[pp % nl];
-        if (zi < nzb) {
-          const cpx<float> v = vals[(idx_t)pp * nz + z0 + zi];
-          ar += w * v.re;
-          ai += w * v.im;
+      // eight entries per step: their indices and weights first, then eight independent
+      // value loads in flight (cells near the origin have lists of ~n_angles * W entries);
+      // the sum still runs in list order
+      constexpr int U = 8;
+      for (int k = k0; k < k1; k += U) {
+        int pp[U];
+        float w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool in = k + u < k1;
+          pp[u] = in ? idx[k + u] : 0;
+          w[u] = in ? wts[k + u] : 0.f;
+        }
+        if (lscale) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) w[u] *= lscale[pp[u] % nl];
+        }
+        cpx<float> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = vals[(idx_t)pp[u] * nz + z0 + zi];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (k + u < k1) {
+            ar += w[u] * v[u].re;
+            ai += w[u] * v[u].im;
+          }
         }
       }
     }
@@ -399,6 +417,8 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
   }
 }
 
+constexpr int SPREAD_ANG_LDS = 2048;
+
 // Gather-spread: H[z][iy][ix] = sum over samples p whose footprint covers cell (ix, iy)
 // of wx[p][ix - g0x] wy[p][iy - g0y] c[z][p], grid index = frequency mod M.
 template <typename T, int ZB, bool CONST>
@@ -407,6 +427,17 @@ spread_kernel(const cpx<T>* __restrict__ vals, cpx<T>* __restrict__ grid,
               const double* __restrict__ atab, const int2* __restrict__ g0,
               const T* __restrict__ wx, const T* __restrict__ wy, int M, int nd, int n_angles,
               int W, int z0, int nzb, idx_t slice_pts, T const_val) {
+  // per-angle grid steps and their reciprocals, once per block (bounds by multiplication)
+  __shared__ float4 ang[SPREAD_ANG_LDS];
+  const float step = (float)M / (float)nd;
+  const bool tab = n_angles <= SPREAD_ANG_LDS;
+  if (tab) {
+    for (int i = threadIdx.x; i < n_angles; i += 256) {
+      const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
+      ang[i] = make_float4(cx, cy, fabsf(cx) > 1e-6f ? 1.f / cx : 0.f, fabsf(cy) > 1e-6f ? 1.f / cy : 0.f);
+    }
+    __syncthreads();
+  }
   const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
   if (cell >= (idx_t)M * M) return;
   const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
@@ -414,8 +445,7 @@ spread_kernel(const cpx<T>* __restrict__ vals, cpx<T>* __restrict__ grid,
   const int gx = ix < half ? ix : ix - M;
   const int gy = iy < half ? iy : iy - M;
   const int nl = nd - 1, lmax = nd / 2 - 1;
-  const float step = (float)M / (float)nd;
-  const float hw = 0.5f * (float)W + 1.5f;
+  const float hw = 0.5f * (float)W + 1.5f;  // 1.5 cells of slack over the footprint half-width
   const float reach = (float)half + hw;
 
   T ar[ZB], ai[ZB];
@@ -429,17 +459,23 @@ spread_kernel(const cpx<T>* __restrict__ vals, cpx<T>* __restrict__ grid,
       const int gyp = gy + sy * M;
       if (fabsf((float)gyp) > reach) continue;
       for (int i = 0; i < n_angles; ++i) {
-        const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
+        float4 a4;
+        if (tab) {
+          a4 = ang[i];
+        } else {
+          const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
+          a4 = make_float4(cx, cy, fabsf(cx) > 1e-6f ? 1.f / cx : 0.f, fabsf(cy) > 1e-6f ? 1.f / cy : 0.f);
+        }
         float lo = (float)(-lmax), hi = (float)lmax;
-        if (fabsf(cx) > 1e-6f) {
-          const float a = ((float)gxp - hw) / cx, b = ((float)gxp + hw) / cx;
+        if (fabsf(a4.x) > 1e-6f) {
+          const float a = ((float)gxp - hw) * a4.z, b = ((float)gxp + hw) * a4.z;
           lo = fmaxf(lo, fminf(a, b));
           hi = fminf(hi, fmaxf(a, b));
         } else if (fabsf((float)gxp) > hw) {
           continue;
         }
-        if (fabsf(cy) > 1e-6f) {
-          const float a = ((float)gyp - hw) / cy, b = ((float)gyp + hw) / cy;
+        if (fabsf(a4.y) > 1e-6f) {
+          const float a = ((float)gyp - hw) * a4.w, b = ((float)gyp + hw) * a4.w;
           lo = fmaxf(lo, fminf(a, b));
           hi = fminf(hi, fmaxf(a, b));
         } else if (fabsf((float)gyp) > hw) {
