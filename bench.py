@@ -12,12 +12,16 @@ value = N^2 * n_slices * iterations / (seconds per step)   [gradient voxel-updat
 
 roofline: the kernel class with the largest share of the step is timed live with
 HIP events on the plan's stream over a second pass of the same steps (events turn
-off graph replay, so they are kept out of the timed region).  For the transform
-passes its algorithmic bytes per launch over its mean launch time are compared with
-the 8 TB/s HBM peak; the prior kernel is bound by vector-ALU issue, so its
-algorithmic VALU lane-operations per launch (transcendentals weighted 4, their issue
-cost) over its mean launch time are compared with the chip's non-packed FP32 VALU
-issue rate, 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
+off graph replay, so they are kept out of the timed region).  For passes R and R' the
+algorithmic bytes per launch over the mean launch time are compared with the 8 TB/s
+HBM peak; pass C (two length-P FFTs per column) is bound by vector-ALU work, so its FFT
+flops (5 P log2 P per transform) per launch over its mean launch time are
+compared with the non-packed FP32 vector peak, 256 CUs x 64 lanes x 2 x 2.4 GHz =
+78.6 TFLOP/s; the prior kernel is bound by vector-ALU issue, so its
+algorithmic VALU lane-operations per launch (transcendentals weighted 2, their issue
+cost on gfx950 as measured by paper_2603_28756_amd/lib/valu_probe) over its mean launch
+time are compared with the chip's non-packed FP32 VALU issue rate,
+256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
 cpu_baseline: the FP64 oracle's own iteration (Toeplitz product by numpy FFTs,
 prior, update) timed on a bounded slab of the same volume on the host.
 """
@@ -36,6 +40,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-operations per second, packed FP32 unused
+FP32_PEAK_TFLOPS = 2 * VALU_PEAK_TOPS        # fused multiply-add = 2 flops, non-packed
 CLASS_NAMES = ["rows_fwd", "cols_conv", "rows_inv", "finalize", "backproject", "psf", "prior"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_volume_64x512.txt")
 
@@ -76,13 +81,21 @@ def prior_lane_ops(n: int, nz: int, neighbours: int) -> float:
     """Algorithmic VALU lane-operations of one prior launch.
 
     Per neighbour pair (each evaluated once): the difference, fma, 1 + w, fma and two
-    multiplies (6 full-rate operations) and log2, exp2, reciprocal (3 quarter-rate
-    transcendentals, weight 4) = 18; each pair value enters both of its voxels with one
-    fused multiply-add = 2.  26 neighbours: 13 pairs per voxel -> 260 per voxel;
-    8 neighbours: 4 pairs -> 80.
+    multiplies (6 full-rate operations) and log2, exp2, reciprocal (3 transcendentals,
+    each issuing in twice the cycles of a full-rate operation on gfx950: weight 2) = 12;
+    each pair value enters both of its voxels with one fused multiply-add = 2.
+    26 neighbours: 13 pairs per voxel -> 182 per voxel; 8 neighbours: 4 pairs -> 56.
     """
     pairs = 13 if neighbours == 26 else 4
-    return float(n) * n * nz * pairs * (18 + 2)
+    return float(n) * n * nz * pairs * (12 + 2)
+
+
+def cols_conv_flops(n: int, nz: int, P: int) -> float:
+    """Algorithmic flops of one pass-C launch: per slice H = P/2 complex columns, each a
+    forward and an inverse complex FFT of length P (5 P log2 P flops each, the standard
+    count) and a real scaling by F K (2 flops per element)."""
+    import math
+    return float(nz) * (P // 2) * (2 * 5 * P * math.log2(P) + 2 * P)
 
 
 def algorithmic_bytes(cls: str, n: int, nz: int, P: int, fused_prior: bool = False) -> float:
@@ -372,6 +385,14 @@ def main() -> int:
                 "unit": "T lane-ops/s (VALU, FP32 non-packed)", "frac": achieved / VALU_PEAK_TOPS,
                 "traffic": traffic, "algorithmic_lane_ops_per_launch": ops,
                 "algorithmic_bytes_per_launch": alg,
+                "hbm_frac": alg / (mean_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    elif name == "cols_conv":
+        flops = cols_conv_flops(wl.n, wl.n_slices, P)
+        achieved = flops / (mean_hot_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s (FP32 vector, non-packed; FFT flops 5 P log2 P)",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": alg,
                 "hbm_frac": alg / (mean_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     else:
         achieved = alg / (mean_hot_ms * 1e-3) / 1e9

@@ -179,13 +179,22 @@ TOMO_DEV void run_stages(cpx<T>* v, int q, const cpx<T>* __restrict__ tw, Lds& l
   }
 }
 
-// LDS views.  Column view: element (idx, c) of TC interleaved transforms at [idx*TC + c].
-template <typename T, int TC>
+// LDS views.  Column view: element (idx, c) of TC interleaved transforms at slot(idx)*TC + c.
+// SWZ = 0: slot = idx.  SWZ = 1: the two low bits of idx are XORed with bits 2-3 and 4-5
+// (a permutation within each aligned group of 4 slots).  For P = 1024, 16 elements per
+// thread and 8 columns, every stage store and load of a wave then spreads over all banks
+// (two passes per 64-lane 8-byte access, the minimum), where the plain layout takes eight
+// passes for the stores of the first forward and first inverse stage.
+template <typename T, int TC, int SWZ = 0>
 struct LdsCols {
   cpx<T>* base;
   int c;
-  TOMO_DEV void st(int i, cpx<T> x) { base[i * TC + c] = x; }
-  TOMO_DEV cpx<T> ld(int i) const { return base[i * TC + c]; }
+  static TOMO_DEV int slot(int i) {
+    if constexpr (SWZ == 1) return i ^ (((i >> 2) ^ (i >> 4)) & 3);
+    else return i;
+  }
+  TOMO_DEV void st(int i, cpx<T> x) { base[slot(i) * TC + c] = x; }
+  TOMO_DEV cpx<T> ld(int i) const { return base[slot(i) * TC + c]; }
 };
 
 // Row view: one contiguous transform per region, padded by one element every 16.

@@ -186,7 +186,7 @@ TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
       v[m * R0 + r] = n < N ? in[(idx_t)n * H] : mk(0.f, 0.f);
     }
 
-  fft::LdsCols<float, TC> L{lds, c};
+  fft::LdsCols<float, TC, 1> L{lds, c};
   fft::run_stages<PL, 0, -1>(v, q, tw, L);
 
   if (bx == 0) {
@@ -258,12 +258,20 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
 // evaluates the forward pairs of its voxel: 4 in-plane offsets (0,1), (1,-1), (1,0), (1,1)
 // and the 9 offsets into plane z+1; the forward pairs that start on the halo ring and end
 // inside the tile are spread over the threads as one (position, offset) item each.  A pair's
-// value enters its first voxel with + and its second with - (rho' is odd).  Tiles whose halo
-// ring lies inside the volume run without bounds tests; on the others a pair that leaves the
-// volume gets difference 0 (rho'(0) = 0) from validity masks computed once per thread.  With
-// OBJ the block also sums rho over the forward pairs of its own voxels.
+// value enters its first voxel with + (kept in registers) and its second with - (read back
+// from LDS by the voxel at the far end; rho' is odd).  Tiles whose halo ring lies inside the
+// volume run without bounds tests; on the others a pair that leaves the volume gets
+// difference 0 (rho'(0) = 0) from validity masks computed once per thread.  With OBJ the
+// block also sums rho over the forward pairs of its own voxels.
+//
+// LDS layout: each wave owns an 8 x 8 block of the tile and planes are stored with a row
+// stride of 24 floats, so that the 8 rows of a wave (offsets 0, 24, ..., 168) fall on
+// disjoint bank ranges for both 32-lane halves (32 banks) and the whole wave (64 banks);
+// every access of a wave to its own block shifted by a constant (a neighbour offset) is
+// then free of bank conflicts.
 constexpr int PR_T = 16, PR_ZC = 16, PR_NT = 256;
-constexpr int PR_H = PR_T + 2, PR_HA = PR_H * PR_H;
+constexpr int PR_H = PR_T + 2, PR_HA = PR_H * PR_H;  // halo width and element count
+constexpr int PR_S = 24, PR_PA = PR_H * PR_S;        // LDS row stride and plane size
 
 // rho'(d) / c_grad and rho(d) for q = 2, arranged for few instructions:
 //   rho'(d) / c_grad = d r (1 + (q/p - 1) r),  r = 1 / (1 + w),
@@ -283,9 +291,9 @@ TOMO_DEV void qggmrf_unit(float d, const PriorParams& pp, float& rp, float& rv) 
 
 template <int NB>
 struct PriorLds {
-  float Y[2][PR_HA];
-  float fin[4][PR_HA];
-  float fz[NB == 26 ? 9 : 1][PR_HA];
+  float Y[2][PR_PA];
+  float fin[4][PR_PA];
+  float fz[NB == 26 ? 9 : 1][PR_PA];
   double sred[(PR_NT / 64) * 4];
 };
 
@@ -294,10 +302,12 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
                          const float* __restrict__ xkm1, float* __restrict__ gp,
                          double* __restrict__ part_out, int N, int nz, int c0, int r0, int z0,
                          float mu, bool fista, const PriorParams& pp) {
-  constexpr int H = PR_H, HA = PR_HA;
+  constexpr int H = PR_H, HA = PR_HA, S = PR_S;
   const int t = threadIdx.x;
-  const int tr = t >> 4, tc = t & 15;
-  const int s = (tr + 1) * H + tc + 1;  // own position (halo coordinates)
+  // own voxel: wave w covers rows 8 (w / 2) .. +7 and columns 8 (w % 2) .. +7 of the tile
+  const int wv = t >> 6, ln = t & 63;
+  const int tr = 8 * (wv >> 1) + (ln >> 3), tc = 8 * (wv & 1) + (ln & 7);
+  const int s = (tr + 1) * S + tc + 1;  // own position in a plane buffer
   const int z1 = min(z0 + PR_ZC, nz);
   // neighbour weights with beta and the rho' prefactor folded in
   const float kb = pp.beta * pp.c_grad;
@@ -309,41 +319,42 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
   };
   auto in_tile = [&](int a, int b) { return a >= 1 && a <= PR_T && b >= 1 && b <= PR_T; };
 
-  // Halo items.  In-plane (98): top row x offsets (1,-1),(1,0),(1,1); left column x (0,1),
-  // (1,1); right column x (1,-1); two corners.  Cross-plane (196): top row x dy=+1, bottom row
-  // x dy=-1, left column x dx=+1, right column x dx=-1 (3 each), four corners.  Items whose
-  // end leaves the tile are idle.
-  int in_pos = -1, in_o = 0;
-  if (t < 48) { in_pos = t / 3 + 1; in_o = 1 + t % 3; }
-  else if (t < 80) { const int k = t - 48; in_pos = (k / 2 + 1) * H; in_o = (k & 1) ? 3 : 0; }
-  else if (t < 96) { in_pos = (t - 80 + 1) * H + H - 1; in_o = 1; }
-  else if (t == 96) { in_pos = 0; in_o = 3; }
-  else if (t == 97) { in_pos = H - 1; in_o = 1; }
-  int x_pos = -1, x_o = 0;
-  if (t < 48) { x_pos = t / 3 + 1; x_o = 6 + t % 3; }
-  else if (t < 96) { x_pos = (H - 1) * H + (t - 48) / 3 + 1; x_o = (t - 48) % 3; }
-  else if (t < 144) { x_pos = ((t - 96) / 3 + 1) * H; x_o = 3 * ((t - 96) % 3) + 2; }
-  else if (t < 192) { x_pos = ((t - 144) / 3 + 1) * H + H - 1; x_o = 3 * ((t - 144) % 3); }
-  else if (t == 192) { x_pos = 0; x_o = 8; }
-  else if (t == 193) { x_pos = H - 1; x_o = 6; }
-  else if (t == 194) { x_pos = (H - 1) * H; x_o = 2; }
-  else if (t == 195) { x_pos = (H - 1) * H + H - 1; x_o = 0; }
-  // resolve the items once: partner position, activity and validity
-  int in_q = 0, x_q = 0;
+  // Halo items, as (row a, column b) of the halo ring and an offset index.  In-plane (98):
+  // top row x offsets (1,-1),(1,0),(1,1); left column x (0,1),(1,1); right column x (1,-1);
+  // two corners.  Cross-plane (196): top row x dy=+1, bottom row x dy=-1, left column x
+  // dx=+1, right column x dx=-1 (3 each), four corners.  Items whose end leaves the tile are
+  // idle.
+  int in_a = -1, in_b = 0, in_o = 0;
+  if (t < 48) { in_a = 0; in_b = t / 3 + 1; in_o = 1 + t % 3; }
+  else if (t < 80) { const int k = t - 48; in_a = k / 2 + 1; in_b = 0; in_o = (k & 1) ? 3 : 0; }
+  else if (t < 96) { in_a = t - 79; in_b = H - 1; in_o = 1; }
+  else if (t == 96) { in_a = 0; in_b = 0; in_o = 3; }
+  else if (t == 97) { in_a = 0; in_b = H - 1; in_o = 1; }
+  int x_a = -1, x_b = 0, x_o = 0;
+  if (t < 48) { x_a = 0; x_b = t / 3 + 1; x_o = 6 + t % 3; }
+  else if (t < 96) { x_a = H - 1; x_b = (t - 48) / 3 + 1; x_o = (t - 48) % 3; }
+  else if (t < 144) { x_a = (t - 96) / 3 + 1; x_b = 0; x_o = 3 * ((t - 96) % 3) + 2; }
+  else if (t < 192) { x_a = (t - 144) / 3 + 1; x_b = H - 1; x_o = 3 * ((t - 144) % 3); }
+  else if (t == 192) { x_a = 0; x_b = 0; x_o = 8; }
+  else if (t == 193) { x_a = 0; x_b = H - 1; x_o = 6; }
+  else if (t == 194) { x_a = H - 1; x_b = 0; x_o = 2; }
+  else if (t == 195) { x_a = H - 1; x_b = H - 1; x_o = 0; }
+  // resolve the items once: start and end positions, activity and validity
+  int in_pos = 0, in_q = 0, x_pos = 0, x_q = 0;
   bool in_act = false, x_act = false, in_ok = true, x_ok = true;
-  if (in_pos >= 0) {
+  if (in_a >= 0) {
     const int dy = in_o == 0 ? 0 : 1, dx = in_o == 0 ? 1 : in_o - 2;
-    const int a = in_pos / H, b = in_pos - (in_pos / H) * H;
-    in_act = in_tile(a + dy, b + dx);
-    in_q = in_pos + dy * H + dx;
-    if constexpr (EDGE) in_ok = inside(a, b) && inside(a + dy, b + dx);
+    in_act = in_tile(in_a + dy, in_b + dx);
+    in_pos = in_a * S + in_b;
+    in_q = in_pos + dy * S + dx;
+    if constexpr (EDGE) in_ok = inside(in_a, in_b) && inside(in_a + dy, in_b + dx);
   }
-  if (x_pos >= 0) {
+  if (x_a >= 0) {
     const int dy = x_o / 3 - 1, dx = x_o % 3 - 1;
-    const int a = x_pos / H, b = x_pos - (x_pos / H) * H;
-    x_act = in_tile(a + dy, b + dx);
-    x_q = x_pos + dy * H + dx;
-    if constexpr (EDGE) x_ok = inside(a, b) && inside(a + dy, b + dx);
+    x_act = in_tile(x_a + dy, x_b + dx);
+    x_pos = x_a * S + x_b;
+    x_q = x_pos + dy * S + dx;
+    if constexpr (EDGE) x_ok = inside(x_a, x_b) && inside(x_a + dy, x_b + dx);
   }
   // own-pair validity: bits 0..3 in-plane offsets, bits 4..12 offsets into the next plane
   uint32_t m_own = 0x1fffu;
@@ -357,18 +368,21 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
       for (int o = 0; o < 9; ++o) m_own |= (uint32_t)inside(a + o / 3 - 1, b + o % 3 - 1) << (4 + o);
     }
   }
-  // plane loads: the (at most two) halo positions of this thread, as in-plane offsets
+  // plane loads: the (at most two) halo elements of this thread, read row by row from
+  // global memory (coalesced) and placed at their padded plane positions
   const int e1 = t + PR_NT;
   const bool has_e1 = e1 < HA;
-  int g0, g1 = 0;
+  int g0, g1 = 0, l0, l1 = 0;
   bool v0 = true, v1 = true;
   {
     const int a = t / H, b = t - a * H;
     g0 = (r0 - 1 + a) * N + (c0 - 1 + b);
+    l0 = a * S + b;
     if constexpr (EDGE) v0 = inside(a, b);
     if (has_e1) {
       const int a1 = e1 / H, b1 = e1 - a1 * H;
       g1 = (r0 - 1 + a1) * N + (c0 - 1 + b1);
+      l1 = a1 * S + b1;
       if constexpr (EDGE) v1 = inside(a1, b1);
     }
   }
@@ -379,22 +393,45 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
   };
   auto load_plane = [&](int z, float* dst) {
     const idx_t zb = (idx_t)z * plane;
-    dst[t] = v0 ? yval(zb + g0) : 0.f;
-    if (has_e1) dst[e1] = v1 ? yval(zb + g1) : 0.f;
+    dst[l0] = v0 ? yval(zb + g0) : 0.f;
+    if (has_e1) dst[l1] = v1 ? yval(zb + g1) : 0.f;
+  };
+  // Planes inside the march are read one iteration ahead into registers (issue) and written
+  // to LDS at the top of the next iteration (commit), so their memory latency overlaps a
+  // whole plane of pair evaluations.
+  float ra0 = 0.f, rb0 = 0.f, ra1 = 0.f, rb1 = 0.f;
+  auto issue = [&](int z) {
+    const idx_t zb = (idx_t)z * plane;
+    if (v0) {
+      ra0 = xk[zb + g0];
+      if (fista) rb0 = xkm1[zb + g0];
+    }
+    if (has_e1 && v1) {
+      ra1 = xk[zb + g1];
+      if (fista) rb1 = xkm1[zb + g1];
+    }
+  };
+  auto commit = [&](float* dst) {
+    dst[l0] = v0 ? (fista ? ra0 + mu * (ra0 - rb0) : ra0) : 0.f;
+    if (has_e1) dst[l1] = v1 ? (fista ? ra1 + mu * (ra1 - rb1) : ra1) : 0.f;
   };
   double phi = 0.0;
 
-  // forward pairs from plane buffer `src` to plane buffer `dst` (9 offsets (dy, dx))
+  // forward pairs from plane buffer `src` to plane buffer `dst` (9 offsets (dy, dx)); the
+  // weighted sum for the voxel in `src` is returned, the values go to fz for the far ends
   auto cross_fwd = [&](const float* src, const float* dst, bool count_phi) {
     const float ys = src[s];
+    float up = 0.f;
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
       const int dy = o / 3 - 1, dx = o % 3 - 1;
-      float d = ys - dst[s + dy * H + dx];
+      const float w = (dy != 0 && dx != 0) ? w3 : ((dy != 0 || dx != 0) ? w2 : w1);
+      float d = ys - dst[s + dy * S + dx];
       if constexpr (EDGE) d = (m_own >> (4 + o)) & 1u ? d : 0.f;
       float rp, rv = 0.f;
       qggmrf_unit<OBJ, QUAD>(d, pp, rp, rv);
       L.fz[o][s] = rp;
+      up = __builtin_fmaf(w, rp, up);
       if (OBJ && count_phi) phi += (double)(pp.wts[1 + (dy != 0) + (dx != 0)] * rv);
     }
     if (x_act) {
@@ -402,19 +439,17 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
       qggmrf_unit<false, QUAD>(x_ok ? src[x_pos] - dst[x_q] : 0.f, pp, rp, rv);
       L.fz[x_o][x_pos] = rp;
     }
+    return up;
   };
-  // acc gets the plane-z voxel's forward sums; the return value is the plane-(z+1) voxel's
-  // backward sum at the same (row, column)
-  auto cross_gather = [&](float& acc, bool to_acc) {
-    float up = 0.f, dn = 0.f;
+  // the plane-(z+1) voxel's backward sum at this thread's (row, column)
+  auto cross_back = [&]() {
+    float dn = 0.f;
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
       const int dy = o / 3 - 1, dx = o % 3 - 1;
       const float w = (dy != 0 && dx != 0) ? w3 : ((dy != 0 || dx != 0) ? w2 : w1);
-      up = __builtin_fmaf(w, L.fz[o][s], up);
-      dn = __builtin_fmaf(w, L.fz[o][s - dy * H - dx], dn);
+      dn = __builtin_fmaf(w, L.fz[o][s - dy * S - dx], dn);
     }
-    if (to_acc) acc += up;
     return -dn;
   };
 
@@ -424,20 +459,27 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
   if (NB == 26 && z0 > 0) {
     load_plane(z0 - 1, L.Y[1 - cur]);
     __syncthreads();
-    cross_fwd(L.Y[1 - cur], L.Y[cur], false);
+    (void)cross_fwd(L.Y[1 - cur], L.Y[cur], false);
     __syncthreads();
-    acc = cross_gather(acc, false);
+    acc = cross_back();
   }
+  // first plane read ahead: z0 + 1 (the next plane of z0, or the second plane of the march)
+  if (NB == 26 ? z0 + 1 < nz : z0 + 1 < z1) issue(z0 + 1);
   __syncthreads();
 
-  constexpr int offs[4] = {1, H - 1, H, H + 1};
+  constexpr int offs[4] = {1, S - 1, S, S + 1};
   for (int z = z0; z < z1; ++z) {
     const bool has_next = NB == 26 && z + 1 < nz;
     if (NB != 26 && z > z0) {
-      load_plane(z, L.Y[cur]);
+      commit(L.Y[cur]);
+      if (z + 1 < z1) issue(z + 1);
       __syncthreads();
     }
-    if (has_next) load_plane(z + 1, L.Y[1 - cur]);
+    if (has_next) {
+      commit(L.Y[1 - cur]);
+      if (z + 2 <= z1 && z + 2 < nz) issue(z + 2);
+    }
+    float own = 0.f;
     {
       const float* y = L.Y[cur];
       const float ys = y[s];
@@ -448,6 +490,7 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
         float rp, rv = 0.f;
         qggmrf_unit<OBJ, QUAD>(d, pp, rp, rv);
         L.fin[o][s] = rp;
+        own = __builtin_fmaf((o == 0 || o == 2) ? w1 : w2, rp, own);
         if (OBJ) phi += (double)(((o == 0 || o == 2) ? pp.wts[1] : pp.wts[2]) * rv);
       }
       if (in_act) {
@@ -457,12 +500,12 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
       }
     }
     __syncthreads();
-    acc += w1 * (L.fin[0][s] - L.fin[0][s - offs[0]]) + w2 * (L.fin[1][s] - L.fin[1][s - offs[1]]) +
-           w1 * (L.fin[2][s] - L.fin[2][s - offs[2]]) + w2 * (L.fin[3][s] - L.fin[3][s - offs[3]]);
+    acc += own - (w1 * L.fin[0][s - offs[0]] + w2 * L.fin[1][s - offs[1]] +
+                  w1 * L.fin[2][s - offs[2]] + w2 * L.fin[3][s - offs[3]]);
     if (has_next) {
-      cross_fwd(L.Y[cur], L.Y[1 - cur], true);
+      acc += cross_fwd(L.Y[cur], L.Y[1 - cur], true);
       __syncthreads();
-      accn = cross_gather(acc, true);
+      accn = cross_back();
     }
     const int r = r0 + tr, c = c0 + tc;
     if (!EDGE || (r < N && c < N)) gp[((idx_t)z * N + r) * N + c] = acc;
@@ -505,7 +548,14 @@ struct RowsInvLds {
   static constexpr int FFT_BYTES = PAIRS * fft::row_region<P>() * 8;
   static constexpr int YT_BYTES = YT * 4;
   static constexpr int A_BYTES = FFT_BYTES > YT_BYTES ? FFT_BYTES : YT_BYTES;
-  static constexpr int TY_BYTES = RB * H * 4;
+  // Without the fused prior the transformed rows of pair pr overlay that pair's own FFT
+  // region (2 H floats fit in P + P/16 complex); the fused prior needs region A for its tile.
+  static constexpr bool OVER = NB == 0;
+  static constexpr int REGF = 2 * fft::row_region<P>();  // floats per pair region
+  static constexpr int TY_BYTES = OVER ? 0 : RB * H * 4;
+  static TOMO_DEV int ty(int ry, int col) {
+    return OVER ? (ry >> 1) * REGF + (ry & 1) * H + col : ry * H + col;
+  }
   static constexpr int RED_BYTES = ((NT + 63) / 64) * 4 * 8;
   static constexpr int BYTES = A_BYTES + TY_BYTES + RED_BYTES;
 };
@@ -527,7 +577,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
   constexpr int CW = LY::CW, ZD = LY::ZD, YT = LY::YT;
   cpx<float>* fl = reinterpret_cast<cpx<float>*>(smem);
   float* ytile = reinterpret_cast<float*>(smem);
-  float* tyt = reinterpret_cast<float*>(smem + LY::A_BYTES);
+  float* tyt = reinterpret_cast<float*>(smem + (LY::OVER ? 0 : LY::A_BYTES));
   double* sred = reinterpret_cast<double*>(smem + LY::A_BYTES + LY::TY_BYTES);
 
   const int bps = (N + RB - 1) / RB;
@@ -537,29 +587,14 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
   const int r1 = r0 + 2 * pr;
   const bool active = r1 < N;
 
-  // Operands of the point-wise epilogue (split-prior path), fetched before the transform so
-  // that their latency overlaps it: thread t owns the float4 groups t + u NT, u < 4, of the
-  // RB x N tile (RB N / 4 <= 4 NT since P >= 2N; otherwise the scalar loop below runs).
+  // The point-wise epilogue (split-prior path) works on float4 groups: thread t owns the
+  // groups t + u NT, u < 4, of the RB x N tile (RB N / 4 <= 4 NT since P >= 2N); its
+  // operands are read after the transform (prefetching them before it costs registers,
+  // hence occupancy, and was measured slower).
   constexpr bool PF = MODE != MODE_POWER && NB == 0;
-  static_assert(LY::A_BYTES % 16 == 0 && H % 4 == 0, "float4 tile access");
+  static_assert(H % 4 == 0, "float4 tile access");
   const int nq = N >> 2;
   const bool vec = PF && (N & 3) == 0 && RB * nq <= 4 * NT;
-  float4 pa[4], pb[4], pbv[4], pg[4];
-  if constexpr (PF) {
-    if (vec) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = t + u * NT, ry = e / nq, row = r0 + ry;
-        if (e < RB * nq && row < N) {
-          const idx_t o = ((idx_t)z * N + row) * N + 4 * (e - ry * nq);
-          pa[u] = *reinterpret_cast<const float4*>(xk + o);
-          if constexpr (MODE == MODE_FISTA) pb[u] = *reinterpret_cast<const float4*>(xkm1 + o);
-          pbv[u] = *reinterpret_cast<const float4*>(bvec + o);
-          pg[u] = *reinterpret_cast<const float4*>(gpv + o);
-        }
-      }
-    }
-  }
 
   // ---- C2R of rows r1, r1+1 packed as Z = X1 + i X2 over the full length P
   {
@@ -597,8 +632,8 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
       for (int r = 0; r < RL; ++r) {
         const int n = fft::reg_pos<P, TPF, RL>(q, m, r);
         if (n < N) {
-          tyt[(2 * pr) * H + n] = v[m * RL + r].re;
-          tyt[(2 * pr + 1) * H + n] = v[m * RL + r].im;
+          tyt[LY::ty(2 * pr, n)] = v[m * RL + r].re;
+          tyt[LY::ty(2 * pr + 1, n)] = v[m * RL + r].im;
         }
       }
   }
@@ -607,21 +642,25 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   if constexpr (PF) {
    if (vec) {
-    // prior gradient precomputed by prior_kernel: point-wise epilogue on the prefetched groups
+    // prior gradient precomputed by prior_kernel: point-wise epilogue on float4 groups
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = t + u * NT, ry = e / nq, row = r0 + ry;
       if (e < RB * nq && row < N) {
         const int col = 4 * (e - ry * nq);
         const idx_t o = ((idx_t)z * N + row) * N + col;
-        const float4 ty4 = *reinterpret_cast<const float4*>(tyt + ry * H + col);
-        const float av[4] = {pa[u].x, pa[u].y, pa[u].z, pa[u].w};
-        const float bv[4] = {pbv[u].x, pbv[u].y, pbv[u].z, pbv[u].w};
-        const float gv[4] = {pg[u].x, pg[u].y, pg[u].z, pg[u].w};
+        const float4 xa4 = *reinterpret_cast<const float4*>(xk + o);
+        const float4 bv4 = *reinterpret_cast<const float4*>(bvec + o);
+        const float4 gp4 = *reinterpret_cast<const float4*>(gpv + o);
+        const float4 ty4 = *reinterpret_cast<const float4*>(tyt + LY::ty(ry, col));
+        const float av[4] = {xa4.x, xa4.y, xa4.z, xa4.w};
+        const float bv[4] = {bv4.x, bv4.y, bv4.z, bv4.w};
+        const float gv[4] = {gp4.x, gp4.y, gp4.z, gp4.w};
         const float tv[4] = {ty4.x, ty4.y, ty4.z, ty4.w};
         float km1[4] = {0.f, 0.f, 0.f, 0.f};
         if constexpr (MODE == MODE_FISTA) {
-          km1[0] = pb[u].x; km1[1] = pb[u].y; km1[2] = pb[u].z; km1[3] = pb[u].w;
+          const float4 b4 = *reinterpret_cast<const float4*>(xkm1 + o);
+          km1[0] = b4.x; km1[1] = b4.y; km1[2] = b4.z; km1[3] = b4.w;
         }
         float res[4];
 #pragma unroll
@@ -650,7 +689,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
         const idx_t o = ((idx_t)z * N + row) * N + col;
         const float a = xk[o];
         const float ys = (MODE == MODE_FISTA) ? a + mu * (a - xkm1[o]) : a;
-        const float ty = tyt[ry * H + col];
+        const float ty = tyt[LY::ty(ry, col)];
         const float bs = bvec[o];
         const float g = ty - bs + gpv[o];
         if constexpr (MODE == MODE_FISTA) {
@@ -669,7 +708,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
     for (int e = t; e < RB * N; e += NT) {
       const int ry = e / N, col = e - ry * N, row = r0 + ry;
       if (row < N) {
-        const float ty = tyt[ry * H + col];
+        const float ty = tyt[LY::ty(ry, col)];
         out[((idx_t)z * N + row) * N + col] = ty;
         acc0 += (double)ty * (double)ty;
       }
@@ -725,7 +764,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
               }
           }
           const idx_t o = ((idx_t)z * N + row) * N + col;
-          const float ty = tyt[ry * H + col];
+          const float ty = tyt[LY::ty(ry, col)];
           const float bs = bvec[o];
           const float g = ty - bs + pp.beta * gsum;
           if constexpr (MODE == MODE_FISTA) {
