@@ -139,15 +139,24 @@ TOMO_DEV void stage_compute(cpx<T>* v, int q, const cpx<T>* __restrict__ tw) {
   }
 }
 
+// Output position of butterfly j of a stage with radix R and span p, before the r * p term:
+// the bits of j with log2(R) zero bits inserted at bit log2(p).  The map is bitwise, so for
+// j = q + m TPF (q < TPF, disjoint bits) it is the sum of the maps of q and of m TPF.
+template <int R, int p>
+TOMO_DEV int out_base(int j) { return (j / p) * p * R + (j & (p - 1)); }
+
+// Stores and loads address the LDS view with a per-thread part Q (from q alone) and a part K
+// known at compile time, with disjoint bits (i = Q + K = Q | K); views whose layout is
+// bitwise in i use the split to keep the per-thread work out of the unrolled accesses.
 template <class PL, int S, typename T, class Lds>
 TOMO_DEV void stage_store(const cpx<T>* v, int q, Lds& lds) {
   constexpr int R = PL::radix(S), p = PL::span(S), E = PL::E, TPF = PL::TPF;
+  const int Q = out_base<R, p>(q);
 #pragma unroll
   for (int m = 0; m < E / R; ++m) {
-    const int j = q + m * TPF;
-    const int base = (j / p) * p * R + (j & (p - 1));
+    const int Kb = out_base<R, p>(m * TPF);
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds.st(base + r * p, v[m * R + r]);
+    for (int r = 0; r < R; ++r) lds.st2(Q, Kb + r * p, v[m * R + r]);
   }
 }
 
@@ -157,7 +166,7 @@ TOMO_DEV void stage_load(cpx<T>* v, int q, Lds& lds) {
 #pragma unroll
   for (int m = 0; m < E / R; ++m)
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[m * R + r] = lds.ld(q + m * TPF + r * (P / R));
+    for (int r = 0; r < R; ++r) v[m * R + r] = lds.ld2(q, m * TPF + r * (P / R));
 }
 
 // Position held by register v[m*R + r] in the layout of a radix-R stage input/last-stage output.
@@ -195,6 +204,19 @@ struct LdsCols {
   }
   TOMO_DEV void st(int i, cpx<T> x) { base[slot(i) * TC + c] = x; }
   TOMO_DEV cpx<T> ld(int i) const { return base[slot(i) * TC + c]; }
+  // i = Q + K with disjoint bits: slot is XOR-linear, slot(i) = slot(Q) ^ slot(K), and only
+  // bits 0-1 of the two can meet, so the address is one of four per-thread bases plus a
+  // compile-time offset.
+  TOMO_DEV cpx<T>* at2(int Q, int K) const {
+    if constexpr (SWZ == 1) {
+      const int sk = slot(K);
+      return base + ((slot(Q) ^ (sk & 3)) * TC + c) + (sk & ~3) * TC;
+    } else {
+      return base + (Q * TC + c) + K * TC;
+    }
+  }
+  TOMO_DEV void st2(int Q, int K, cpx<T> x) { *at2(Q, K) = x; }
+  TOMO_DEV cpx<T> ld2(int Q, int K) const { return *at2(Q, K); }
 };
 
 // Row view: one contiguous transform per region, padded by one element every 16.
@@ -204,6 +226,8 @@ struct LdsRow {
   static TOMO_DEV int pad(int i) { return i + (i >> 4); }
   TOMO_DEV void st(int i, cpx<T> x) { base[pad(i)] = x; }
   TOMO_DEV cpx<T> ld(int i) const { return base[pad(i)]; }
+  TOMO_DEV void st2(int Q, int K, cpx<T> x) { st(Q + K, x); }
+  TOMO_DEV cpx<T> ld2(int Q, int K) const { return ld(Q + K); }
 };
 
 template <int P>

@@ -27,7 +27,11 @@ enum ScalarSlot {
   SC_COUNT = 16
 };
 
-enum Mode { MODE_FISTA = 0, MODE_GRAD = 1, MODE_POWER = 2 };
+// MODE_FISTA_Y: a FISTA step whose extrapolated point y and prior term gp - b were written by
+// the prior kernel (launch_prior with b and yout): pass R reads y (xk = y), pass R' reads
+// x_k, y (in the x_{k-1} slot) and gp - b (in the gpv slot) and not b; <y, b> comes from the
+// prior kernel's partial sums.
+enum Mode { MODE_FISTA = 0, MODE_GRAD = 1, MODE_POWER = 2, MODE_FISTA_Y = 3 };
 
 // Launch geometry of the hot-path kernels for a padded size P (used for partials sizing).
 // v: tile variant 0, 1 (default), 2 of a transform pass.
@@ -55,9 +59,12 @@ hipError_t launch_rows_inv(int P, int v, int mode, int neighbours, bool with_obj
                            const PriorParams& pp, int* nblocks_out, hipStream_t st);
 // Prior gradient (and Phi partial sums [blocks][4], slot 0, when with_obj) over z-marching tiles.
 int prior_blocks(int N, int nz);
+// gp = beta grad Phi(y); with b and yout (both non-null, MODE_FISTA only) gp - b is written
+// to gp and y to yout, and the partial sums carry <y, b> in slot 1 (with_obj).
 hipError_t launch_prior(int mode, int neighbours, bool with_obj, const float* xk,
-                        const float* xkm1, const double* scal, float* gp, double* partials,
-                        int N, int nz, const PriorParams& pp, hipStream_t st);
+                        const float* xkm1, const double* scal, float* gp, const float* b,
+                        float* yout, double* partials, int N, int nz, const PriorParams& pp,
+                        hipStream_t st);
 // Deterministic float64 reduction of the partials + scalar update.
 hipError_t launch_finalize(int mode, const double* partials, int nblocks,
                            const double* prior_partials, int nprior, double* scal,

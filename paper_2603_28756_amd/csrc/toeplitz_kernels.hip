@@ -78,7 +78,7 @@ template <int P, int PAIRS>
 constexpr int rows_fwd_lds() { return PAIRS * fft::row_region<P>() * 8; }
 
 // Block `blk` transforms row pairs blk*PAIRS .. blk*PAIRS+PAIRS-1 (counted over all slices).
-// y = x_k + mu (x_k - x_{k-1}), or s * x_k in power mode.
+// y = x_k + mu (x_k - x_{k-1}), or s * x_k in power mode, or y = xk as given (MODE_FISTA_Y).
 template <int P, int PAIRS, int MODE>
 TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restrict__ xk,
                             const float* __restrict__ xkm1, float mu, float s,
@@ -110,6 +110,8 @@ TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restric
         const float a1 = xk[row1 + n], a2 = xk[row2 + n];
         if constexpr (MODE == MODE_POWER) {
           zz = mk(s * a1, s * a2);
+        } else if constexpr (MODE == MODE_FISTA_Y) {
+          zz = mk(a1, a2);  // y written by the prior kernel
         } else {
           const float b1 = xkm1[row1 + n], b2 = xkm1[row2 + n];
           zz = mk(a1 + mu * (a1 - b1), a2 + mu * (a2 - b2));
@@ -297,9 +299,12 @@ struct PriorLds {
   double sred[(PR_NT / 64) * 4];
 };
 
-template <int NB, bool OBJ, bool QUAD, bool EDGE>
+// YG: also store y and write gp - b in place of gp (b = bvec), and with OBJ sum <y, b>, for
+// a FISTA step whose passes R and R' then read y and gp - b instead of x_{k-1}, b and gp.
+template <int NB, bool OBJ, bool QUAD, bool EDGE, bool YG>
 TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
                          const float* __restrict__ xkm1, float* __restrict__ gp,
+                         const float* __restrict__ bvec, float* __restrict__ yout,
                          double* __restrict__ part_out, int N, int nz, int c0, int r0, int z0,
                          float mu, bool fista, const PriorParams& pp) {
   constexpr int H = PR_H, HA = PR_HA, S = PR_S;
@@ -415,7 +420,7 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
     dst[l0] = v0 ? (fista ? ra0 + mu * (ra0 - rb0) : ra0) : 0.f;
     if (has_e1) dst[l1] = v1 ? (fista ? ra1 + mu * (ra1 - rb1) : ra1) : 0.f;
   };
-  double phi = 0.0;
+  double phi = 0.0, yb = 0.0;
 
   // forward pairs from plane buffer `src` to plane buffer `dst` (9 offsets (dy, dx)); the
   // weighted sum for the voxel in `src` is returned, the values go to fz for the far ends
@@ -465,6 +470,11 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
   }
   // first plane read ahead: z0 + 1 (the next plane of z0, or the second plane of the march)
   if (NB == 26 ? z0 + 1 < nz : z0 + 1 < z1) issue(z0 + 1);
+  // YG: b is read one plane ahead as well (bcur for this plane, bnext for the next)
+  const int r = r0 + tr, c = c0 + tc;
+  const bool store = !EDGE || (r < N && c < N);
+  float bcur = 0.f, bnext = 0.f;
+  if (YG && store) bcur = bvec[((idx_t)z0 * N + r) * N + c];
   __syncthreads();
 
   constexpr int offs[4] = {1, S - 1, S, S + 1};
@@ -477,12 +487,17 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
     }
     if (has_next) {
       commit(L.Y[1 - cur]);
-      if (z + 2 <= z1 && z + 2 < nz) issue(z + 2);
+      // the plane after next, or (past the march) plane z again, an L2 hit whose values are
+      // not used: the reads stay unconditional, which keeps the memory-counter waits exact
+      issue(z + 2 <= z1 && z + 2 < nz ? z + 2 : z);
     }
-    float own = 0.f;
+    const idx_t go = ((idx_t)z * N + r) * N + c;
+    if (YG && store) bnext = bvec[go + (z + 1 < z1 ? plane : 0)];  // b of the next plane
+    float own = 0.f, ys_own;
     {
       const float* y = L.Y[cur];
       const float ys = y[s];
+      ys_own = ys;
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
         float d = ys - y[s + offs[o]];
@@ -507,20 +522,29 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
       __syncthreads();
       accn = cross_back();
     }
-    const int r = r0 + tr, c = c0 + tc;
-    if (!EDGE || (r < N && c < N)) gp[((idx_t)z * N + r) * N + c] = acc;
+    if (store) {
+      if constexpr (YG) {
+        gp[go] = acc - bcur;
+        yout[go] = ys_own;
+        if (OBJ) yb += (double)ys_own * (double)bcur;
+      } else {
+        gp[go] = acc;
+      }
+    }
+    bcur = bnext;
     acc = accn;
     accn = 0.f;
     if (NB == 26) cur = 1 - cur;
     __syncthreads();
   }
-  if (part_out) block_sum4<PR_NT>(phi, 0.0, 0.0, 0.0, part_out, L.sred);
+  if (part_out) block_sum4<PR_NT>(phi, yb, 0.0, 0.0, part_out, L.sred);
 }
 
-template <int NB, bool OBJ, bool QUAD>
+template <int NB, bool OBJ, bool QUAD, bool YG>
 __global__ void __launch_bounds__(PR_NT)
 prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
              const double* __restrict__ scal, float* __restrict__ gp,
+             const float* __restrict__ bvec, float* __restrict__ yout,
              double* __restrict__ partials, int N, int nz, int mode_fista, PriorParams pp) {
   __shared__ PriorLds<NB> L;
   // logical tile: x fastest, then y, then the slice chunk; XCD-contiguous so that tiles
@@ -533,9 +557,11 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
   double* part = partials ? partials + (idx_t)blockIdx.x * 4 : nullptr;
   const bool interior = r0 >= 1 && c0 >= 1 && r0 + PR_T + 1 <= N && c0 + PR_T + 1 <= N;
   if (interior)
-    prior_tile<NB, OBJ, QUAD, false>(L, xk, xkm1, gp, part, N, nz, c0, r0, z0, mu, mode_fista != 0, pp);
+    prior_tile<NB, OBJ, QUAD, false, YG>(L, xk, xkm1, gp, bvec, yout, part, N, nz, c0, r0, z0, mu,
+                                         mode_fista != 0, pp);
   else
-    prior_tile<NB, OBJ, QUAD, true>(L, xk, xkm1, gp, part, N, nz, c0, r0, z0, mu, mode_fista != 0, pp);
+    prior_tile<NB, OBJ, QUAD, true, YG>(L, xk, xkm1, gp, bvec, yout, part, N, nz, c0, r0, z0, mu,
+                                        mode_fista != 0, pp);
 }
 
 // --------------------------------------------------------------------------------- pass R'
@@ -649,16 +675,20 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
       if (e < RB * nq && row < N) {
         const int col = 4 * (e - ry * nq);
         const idx_t o = ((idx_t)z * N + row) * N + col;
+        // MODE_FISTA_Y: xkm1 holds y and gpv holds gp - b (b not read)
         const float4 xa4 = *reinterpret_cast<const float4*>(xk + o);
-        const float4 bv4 = *reinterpret_cast<const float4*>(bvec + o);
         const float4 gp4 = *reinterpret_cast<const float4*>(gpv + o);
         const float4 ty4 = *reinterpret_cast<const float4*>(tyt + LY::ty(ry, col));
+        float bv[4] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE != MODE_FISTA_Y) {
+          const float4 bv4 = *reinterpret_cast<const float4*>(bvec + o);
+          bv[0] = bv4.x; bv[1] = bv4.y; bv[2] = bv4.z; bv[3] = bv4.w;
+        }
         const float av[4] = {xa4.x, xa4.y, xa4.z, xa4.w};
-        const float bv[4] = {bv4.x, bv4.y, bv4.z, bv4.w};
         const float gv[4] = {gp4.x, gp4.y, gp4.z, gp4.w};
         const float tv[4] = {ty4.x, ty4.y, ty4.z, ty4.w};
         float km1[4] = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (MODE == MODE_FISTA) {
+        if constexpr (MODE == MODE_FISTA || MODE == MODE_FISTA_Y) {
           const float4 b4 = *reinterpret_cast<const float4*>(xkm1 + o);
           km1[0] = b4.x; km1[1] = b4.y; km1[2] = b4.z; km1[3] = b4.w;
         }
@@ -666,9 +696,11 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const float a = av[k];
-          const float ys = (MODE == MODE_FISTA) ? a + mu * (a - km1[k]) : a;
-          const float g = tv[k] - bv[k] + gv[k];
-          if constexpr (MODE == MODE_FISTA) {
+          const float ys = (MODE == MODE_FISTA)   ? a + mu * (a - km1[k])
+                           : (MODE == MODE_FISTA_Y) ? km1[k]
+                                                    : a;
+          const float g = (MODE == MODE_FISTA_Y) ? tv[k] + gv[k] : tv[k] - bv[k] + gv[k];
+          if constexpr (MODE == MODE_FISTA || MODE == MODE_FISTA_Y) {
             const float xn = ys - g * invL;
             res[k] = xn;
             acc3 += (double)(ys - xn) * (double)(xn - a);
@@ -676,7 +708,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
             res[k] = g;
           }
           acc0 += (double)ys * (double)tv[k];
-          acc1 += (double)ys * (double)bv[k];
+          if constexpr (MODE != MODE_FISTA_Y) acc1 += (double)ys * (double)bv[k];
         }
         *reinterpret_cast<float4*>(out + o) = make_float4(res[0], res[1], res[2], res[3]);
       }
@@ -688,11 +720,13 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
       if (row < N) {
         const idx_t o = ((idx_t)z * N + row) * N + col;
         const float a = xk[o];
-        const float ys = (MODE == MODE_FISTA) ? a + mu * (a - xkm1[o]) : a;
+        const float ys = (MODE == MODE_FISTA)   ? a + mu * (a - xkm1[o])
+                         : (MODE == MODE_FISTA_Y) ? xkm1[o]
+                                                  : a;
         const float ty = tyt[LY::ty(ry, col)];
-        const float bs = bvec[o];
+        const float bs = (MODE == MODE_FISTA_Y) ? 0.f : bvec[o];
         const float g = ty - bs + gpv[o];
-        if constexpr (MODE == MODE_FISTA) {
+        if constexpr (MODE == MODE_FISTA || MODE == MODE_FISTA_Y) {
           const float xn = ys - g * invL;
           out[o] = xn;
           acc3 += (double)(ys - xn) * (double)(xn - a);
@@ -795,7 +829,7 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
                 const cpx<float>* __restrict__ tw, int N, int nz, PriorParams pp) {
   __shared__ __align__(16) unsigned char smem[RowsInvLds<P, PAIRS, NB>::BYTES];
   const float mu = (MODE == MODE_FISTA) ? (float)scal[SC_MU] : 0.f;
-  const float invL = (MODE == MODE_FISTA) ? (float)scal[SC_INVL] : 0.f;
+  const float invL = (MODE == MODE_FISTA || MODE == MODE_FISTA_Y) ? (float)scal[SC_INVL] : 0.f;
   rows_inv_body<P, PAIRS, MODE, NB, OBJ>(smem, blockIdx.x, S2, xk, xkm1, bvec, gpv, out,
                                          partials + (idx_t)blockIdx.x * 4, mu, invL, tw, N, nz,
                                          pp);
@@ -814,8 +848,12 @@ finalize_kernel(const double* __restrict__ partials, int nblocks,
   for (int b = t; b < nblocks; b += 256)
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] += partials[(idx_t)b * 4 + i];
-  // Phi from the separate prior kernel (slot 0 of its partials) lands in slot 2
-  for (int b = t; b < nprior; b += 256) a[2] += prior_partials[(idx_t)b * 4];
+  // Phi from the separate prior kernel (slot 0 of its partials) lands in slot 2; its slot 1
+  // holds <y, b> when the prior kernel wrote y and gp - b (zero otherwise)
+  for (int b = t; b < nprior; b += 256) {
+    a[2] += prior_partials[(idx_t)b * 4];
+    a[1] += prior_partials[(idx_t)b * 4 + 1];
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) sh[i][t] = a[i];
   __syncthreads();
@@ -1102,6 +1140,9 @@ hipError_t rows_fwd_pv(int mode, const float* xk, const float* xkm1, const doubl
   if (mode == MODE_POWER)
     hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_POWER>), grid, dim3(NT), 0, st, xk, xkm1,
                        scal, S1, tw, N, n_pairs);
+  else if (mode == MODE_FISTA_Y)
+    hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_FISTA_Y>), grid, dim3(NT), 0, st, xk, xkm1,
+                       scal, S1, tw, N, n_pairs);
   else
     hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_FISTA>), grid, dim3(NT), 0, st, xk, xkm1,
                        scal, S1, tw, N, n_pairs);
@@ -1162,6 +1203,12 @@ hipError_t rows_inv_p(int v, int mode, int nbh, bool obj, const cpx<float>* S2, 
   return rows_inv_launch<P, MODE, 0, false, V>(S2, xk, xkm1, b, gpv, out, partials, scal, tw, N, \
                                                nz, pp, nblocks, st)
   if (mode == MODE_POWER) TOMO_INV(MODE_POWER, 8, false);
+  if (mode == MODE_FISTA_Y) {  // y and gp - b from the prior kernel
+    if (!gpv || !xkm1) return hipErrorInvalidValue;
+    if (v == 0) TOMO_INV_V(MODE_FISTA_Y, 0);
+    if (v == 2) TOMO_INV_V(MODE_FISTA_Y, 2);
+    TOMO_INV_V(MODE_FISTA_Y, 1);
+  }
   if (gpv) {  // prior gradient precomputed: the tile variant applies
     if (mode == MODE_GRAD) {
       if (v == 0) TOMO_INV_V(MODE_GRAD, 0);
@@ -1288,21 +1335,28 @@ int prior_blocks(int N, int nz) {
 
 template <int NB, bool OBJ, bool QUAD>
 void prior_launch(dim3 grid, hipStream_t st, const float* xk, const float* xkm1,
-                  const double* scal, float* gp, double* part, int N, int nz, int fista,
-                  const PriorParams& pp) {
-  hipLaunchKernelGGL((prior_kernel<NB, OBJ, QUAD>), grid, dim3(PR_NT), 0, st, xk, xkm1, scal, gp,
-                     part, N, nz, fista, pp);
+                  const double* scal, float* gp, const float* b, float* yout, double* part,
+                  int N, int nz, int fista, const PriorParams& pp) {
+  if (yout)
+    hipLaunchKernelGGL((prior_kernel<NB, OBJ, QUAD, true>), grid, dim3(PR_NT), 0, st, xk, xkm1,
+                       scal, gp, b, yout, part, N, nz, fista, pp);
+  else
+    hipLaunchKernelGGL((prior_kernel<NB, OBJ, QUAD, false>), grid, dim3(PR_NT), 0, st, xk, xkm1,
+                       scal, gp, b, yout, part, N, nz, fista, pp);
 }
 
 hipError_t launch_prior(int mode, int neighbours, bool with_obj, const float* xk,
-                        const float* xkm1, const double* scal, float* gp, double* partials,
-                        int N, int nz, const PriorParams& pp, hipStream_t st) {
+                        const float* xkm1, const double* scal, float* gp, const float* b,
+                        float* yout, double* partials, int N, int nz, const PriorParams& pp,
+                        hipStream_t st) {
+  if ((yout != nullptr) != (b != nullptr) || (yout && mode != MODE_FISTA))
+    return hipErrorInvalidValue;
   const dim3 grid(prior_blocks(N, nz));
   const int fista = mode == MODE_FISTA ? 1 : 0;
   double* part = with_obj ? partials : nullptr;
   const bool quad = pp.quadratic != 0;
 #define PRIOR_CALL(NB, OBJ, QUAD) \
-  prior_launch<NB, OBJ, QUAD>(grid, st, xk, xkm1, scal, gp, part, N, nz, fista, pp)
+  prior_launch<NB, OBJ, QUAD>(grid, st, xk, xkm1, scal, gp, b, yout, part, N, nz, fista, pp)
   if (neighbours == 26) {
     if (with_obj) { if (quad) PRIOR_CALL(26, true, true); else PRIOR_CALL(26, true, false); }
     else { if (quad) PRIOR_CALL(26, false, true); else PRIOR_CALL(26, false, false); }
@@ -1324,7 +1378,7 @@ hipError_t launch_finalize(int mode, const double* partials, int nblocks,
   else if (mode == MODE_GRAD)
     hipLaunchKernelGGL((finalize_kernel<MODE_GRAD>), dim3(1), dim3(256), 0, st, partials,
                        nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
-  else
+  else  // MODE_FISTA, MODE_FISTA_Y
     hipLaunchKernelGGL((finalize_kernel<MODE_FISTA>), dim3(1), dim3(256), 0, st, partials,
                        nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   return hipGetLastError();

@@ -70,7 +70,7 @@ struct tomo_plan_s {
   size_t off_ghat = 0, off_dfttab = 0, off_post = 0;
   size_t off_g0 = 0, off_wx = 0, off_wy = 0;
   size_t off_scratch = 0, scratch_bytes = 0;
-  size_t off_gp = 0, off_ppartials = 0;
+  size_t off_gp = 0, off_ppartials = 0, off_y = 0;
   size_t off_cnt = 0, off_scan = 0, off_rampf = 0;
   bool fused_prior = false, grids_ready = false;
   bool tables_ready = false, psf_ready = false;
@@ -178,6 +178,7 @@ void layout(tomo_plan p) {
   p->off_scan = take((maxcells / 4096 + 2) * sizeof(int));
   for (int i = 0; i < 3; ++i) p->off_x[i] = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
   p->off_gp = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
+  p->off_y = take((size_t)p->nz * fin.n * fin.n * sizeof(float));
   size_t maxprior = 1;
   for (const Level& l : p->lv) maxprior = std::max(maxprior, (size_t)prior_blocks(l.n, p->nz));
   p->off_ppartials = take(maxprior * 4 * sizeof(double));
@@ -370,6 +371,12 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
   const float* gpv = nullptr;
   if (nprior) *nprior = 0;
   const bool conc = mode != MODE_POWER && !p->fused_prior && p->concurrent_prior;
+  // In sequence, a FISTA step lets the prior kernel (which forms y anyway and is bound by
+  // its arithmetic, not by memory) also write y and gp - b: pass R then reads y alone and
+  // pass R' reads y and gp - b instead of x_{k-1}, b and gp (4 bytes per voxel less for each
+  // of the two memory-bound passes).
+  const bool yg = mode == MODE_FISTA && !p->fused_prior && !conc;
+  float* ybuf = yg ? p->at<float>(p->off_y) : nullptr;
   if (mode != MODE_POWER && !p->fused_prior) {
     hipStream_t ps = st;
     if (conc) {
@@ -381,7 +388,8 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
     }
     const int tp = tbegin(p, TOMO_T_PRIOR, ps);
     HIPCHK(p, launch_prior(mode, p->g.neighbours, obj, xk, xkm1, p->scal(), p->at<float>(p->off_gp),
-                           p->at<double>(p->off_ppartials), l.n, nz, p->pp, ps));
+                           yg ? b : nullptr, ybuf, p->at<double>(p->off_ppartials), l.n, nz,
+                           p->pp, ps));
     tend(p, tp, ps);
     if (conc) HIPCHK(p, hipEventRecord(p->pev_join, ps));
     gpv = p->at<float>(p->off_gp);
@@ -390,7 +398,12 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
   // per-class timing covers the iteration and gradient launches, not the power iteration
   const bool timed = mode != MODE_POWER;
   int ti = timed ? tbegin(p, TOMO_T_ROWS_FWD) : -1;
-  HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz, st));
+  if (yg)
+    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, MODE_FISTA_Y, ybuf, ybuf, p->scal(), S1, p->tw32(l.P),
+                              l.n, nz, st));
+  else
+    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz,
+                              st));
   tend(p, ti);
   ti = timed ? tbegin(p, TOMO_T_COLS_CONV) : -1;
   HIPCHK(p, launch_cols_conv(l.P, l.v_cc, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
@@ -398,8 +411,14 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
   tend(p, ti);
   if (conc) HIPCHK(p, hipStreamWaitEvent(st, p->pev_join, 0));
   ti = timed ? tbegin(p, TOMO_T_ROWS_INV) : -1;
-  HIPCHK(p, launch_rows_inv(l.P, l.v_inv, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
-                            p->partials(), p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks, st));
+  if (yg)
+    HIPCHK(p, launch_rows_inv(l.P, l.v_inv, MODE_FISTA_Y, p->g.neighbours, obj, S2, xk, ybuf,
+                              nullptr, gpv, out, p->partials(), p->scal(), p->tw32(l.P), l.n, nz,
+                              p->pp, nblocks, st));
+  else
+    HIPCHK(p, launch_rows_inv(l.P, l.v_inv, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
+                              p->partials(), p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks,
+                              st));
   tend(p, ti);
   return TOMO_OK;
 }
@@ -1263,13 +1282,17 @@ tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
       for (int v = 0; v < 3 && s == TOMO_OK; ++v) {
         auto launch = [&]() -> hipError_t {
           int nb = 0;
+          // the modes a FISTA step uses: y and gp - b precomputed unless the prior runs
+          // fused or on its own stream
+          const bool yg = !p->fused_prior && !p->concurrent_prior;
           if (pass == 0)
-            return launch_rows_fwd(l.P, v, MODE_FISTA, x, x, p->scal(), S1, p->tw32(l.P), l.n,
-                                   p->nz, st);
+            return launch_rows_fwd(l.P, v, yg ? MODE_FISTA_Y : MODE_FISTA, x, x, p->scal(), S1,
+                                   p->tw32(l.P), l.n, p->nz, st);
           if (pass == 1)
             return launch_cols_conv(l.P, v, S1, S2, fk, fkn, p->tw32(l.P), l.n, p->nz, st);
-          return launch_rows_inv(l.P, v, MODE_GRAD, p->g.neighbours, false, S2, x, x, bb, gp, out,
-                                 p->partials(), p->scal(), p->tw32(l.P), l.n, p->nz, p->pp, &nb, st);
+          return launch_rows_inv(l.P, v, yg ? MODE_FISTA_Y : MODE_GRAD, p->g.neighbours, false, S2,
+                                 x, x, bb, gp, out, p->partials(), p->scal(), p->tw32(l.P), l.n,
+                                 p->nz, p->pp, &nb, st);
         };
         hipError_t e = launch();
         if (e == hipSuccess) e = hipEventRecord(e0, st);

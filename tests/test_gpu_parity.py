@@ -220,12 +220,14 @@ def test_not_ready_before_psf():
 def test_graph_replay_matches_direct_launches():
     # The iteration loop replays captured 3-iteration graphs; every replay must equal the
     # directly launched iterations bit for bit, also after unrelated eager work between calls,
-    # with the prior kernel on its own stream or in sequence.
+    # with the prior kernel on its own stream or in sequence.  In sequence the prior kernel
+    # also writes y and gp - b for passes R and R' (a different rounding order of the same
+    # sums), so the two settings agree to rounding, not bit for bit.
     from paper_2603_28756_amd import tomo
     n, nz, na, nd, iters = 64, 2, 30, 92, 20
     sino, ang, center, _ = problem(n, nz, na, nd, seed=21)
     g = to_dev(sino)
-    outs = []
+    outs = {False: [], True: []}
     # (graphs, concurrent prior): the prior kernel in sequence or on its own stream
     for graphs, conc in ((False, False), (False, True), (True, True), (True, False)):
         plan = make_plan(n, nz, ang, nd, neighbours=26, graphs=graphs, concurrent_prior=conc)
@@ -236,8 +238,13 @@ def test_graph_replay_matches_direct_launches():
             junk = torch.randn(1 << 20, device=dev())
             junk.mul_(2.0).sum().item()
             torch.cuda.synchronize()
-            outs.append((x.clone(), hist.clone()))
-    ref_x, ref_h = outs[0]
-    for x, h in outs[1:]:
-        assert torch.equal(x, ref_x)
-        assert torch.equal(h, ref_h)
+            outs[conc].append((x.clone(), hist.clone()))
+    for conc in (False, True):
+        ref_x, ref_h = outs[conc][0]
+        for x, h in outs[conc][1:]:
+            assert torch.equal(x, ref_x)
+            assert torch.equal(h, ref_h)
+    (xs, hs), (xc, hc) = outs[False][0], outs[True][0]
+    assert rel_l2(to_np(xs), to_np(xc)) < 1e-5
+    # objective differences relative to F(0) = <g, g>/2, the scale of the terms that cancel in F
+    assert np.max(np.abs(to_np(hs) - to_np(hc))) / abs(float(hc[0])) < 1e-5
