@@ -98,20 +98,27 @@ def cols_conv_flops(n: int, nz: int, P: int) -> float:
     return float(nz) * (P // 2) * (2 * 5 * P * math.log2(P) + 2 * P)
 
 
-def algorithmic_bytes(cls: str, n: int, nz: int, P: int, fused_prior: bool = False) -> float:
-    """Bytes each kernel class must move per launch (compulsory reads + writes)."""
+def algorithmic_bytes(cls: str, n: int, nz: int, P: int, fused_prior: bool = False,
+                      concurrent_prior: bool = False) -> float:
+    """Bytes each kernel class must move per launch (compulsory reads + writes).
+
+    In sequence (the default) the prior kernel of a FISTA step also writes y and
+    gp - b, which passes R and R' then read in place of x_{k-1}, b and gp; with the
+    fused prior or the prior on its own stream the passes read x_k, x_{k-1}, b (and gp).
+    """
     H = P // 2
     spec = 8.0 * nz * n * H          # one half spectrum S1 or S2 (complex64)
     vol = 4.0 * nz * n * n           # one float32 volume
     fk = 4.0 * P * (H + 1)           # PSF spectrum (float32)
-    if cls == "rows_fwd":            # read x_k, x_{k-1}; write S1
-        return 2 * vol + spec
+    yg = not fused_prior and not concurrent_prior
+    if cls == "rows_fwd":            # read y (or x_k, x_{k-1}); write S1
+        return (1 if yg else 2) * vol + spec
     if cls == "cols_conv":           # read S1 and F K; write S2
         return 2 * spec + fk
-    if cls == "rows_inv":            # read S2, x_k, x_{k-1}, b, prior gradient; write x_{k+1}
-        return spec + (4 if fused_prior else 5) * vol
-    if cls == "prior":               # read x_k, x_{k-1}; write the prior gradient
-        return 3 * vol
+    if cls == "rows_inv":            # read S2, x_k, y, gp - b (or S2, x_k, x_{k-1}, b[, gp]); write x_{k+1}
+        return spec + (4 if yg else (4 if fused_prior else 5)) * vol
+    if cls == "prior":               # read x_k, x_{k-1}[, b]; write gp[ - b, y]
+        return (5 if yg else 3) * vol
     return float("nan")
 
 
@@ -376,7 +383,7 @@ def main() -> int:
     iter_ms = sum(breakdown[CLASS_NAMES[i]]["total_ms"]
                   for i in iter_classes + [tomo.T_FINALIZE]) / total_iters
     name = CLASS_NAMES[hot]
-    alg = algorithmic_bytes(name, wl.n, wl.n_slices, P, args.fused_prior)
+    alg = algorithmic_bytes(name, wl.n, wl.n_slices, P, args.fused_prior, args.concurrent_prior)
     traffic = read_traffic(name)
     if name == "prior":
         ops = prior_lane_ops(wl.n, wl.n_slices, wl.neighbours)

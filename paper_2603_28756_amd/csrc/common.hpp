@@ -23,6 +23,13 @@ template <typename T> TOMO_DEV cpx<T> scale(cpx<T> a, T s) { return mk(a.re * s,
 // Row-major element counts can exceed 2^31 for the largest grids.
 typedef int64_t idx_t;
 
+// Layout of F K / P^2 ([P] rows v, P/2 columns u; the Nyquist column is stored apart):
+// columns in groups of 4, each group row-major [P][4], so that the columns of a pass-C
+// column tile are contiguous along the rows that pass walks.
+TOMO_DEV idx_t fk_index(int v, int u, int P) {
+  return ((idx_t)(u >> 2) * P + v) * 4 + (u & 3);
+}
+
 // Parameters of the qGGMRF potential passed by value to kernels.
 struct PriorParams {
   float beta;        // prior weight

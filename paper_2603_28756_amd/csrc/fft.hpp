@@ -54,12 +54,17 @@ TOMO_DEV cpx<T> rot_const(cpx<T> a, int j, int L) {
 }
 
 // In-register radix-R DFT (R = 1, 2, 4, 8, 16), natural order in and out:
-// radix-2 decimation in frequency followed by a bit-reversal renaming.
-template <int R, int DIR, typename T>
+// radix-2 decimation in frequency followed by a bit-reversal renaming.  HZ: the upper
+// half of the inputs is zero (a zero-padded transform), so the first level only rotates.
+template <int R, int DIR, bool HZ = false, typename T>
 TOMO_DEV void dft_reg(cpx<T>* v) {
   if constexpr (R > 1) {
+    if constexpr (HZ) {
 #pragma unroll
-    for (int h = R / 2; h >= 1; h >>= 1) {
+      for (int j = 0; j < R / 2; ++j) v[j + R / 2] = rot_const<DIR>(v[j], j, R);
+    }
+#pragma unroll
+    for (int h = HZ ? R / 4 : R / 2; h >= 1; h >>= 1) {
 #pragma unroll
       for (int blk = 0; blk < R; blk += 2 * h) {
 #pragma unroll
@@ -120,7 +125,8 @@ TOMO_DEV void stage_twiddles(const cpx<T>* __restrict__ tw, int e, cpx<T>* w) {
 }
 
 // Twiddle + radix-R butterfly of every butterfly this thread owns (registers only).
-template <class PL, int S, int DIR, typename T>
+// HZ (first stage only): inputs at positions >= P/2 are zero.
+template <class PL, int S, int DIR, bool HZ = false, typename T>
 TOMO_DEV void stage_compute(cpx<T>* v, int q, const cpx<T>* __restrict__ tw) {
   constexpr int R = PL::radix(S), p = PL::span(S), E = PL::E, TPF = PL::TPF, P = PL::P;
 #pragma unroll
@@ -135,7 +141,9 @@ TOMO_DEV void stage_compute(cpx<T>* v, int q, const cpx<T>* __restrict__ tw) {
         for (int r = 1; r < R; ++r) v[m * R + r] = cmul(v[m * R + r], DIR < 0 ? w[r] : conj(w[r]));
       }
     }
-    dft_reg<R, DIR>(&v[m * R]);
+    // position j + r P/R >= P/2 exactly when r >= R/2 (one butterfly per thread, E = R)
+    static_assert(!HZ || (S == 0 && E == R), "zero upper half: first stage with E = R only");
+    dft_reg<R, DIR, HZ>(&v[m * R]);
   }
 }
 
@@ -175,10 +183,10 @@ TOMO_DEV int reg_pos(int q, int m, int r) { return q + m * TPF + r * (P / R); }
 
 // Run stages S..NS-1 of plan PL; v enters in the input layout of stage S and leaves in
 // the output layout of the last stage.  Every thread of the block must call this
-// (it contains block barriers).
-template <class PL, int S, int DIR, typename T, class Lds>
+// (it contains block barriers).  HZ: the input's upper half (positions >= P/2) is zero.
+template <class PL, int S, int DIR, bool HZ = false, typename T, class Lds>
 TOMO_DEV void run_stages(cpx<T>* v, int q, const cpx<T>* __restrict__ tw, Lds& lds) {
-  stage_compute<PL, S, DIR>(v, q, tw);
+  stage_compute<PL, S, DIR, HZ && S == 0>(v, q, tw);
   if constexpr (S + 1 < PL::NS) {
     stage_store<PL, S>(v, q, lds);
     __syncthreads();

@@ -633,7 +633,7 @@ __global__ void psf_embed_kernel(const cpx<double>* __restrict__ grid,
   emb[i] = mk(k, 0.0);
 }
 
-// fk[v][u] = Re S[v][u] / P^2 for u < P/2; fkn[v] = Re S[v][P/2] / P^2.
+// fk[fk_index(v, u)] = Re S[v][u] / P^2 for u < P/2; fkn[v] = Re S[v][P/2] / P^2.
 __global__ void fk_store_kernel(const cpx<double>* __restrict__ spec, float* __restrict__ fk,
                                 float* __restrict__ fkn, int P) {
   const idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -642,7 +642,7 @@ __global__ void fk_store_kernel(const cpx<double>* __restrict__ spec, float* __r
   const int v = (int)(i / (H + 1)), u = (int)(i - (idx_t)v * (H + 1));
   const double inv = 1.0 / ((double)P * (double)P);
   const double val = spec[(idx_t)v * P + u].re * inv;
-  if (u < H) fk[(idx_t)v * H + u] = (float)val;
+  if (u < H) fk[fk_index(v, u, P)] = (float)val;
   else fkn[v] = (float)val;
 }
 
@@ -653,7 +653,7 @@ __global__ void fk_export_kernel(const float* __restrict__ fk, const float* __re
   if (i >= (idx_t)P * (H + 1)) return;
   const int v = (int)(i / (H + 1)), u = (int)(i - (idx_t)v * (H + 1));
   const float s = (float)P * (float)P;
-  out[i] = (u < H ? fk[(idx_t)v * H + u] : fkn[v]) * s;
+  out[i] = (u < H ? fk[fk_index(v, u, P)] : fkn[v]) * s;
 }
 
 // sum of (scale * g[row][j*stride])^2 over rows x n_out samples; two-stage deterministic.

@@ -106,7 +106,8 @@ TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restric
     for (int r = 0; r < R0; ++r) {
       const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
       cpx<float> zz = mk(0.f, 0.f);
-      if (active && n < N) {
+      // positions >= P/2 >= N are the zero padding: r >= R0/2 (E = R0) never loads
+      if (2 * r < R0 && active && n < N) {
         const float a1 = xk[row1 + n], a2 = xk[row2 + n];
         if constexpr (MODE == MODE_POWER) {
           zz = mk(s * a1, s * a2);
@@ -121,7 +122,7 @@ TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restric
     }
 
   fft::LdsRow<float> L{lds + pr * REG};
-  fft::run_stages<PL, 0, -1>(v, q, tw, L);
+  fft::run_stages<PL, 0, -1, true>(v, q, tw, L);
 #pragma unroll
   for (int m = 0; m < E / RL; ++m)
 #pragma unroll
@@ -185,11 +186,12 @@ TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
-      v[m * R0 + r] = n < N ? in[(idx_t)n * H] : mk(0.f, 0.f);
+      // positions >= P/2 >= N are the zero padding (r >= R0/2)
+      v[m * R0 + r] = (2 * r < R0 && n < N) ? in[(idx_t)n * H] : mk(0.f, 0.f);
     }
 
   fft::LdsCols<float, TC, 1> L{lds, c};
-  fft::run_stages<PL, 0, -1>(v, q, tw, L);
+  fft::run_stages<PL, 0, -1, true>(v, q, tw, L);
 
   if (bx == 0) {
     // Column 0 carries the DC column (real part) and the Nyquist column (imag part); both
@@ -208,11 +210,11 @@ TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
         const cpx<float> zv = v[m * RL + r];
         if (c == 0) {
           const cpx<float> zm = conj(L.ld((P - n) & (P - 1)));
-          const float f0 = fk[(idx_t)n * H], fN = fkn[n];
+          const float f0 = fk[fk_index(n, 0, P)], fN = fkn[n];
           const float a = 0.5f * (f0 + fN), b = 0.5f * (f0 - fN);
           v[m * RL + r] = mk(a * zv.re + b * zm.re, a * zv.im + b * zm.im);
         } else {
-          v[m * RL + r] = scale(zv, fk[(idx_t)n * H + u]);
+          v[m * RL + r] = scale(zv, fk[fk_index(n, u, P)]);
         }
       }
     __syncthreads();
@@ -222,7 +224,7 @@ TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int n = fft::reg_pos<P, TPF, RL>(q, m, r);
-        v[m * RL + r] = scale(v[m * RL + r], fk[(idx_t)n * H + u]);
+        v[m * RL + r] = scale(v[m * RL + r], fk[fk_index(n, u, P)]);
       }
   }
 
@@ -234,7 +236,7 @@ TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const int n = fft::reg_pos<P, TPF, R0>(q, m, r);
-      if (n < N) out[(idx_t)n * H] = v[m * R0 + r];
+      if (2 * r < R0 && n < N) out[(idx_t)n * H] = v[m * R0 + r];  // rows >= P/2 are cropped
     }
 }
 
@@ -657,7 +659,7 @@ TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __re
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int n = fft::reg_pos<P, TPF, RL>(q, m, r);
-        if (n < N) {
+        if (2 * r < RL && n < N) {  // positions >= P/2 (r >= RL/2) are cropped
           tyt[LY::ty(2 * pr, n)] = v[m * RL + r].re;
           tyt[LY::ty(2 * pr + 1, n)] = v[m * RL + r].im;
         }
