@@ -838,28 +838,35 @@ rows_inv_kernel(const cpx<float>* __restrict__ S2, const float* __restrict__ xk,
 }
 
 // -------------------------------------------------------------------------------- finalize
+// One block of FIN_NT threads: the partial sums are read with FIN_NT loads in flight (the
+// kernel is bound by that latency), then summed in a fixed tree order.
+constexpr int FIN_NT = 1024;
 template <int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(FIN_NT)
 finalize_kernel(const double* __restrict__ partials, int nblocks,
                 const double* __restrict__ prior_partials, int nprior, double* __restrict__ scal,
                 double* __restrict__ hist, int32_t* __restrict__ rhist,
                 double* __restrict__ obj_out) {
-  __shared__ double sh[4][256];
+  __shared__ double sh[4][FIN_NT];
   const int t = threadIdx.x;
   double a[4] = {0, 0, 0, 0};
-  for (int b = t; b < nblocks; b += 256)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] += partials[(idx_t)b * 4 + i];
+  for (int b = t; b < nblocks; b += FIN_NT) {
+    const double4 pv = *reinterpret_cast<const double4*>(partials + (idx_t)b * 4);
+    a[0] += pv.x;
+    a[1] += pv.y;
+    a[2] += pv.z;
+    a[3] += pv.w;
+  }
   // Phi from the separate prior kernel (slot 0 of its partials) lands in slot 2; its slot 1
   // holds <y, b> when the prior kernel wrote y and gp - b (zero otherwise)
-  for (int b = t; b < nprior; b += 256) {
+  for (int b = t; b < nprior; b += FIN_NT) {
     a[2] += prior_partials[(idx_t)b * 4];
     a[1] += prior_partials[(idx_t)b * 4 + 1];
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) sh[i][t] = a[i];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = FIN_NT / 2; s > 0; s >>= 1) {
     if (t < s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) sh[i][t] += sh[i][t + s];
@@ -1375,13 +1382,13 @@ hipError_t launch_finalize(int mode, const double* partials, int nblocks,
                            double* obj_hist, int32_t* restart_hist, double* obj_out,
                            hipStream_t st) {
   if (mode == MODE_POWER)
-    hipLaunchKernelGGL((finalize_kernel<MODE_POWER>), dim3(1), dim3(256), 0, st, partials,
+    hipLaunchKernelGGL((finalize_kernel<MODE_POWER>), dim3(1), dim3(FIN_NT), 0, st, partials,
                        nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   else if (mode == MODE_GRAD)
-    hipLaunchKernelGGL((finalize_kernel<MODE_GRAD>), dim3(1), dim3(256), 0, st, partials,
+    hipLaunchKernelGGL((finalize_kernel<MODE_GRAD>), dim3(1), dim3(FIN_NT), 0, st, partials,
                        nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   else  // MODE_FISTA, MODE_FISTA_Y
-    hipLaunchKernelGGL((finalize_kernel<MODE_FISTA>), dim3(1), dim3(256), 0, st, partials,
+    hipLaunchKernelGGL((finalize_kernel<MODE_FISTA>), dim3(1), dim3(FIN_NT), 0, st, partials,
                        nblocks, prior_partials, nprior, scal, obj_hist, restart_hist, obj_out);
   return hipGetLastError();
 }
