@@ -228,13 +228,13 @@ int tbegin(tomo_plan p, int cls, hipStream_t s) {
   if (!(p->tmask & (1u << cls))) return -1;
   hipEvent_t a = take_event(p), b = take_event(p);
   if (!a || !b) return -1;
-  hipEventRecord(a, s);
+  (void)hipEventRecord(a, s);
   p->pending.push_back({a, b, cls});
   return (int)p->pending.size() - 1;
 }
 int tbegin(tomo_plan p, int cls) { return tbegin(p, cls, p->stream); }
 void tend(tomo_plan p, int idx, hipStream_t s) {
-  if (idx >= 0) hipEventRecord(p->pending[idx].b, s);
+  if (idx >= 0) (void)hipEventRecord(p->pending[idx].b, s);
 }
 void tend(tomo_plan p, int idx) { tend(p, idx, p->stream); }
 
@@ -526,13 +526,13 @@ tomo_status get_graph(tomo_plan p, int level, int ik, int ikm1, int inext, const
   }
   hipError_t e = hipStreamEndCapture(p->gstream, &graph);
   if (s != TOMO_OK) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return s;
   }
   if (e != hipSuccess) return fail(p, TOMO_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
   hipGraphExec_t exec = nullptr;
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(p, TOMO_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
   p->graphs.push_back({{level, ik * 9 + ikm1 * 3 + inext, p->nz, hist, rhist, hist != nullptr}, exec});
   *out = exec;
@@ -691,7 +691,7 @@ tomo_status tomo_plan_set_workspace(tomo_plan p, void* dev, size_t bytes) {
   if (!aligned(dev)) return fail(p, TOMO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (bytes < p->need)
     return fail(p, TOMO_ERR_WORKSPACE_TOO_SMALL, "workspace %zu B < required %zu B", bytes, p->need);
-  for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);  // captured with the old pointers
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);  // captured with the old pointers
   p->graphs.clear();
   p->ws = static_cast<char*>(dev);
   p->ws_bytes = bytes;
@@ -1046,7 +1046,7 @@ tomo_status tomo_batch_set_workspace(tomo_batch b, void* dev, size_t bytes) {
   if (!aligned(dev)) return bfail(b, TOMO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (bytes < b->need) return bfail(b, TOMO_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
   if (b->gexec) {
-    hipGraphExecDestroy(b->gexec);
+    (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
   }
   b->ws = static_cast<char*>(dev);
@@ -1104,7 +1104,7 @@ tomo_status tomo_batch_reconstruct(tomo_batch b, const float* const* sinos, floa
         BHIPCHK(b, hipEventCreateWithFlags(&b->gev_out, hipEventDisableTiming));
       }
       if (!b->gexec || b->graph_rot != rot) {
-        if (b->gexec) hipGraphExecDestroy(b->gexec);
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
         hipGraph_t g = nullptr;
         BHIPCHK(b, hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
@@ -1118,12 +1118,12 @@ tomo_status tomo_batch_reconstruct(tomo_batch b, const float* const* sinos, floa
         }
         const hipError_t e = hipStreamEndCapture(b->gstream, &g);
         if (s != TOMO_OK) {
-          if (g) hipGraphDestroy(g);
+          if (g) (void)hipGraphDestroy(g);
           return s;
         }
         if (e != hipSuccess) return bfail(b, TOMO_ERR_HIP, "batch graph capture: %s", hipGetErrorString(e));
         const hipError_t e2 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e2 != hipSuccess) return bfail(b, TOMO_ERR_HIP, "batch graph instantiate: %s", hipGetErrorString(e2));
         b->graph_rot = rot;
       }
@@ -1170,13 +1170,13 @@ tomo_status tomo_batch_reconstruct(tomo_batch b, const float* const* sinos, floa
 
 tomo_status tomo_batch_destroy(tomo_batch b) {
   if (!b) return TOMO_OK;
-  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->gstream) {
-    hipStreamSynchronize(b->gstream);
-    hipStreamDestroy(b->gstream);
+    (void)hipStreamSynchronize(b->gstream);
+    (void)hipStreamDestroy(b->gstream);
   }
-  if (b->gev_in) hipEventDestroy(b->gev_in);
-  if (b->gev_out) hipEventDestroy(b->gev_out);
+  if (b->gev_in) (void)hipEventDestroy(b->gev_in);
+  if (b->gev_out) (void)hipEventDestroy(b->gev_out);
   delete b;
   return TOMO_OK;
 }
@@ -1215,8 +1215,8 @@ void fill_tiles(const Level& l, tomo_tiles_t* o) {
 }
 void drop_graphs(tomo_plan p) {
   if (p->graphs.empty()) return;
-  if (p->gstream) hipStreamSynchronize(p->gstream);
-  for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
+  if (p->gstream) (void)hipStreamSynchronize(p->gstream);
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   p->graphs.clear();
 }
 }  // namespace
@@ -1255,7 +1255,7 @@ tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(p, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return fail(p, TOMO_ERR_HIP, "event create failed");
   }
   tomo_status s = TOMO_OK;
@@ -1323,32 +1323,32 @@ tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
       std::memcpy(chosen[li].ms, ms, sizeof ms);
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return s;
 }
 
 tomo_status tomo_plan_destroy(tomo_plan p) {
   if (!p) return TOMO_OK;
-  if (!p->pending.empty()) hipStreamSynchronize(p->stream);
+  if (!p->pending.empty()) (void)hipStreamSynchronize(p->stream);
   for (auto& e : p->pending) {
-    hipEventDestroy(e.a);
-    hipEventDestroy(e.b);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
-  for (hipEvent_t e : p->pool) hipEventDestroy(e);
-  for (auto& g : p->graphs) hipGraphExecDestroy(g.exec);
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   if (p->gstream) {
-    hipStreamSynchronize(p->gstream);
-    hipStreamDestroy(p->gstream);
+    (void)hipStreamSynchronize(p->gstream);
+    (void)hipStreamDestroy(p->gstream);
   }
   if (p->pstream) {
-    hipStreamSynchronize(p->pstream);
-    hipStreamDestroy(p->pstream);
+    (void)hipStreamSynchronize(p->pstream);
+    (void)hipStreamDestroy(p->pstream);
   }
-  if (p->pev_fork) hipEventDestroy(p->pev_fork);
-  if (p->pev_join) hipEventDestroy(p->pev_join);
-  if (p->gev_in) hipEventDestroy(p->gev_in);
-  if (p->gev_out) hipEventDestroy(p->gev_out);
+  if (p->pev_fork) (void)hipEventDestroy(p->pev_fork);
+  if (p->pev_join) (void)hipEventDestroy(p->pev_join);
+  if (p->gev_in) (void)hipEventDestroy(p->gev_in);
+  if (p->gev_out) (void)hipEventDestroy(p->gev_out);
   delete p;
   return TOMO_OK;
 }

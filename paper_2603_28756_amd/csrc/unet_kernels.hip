@@ -39,57 +39,7 @@ TOMO_DEV f32x4 mfma(u16x8 a, u16x8 b, f32x4 c) {
 // ------------------------------------------------------------------ 3x3 conv, forward
 // y[p, co] = act(bias[co] + sum_{tap, ci} w[co][tap][ci] x[p + tap, ci]) (zero padding), then
 // multiplied by (mask[p, co] > 0) when a mask is given (the ReLU derivative of the forward
-// activation when this kernel computes an input gradient).  A block computes 64 pixels of
-// one image row (16 per wave) x COT output channels.
-constexpr int CV_PX = 64;
-
-template <int COT, bool RELU, bool BIAS, bool MASK>
-__global__ void __launch_bounds__(256)
-conv3x3_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
-               const float* __restrict__ bias, uint16_t* __restrict__ y, int ldy,
-               const uint16_t* __restrict__ mask, int ldm, int cin, int H, int W, int ntx) {
-  constexpr int NT = COT / 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tx = blockIdx.x % ntx, cot = blockIdx.x / ntx;
-  const int row = blockIdx.y;
-  const size_t img = (size_t)blockIdx.z * H * W;
-  const int px = tx * CV_PX + wave * 16 + (lane & 15);
-  const int kq = (lane >> 4) * 8;
-  const int co0 = cot * COT;
-  f32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const size_t wstride = (size_t)16 * 9 * cin;  // between 16-channel output groups
-  for (int tap = 0; tap < 9; ++tap) {
-    const int yy = row + tap / 3 - 1, xx = px + tap % 3 - 1;
-    const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const uint16_t* xa = x + (ok ? (img + (size_t)yy * W + xx) * ldx : 0) + kq;
-    const uint16_t* wb = w + ((size_t)(co0 + (lane & 15)) * 9 + tap) * cin + kq;
-    for (int c0 = 0; c0 < cin; c0 += 32) {
-      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (ok) a = ld8(xa + c0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = mfma(a, ld8(wb + t * wstride + c0), acc[t]);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = co0 + 16 * t + (lane & 15);
-    const float bv = BIAS ? bias[co] : 0.f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int p = tx * CV_PX + wave * 16 + 4 * (lane >> 4) + i;
-      if (p < W) {
-        const size_t pix = img + (size_t)row * W + p;
-        float v = acc[t][i] + bv;
-        if (RELU) v = fmaxf(v, 0.f);
-        if (MASK && !(bf2f(mask[pix * ldm + co]) > 0.f)) v = 0.f;
-        y[pix * ldy + co] = f2bf(v);
-      }
-    }
-  }
-}
-
+// activation when this kernel computes an input gradient).
 // 3x3 conv on 2D pixel tiles staged through LDS.  A block owns a tile 16 pixels wide and
 // 4*RPW rows high (wave w: rows w*RPW .. w*RPW+RPW-1) x BN output channels.  For each chunk
 // of 32 input channels it stages (a) the input tile with a one-pixel halo, 64 bytes per
