@@ -45,14 +45,17 @@ CLASS_NAMES = ["rows_fwd", "cols_conv", "rows_inv", "finalize", "backproject", "
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_volume_64x512.txt")
 
 
+# sources that determine the iteration kernels and their launch configuration
+HOT_SOURCES = ("common.hpp", "fft.hpp", "kernels.hpp", "tomo_api.cpp", "toeplitz_kernels.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_28756_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in HOT_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
