@@ -257,10 +257,10 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
 
 // ---------------------------------------------------------------------------- prior (3D)
 // gp = beta grad Phi(y), y = x_k + mu (x_k - x_{k-1}), with every neighbour pair evaluated
-// once.  A block owns a 16 x 16 column of voxels (one per thread) and marches through 16
-// slices, keeping planes z and z+1 (with a one-voxel halo) in LDS.  Per plane each thread
-// evaluates the forward pairs of its voxel: 4 in-plane offsets (0,1), (1,-1), (1,0), (1,1)
-// and the 9 offsets into plane z+1; the forward pairs that start on the halo ring and end
+// once.  A block owns a TX x 16 column of voxels (32 x 16 by default, one per thread) and
+// marches through 16 slices, keeping planes z and z+1 (with a one-voxel halo) in LDS.  Per
+// plane each thread evaluates the forward pairs of its voxel: 4 in-plane offsets (0,1),
+// (1,-1), (1,0), (1,1) and the 9 offsets into plane z+1; the forward pairs that start on the halo ring and end
 // inside the tile are spread over the threads as one (position, offset) item each.  A pair's
 // value enters its first voxel with + (kept in registers) and its second with - (read back
 // from LDS by the voxel at the far end; rho' is odd).  Tiles whose halo ring lies inside the
@@ -269,13 +269,16 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
 // block also sums rho over the forward pairs of its own voxels.
 //
 // LDS layout: each wave owns an 8 x 8 block of the tile and planes are stored with a row
-// stride of 24 floats, so that the 8 rows of a wave (offsets 0, 24, ..., 168) fall on
-// disjoint bank ranges for both 32-lane halves (32 banks) and the whole wave (64 banks);
-// every access of a wave to its own block shifted by a constant (a neighbour offset) is
-// then free of bank conflicts.
-constexpr int PR_T = 16, PR_ZC = 16, PR_NT = 256;
-constexpr int PR_H = PR_T + 2, PR_HA = PR_H * PR_H;  // halo width and element count
-constexpr int PR_S = 24, PR_PA = PR_H * PR_S;        // LDS row stride and plane size
+// stride S (24 for 16-wide tiles, 40 for 32-wide) for which the 8 rows of a wave (offsets
+// 0, S, ..., 7 S) fall on disjoint bank ranges for both 32-lane halves (32 banks) and the
+// whole wave (64 banks); every access of a wave to its own block shifted by a constant (a
+// neighbour offset) is then free of bank conflicts.
+constexpr int PR_TX = 32, PR_TY = 16, PR_ZC = 16;  // tile columns, rows, slices
+constexpr int PR_NT = PR_TX * PR_TY;                       // one voxel per thread
+constexpr int PR_WX = PR_TX / 8;                           // 8 x 8 wave blocks per tile row
+constexpr int PR_HX = PR_TX + 2, PR_HY = PR_TY + 2, PR_HA = PR_HX * PR_HY;  // halo tile
+constexpr int PR_S = PR_TX == 32 ? 40 : 24, PR_PA = PR_HY * PR_S;  // LDS row stride, plane
+static_assert(PR_TX == 16 || PR_TX == 32, "tile width");
 
 // rho'(d) / c_grad and rho(d) for q = 2, arranged for few instructions:
 //   rho'(d) / c_grad = d r (1 + (q/p - 1) r),  r = 1 / (1 + w),
@@ -309,11 +312,11 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
                          const float* __restrict__ bvec, float* __restrict__ yout,
                          double* __restrict__ part_out, int N, int nz, int c0, int r0, int z0,
                          float mu, bool fista, const PriorParams& pp) {
-  constexpr int H = PR_H, HA = PR_HA, S = PR_S;
+  constexpr int HX = PR_HX, HY = PR_HY, HA = PR_HA, S = PR_S, TX = PR_TX, TY = PR_TY;
   const int t = threadIdx.x;
-  // own voxel: wave w covers rows 8 (w / 2) .. +7 and columns 8 (w % 2) .. +7 of the tile
+  // own voxel: wave w covers rows 8 (w / WX) .. +7 and columns 8 (w % WX) .. +7 of the tile
   const int wv = t >> 6, ln = t & 63;
-  const int tr = 8 * (wv >> 1) + (ln >> 3), tc = 8 * (wv & 1) + (ln & 7);
+  const int tr = 8 * (wv / PR_WX) + (ln >> 3), tc = 8 * (wv % PR_WX) + (ln & 7);
   const int s = (tr + 1) * S + tc + 1;  // own position in a plane buffer
   const int z1 = min(z0 + PR_ZC, nz);
   // neighbour weights with beta and the rho' prefactor folded in
@@ -324,28 +327,35 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
     const int r = r0 - 1 + a, c = c0 - 1 + b;
     return r >= 0 && r < N && c >= 0 && c < N;
   };
-  auto in_tile = [&](int a, int b) { return a >= 1 && a <= PR_T && b >= 1 && b <= PR_T; };
+  auto in_tile = [&](int a, int b) { return a >= 1 && a <= TY && b >= 1 && b <= TX; };
 
-  // Halo items, as (row a, column b) of the halo ring and an offset index.  In-plane (98):
-  // top row x offsets (1,-1),(1,0),(1,1); left column x (0,1),(1,1); right column x (1,-1);
-  // two corners.  Cross-plane (196): top row x dy=+1, bottom row x dy=-1, left column x
-  // dx=+1, right column x dx=-1 (3 each), four corners.  Items whose end leaves the tile are
-  // idle.
+  // Halo items, as (row a, column b) of the halo ring and an offset index.  In-plane
+  // (3 TX + 3 TY + 2): top row x offsets (1,-1),(1,0),(1,1); left column x (0,1),(1,1);
+  // right column x (1,-1); two corners.  Cross-plane (6 TX + 6 TY + 4): top row x dy=+1,
+  // bottom row x dy=-1, left column x dx=+1, right column x dx=-1 (3 each), four corners.
+  // Items whose end leaves the tile are idle.
   int in_a = -1, in_b = 0, in_o = 0;
-  if (t < 48) { in_a = 0; in_b = t / 3 + 1; in_o = 1 + t % 3; }
-  else if (t < 80) { const int k = t - 48; in_a = k / 2 + 1; in_b = 0; in_o = (k & 1) ? 3 : 0; }
-  else if (t < 96) { in_a = t - 79; in_b = H - 1; in_o = 1; }
-  else if (t == 96) { in_a = 0; in_b = 0; in_o = 3; }
-  else if (t == 97) { in_a = 0; in_b = H - 1; in_o = 1; }
+  {
+    constexpr int i0 = 3 * TX, i1 = i0 + 2 * TY, i2 = i1 + TY;
+    if (t < i0) { in_a = 0; in_b = t / 3 + 1; in_o = 1 + t % 3; }
+    else if (t < i1) { const int k = t - i0; in_a = k / 2 + 1; in_b = 0; in_o = (k & 1) ? 3 : 0; }
+    else if (t < i2) { in_a = t - i1 + 1; in_b = HX - 1; in_o = 1; }
+    else if (t == i2) { in_a = 0; in_b = 0; in_o = 3; }
+    else if (t == i2 + 1) { in_a = 0; in_b = HX - 1; in_o = 1; }
+  }
   int x_a = -1, x_b = 0, x_o = 0;
-  if (t < 48) { x_a = 0; x_b = t / 3 + 1; x_o = 6 + t % 3; }
-  else if (t < 96) { x_a = H - 1; x_b = (t - 48) / 3 + 1; x_o = (t - 48) % 3; }
-  else if (t < 144) { x_a = (t - 96) / 3 + 1; x_b = 0; x_o = 3 * ((t - 96) % 3) + 2; }
-  else if (t < 192) { x_a = (t - 144) / 3 + 1; x_b = H - 1; x_o = 3 * ((t - 144) % 3); }
-  else if (t == 192) { x_a = 0; x_b = 0; x_o = 8; }
-  else if (t == 193) { x_a = 0; x_b = H - 1; x_o = 6; }
-  else if (t == 194) { x_a = H - 1; x_b = 0; x_o = 2; }
-  else if (t == 195) { x_a = H - 1; x_b = H - 1; x_o = 0; }
+  {
+    constexpr int j0 = 3 * TX, j1 = 2 * j0, j2 = j1 + 3 * TY, j3 = j2 + 3 * TY;
+    if (t < j0) { x_a = 0; x_b = t / 3 + 1; x_o = 6 + t % 3; }
+    else if (t < j1) { x_a = HY - 1; x_b = (t - j0) / 3 + 1; x_o = (t - j0) % 3; }
+    else if (t < j2) { x_a = (t - j1) / 3 + 1; x_b = 0; x_o = 3 * ((t - j1) % 3) + 2; }
+    else if (t < j3) { x_a = (t - j2) / 3 + 1; x_b = HX - 1; x_o = 3 * ((t - j2) % 3); }
+    else if (t == j3) { x_a = 0; x_b = 0; x_o = 8; }
+    else if (t == j3 + 1) { x_a = 0; x_b = HX - 1; x_o = 6; }
+    else if (t == j3 + 2) { x_a = HY - 1; x_b = 0; x_o = 2; }
+    else if (t == j3 + 3) { x_a = HY - 1; x_b = HX - 1; x_o = 0; }
+    static_assert(j3 + 4 <= PR_NT && 3 * TX + 3 * TY + 2 <= PR_NT, "one item per thread");
+  }
   // resolve the items once: start and end positions, activity and validity
   int in_pos = 0, in_q = 0, x_pos = 0, x_q = 0;
   bool in_act = false, x_act = false, in_ok = true, x_ok = true;
@@ -382,12 +392,12 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
   int g0, g1 = 0, l0, l1 = 0;
   bool v0 = true, v1 = true;
   {
-    const int a = t / H, b = t - a * H;
+    const int a = t / HX, b = t - a * HX;
     g0 = (r0 - 1 + a) * N + (c0 - 1 + b);
     l0 = a * S + b;
     if constexpr (EDGE) v0 = inside(a, b);
     if (has_e1) {
-      const int a1 = e1 / H, b1 = e1 - a1 * H;
+      const int a1 = e1 / HX, b1 = e1 - a1 * HX;
       g1 = (r0 - 1 + a1) * N + (c0 - 1 + b1);
       l1 = a1 * S + b1;
       if constexpr (EDGE) v1 = inside(a1, b1);
@@ -551,13 +561,13 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
   __shared__ PriorLds<NB> L;
   // logical tile: x fastest, then y, then the slice chunk; XCD-contiguous so that tiles
   // sharing halo lines meet in one L2
-  const int ntx = (N + PR_T - 1) / PR_T, nty = ntx;
+  const int ntx = (N + PR_TX - 1) / PR_TX, nty = (N + PR_TY - 1) / PR_TY;
   const int lam = xcd_contiguous(blockIdx.x, ntx * nty * ((nz + PR_ZC - 1) / PR_ZC));
-  const int c0 = (lam % ntx) * PR_T, r0 = ((lam / ntx) % nty) * PR_T;
+  const int c0 = (lam % ntx) * PR_TX, r0 = ((lam / ntx) % nty) * PR_TY;
   const int z0 = (lam / (ntx * nty)) * PR_ZC;
   const float mu = mode_fista ? (float)scal[SC_MU] : 0.f;
   double* part = partials ? partials + (idx_t)blockIdx.x * 4 : nullptr;
-  const bool interior = r0 >= 1 && c0 >= 1 && r0 + PR_T + 1 <= N && c0 + PR_T + 1 <= N;
+  const bool interior = r0 >= 1 && c0 >= 1 && r0 + PR_TY + 1 <= N && c0 + PR_TX + 1 <= N;
   if (interior)
     prior_tile<NB, OBJ, QUAD, false, YG>(L, xk, xkm1, gp, bvec, yout, part, N, nz, c0, r0, z0, mu,
                                          mode_fista != 0, pp);
@@ -1339,7 +1349,7 @@ hipError_t launch_rows_inv(int P, int v, int mode, int neighbours, bool with_obj
 }
 
 int prior_blocks(int N, int nz) {
-  return ((N + PR_T - 1) / PR_T) * ((N + PR_T - 1) / PR_T) * ((nz + PR_ZC - 1) / PR_ZC);
+  return ((N + PR_TX - 1) / PR_TX) * ((N + PR_TY - 1) / PR_TY) * ((nz + PR_ZC - 1) / PR_ZC);
 }
 
 template <int NB, bool OBJ, bool QUAD>
