@@ -216,7 +216,7 @@ def run_learned(args) -> int:
 
     2000 training and 64 held-out 512^2 slices (ellipses + Gaussian texture, 60 angles,
     1% noise); training targets are the method's own reconstructions (300 iterations from
-    FBP); the U-Net (4 levels, 32 base channels) is trained on the GPU; both starts are run
+    FBP); the U-Net (--unet-levels levels, default 2, 32 base channels) is trained on the GPU; both starts are run
     on the held-out slices (solved together) and timed.  One JSON line.
     """
     import numpy as np
@@ -240,8 +240,9 @@ def run_learned(args) -> int:
     target_s = time.perf_counter() - t0
     print(f"targets: {target_s:.1f} s", file=sys.stderr, flush=True)
     scale = float(torch.sqrt(torch.mean(fbp * fbp)).item())
-    net = tomo.UNet(wl.n, wl.n, levels=4, base=32, max_batch=args.batch)
-    net.set_params(learned.init_params(4, 32, 7, dev))
+    levels = args.unet_levels
+    net = tomo.UNet(wl.n, wl.n, levels=levels, base=32, max_batch=args.batch)
+    net.set_params(learned.init_params(levels, 32, 7, dev))
     t0 = time.perf_counter()
     losses = learned.train(net, fbp, tgt, scale, args.epochs, args.batch, args.lr, seed=7)
     torch.cuda.synchronize()
@@ -250,7 +251,11 @@ def run_learned(args) -> int:
           file=sys.stderr, flush=True)
     del fbp, tgt
     res = learned.compare_starts(pr, test_s, net, scale, dev, long_iters=2000, net_batch=args.batch)
-    step_flop = 3 * 85.0e9 * args.batch  # forward + backward of one batch at 512^2
+    # 3x3 convolutions dominate: 2 x 9 cin cout flops per pixel at each level's resolution
+    shapes = learned.layer_shapes(levels, 32)
+    lvl = [l for l in range(levels) for _ in (0, 1)] + [l for l in range(levels - 2, -1, -1) for _ in (0, 1)]
+    fwd_flop = sum(18.0 * ci * co * (wl.n >> l) ** 2 for (ci, co), l in zip(shapes, lvl))
+    step_flop = 3 * fwd_flop * args.batch  # forward + backward of one batch
     out = {
         "metric": "time to 1e-4 relative objective gap, U-Net start (FBP start alongside)",
         "value": res["ms"]["total_unet"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -258,7 +263,8 @@ def run_learned(args) -> int:
         "vs_baseline": None, "dtype": "bf16 network, f32 reconstruction", "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "n_angles": wl.n_angles, "n_det": wl.n_det,
                    "noise": wl.noise, "train_slices": n_train, "test_slices": wl.n_slices,
-                   "target_iterations": args.target_iters, "unet": {"levels": 4, "base": 32},
+                   "target_iterations": args.target_iters,
+                   "unet": {"levels": levels, "base": 32, "forward_gflop_per_slice": fwd_flop / 1e9},
                    "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "neighbours": wl.neighbours},
         "result": res,
         "training": {"seconds": train_s_time, "steps": int(len(losses)),
@@ -288,6 +294,7 @@ def main() -> int:
     ap.add_argument("--epochs", type=int, default=10, help="learned start: training epochs")
     ap.add_argument("--batch", type=int, default=8, help="learned start: mini-batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="learned start: Adam learning rate")
+    ap.add_argument("--unet-levels", type=int, default=2, help="learned start: U-Net levels")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile schedule instead of the autotuned one")
     ap.add_argument("--copy-calib", action="store_true",
