@@ -359,9 +359,11 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
 
 // One application of the Toeplitz passes on level l (and, outside power mode, of the prior
 // kernel unless the fused-prior epilogue is selected).  *nprior receives the number of prior
-// partial sums the finalize must add (0 when none).  The prior kernel reads only x_k, x_{k-1}
-// and mu, so with the concurrent flag it runs on its own stream beside the forward-row and
-// column passes; the inverse-row pass, the only reader of its output, waits for it.
+// partial sums the finalize must add (0 when none).  In sequence, a FISTA step's prior
+// kernel also writes y and gp - b for passes R and R'.  With the concurrent flag the prior
+// kernel reads only x_k, x_{k-1} and mu and runs on its own stream beside the forward-row
+// and column passes (which then form y themselves); the inverse-row pass, the only reader
+// of its output, waits for it.
 tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const float* xk,
                             const float* xkm1, const float* b, float* out, bool obj,
                             int* nblocks, int* nprior = nullptr) {
