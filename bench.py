@@ -241,7 +241,7 @@ def run_learned(args) -> int:
     print(f"targets: {target_s:.1f} s", file=sys.stderr, flush=True)
     scale = float(torch.sqrt(torch.mean(fbp * fbp)).item())
     levels = args.unet_levels
-    net = tomo.UNet(wl.n, wl.n, levels=levels, base=32, max_batch=args.batch)
+    net = tomo.UNet(wl.n, wl.n, levels=levels, base=32, max_batch=max(args.batch, args.infer_batch))
     net.set_params(learned.init_params(levels, 32, 7, dev))
     t0 = time.perf_counter()
     losses = learned.train(net, fbp, tgt, scale, args.epochs, args.batch, args.lr, seed=7)
@@ -250,7 +250,7 @@ def run_learned(args) -> int:
     print(f"training: {train_s_time:.1f} s, loss {np.mean(losses[:20]):.3e} -> {np.mean(losses[-20:]):.3e}",
           file=sys.stderr, flush=True)
     del fbp, tgt
-    res = learned.compare_starts(pr, test_s, net, scale, dev, long_iters=2000, net_batch=args.batch)
+    res = learned.compare_starts(pr, test_s, net, scale, dev, long_iters=2000, net_batch=args.infer_batch)
     # 3x3 convolutions dominate: 2 x 9 cin cout flops per pixel at each level's resolution
     shapes = learned.layer_shapes(levels, 32)
     lvl = [l for l in range(levels) for _ in (0, 1)] + [l for l in range(levels - 2, -1, -1) for _ in (0, 1)]
@@ -265,7 +265,8 @@ def run_learned(args) -> int:
                    "noise": wl.noise, "train_slices": n_train, "test_slices": wl.n_slices,
                    "target_iterations": args.target_iters,
                    "unet": {"levels": levels, "base": 32, "forward_gflop_per_slice": fwd_flop / 1e9},
-                   "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "neighbours": wl.neighbours},
+                   "epochs": args.epochs, "batch": args.batch, "infer_batch": args.infer_batch,
+                   "lr": args.lr, "neighbours": wl.neighbours},
         "result": res,
         "training": {"seconds": train_s_time, "steps": int(len(losses)),
                      "ms_per_step": 1e3 * train_s_time / max(1, len(losses)),
@@ -295,6 +296,7 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=8, help="learned start: mini-batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="learned start: Adam learning rate")
     ap.add_argument("--unet-levels", type=int, default=2, help="learned start: U-Net levels")
+    ap.add_argument("--infer-batch", type=int, default=8, help="learned start: slices per inference call")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile schedule instead of the autotuned one")
     ap.add_argument("--copy-calib", action="store_true",
