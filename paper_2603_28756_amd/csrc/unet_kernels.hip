@@ -246,14 +246,25 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* _
   if (blockIdx.x == 0 && t < 64 && co0 + t < cout) partb[(size_t)s * cout + co0 + t] = bsum;
 }
 
-// out[i] = sum_s part[s][i] (fixed order), optionally accumulated into out
-__global__ void sum_splits_kernel(const float* __restrict__ part, int nsplit, size_t n,
-                                  float* __restrict__ out) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// out[i] = sum_s part[s][i] in a fixed order: a block takes 64 outputs; thread group g (of
+// SS_G) sums the splits g, g + SS_G, ... in order, then the group sums are added in order.
+constexpr int SS_G = 4;
+__global__ void __launch_bounds__(64 * SS_G)
+sum_splits_kernel(const float* __restrict__ part, int nsplit, size_t n, float* __restrict__ out) {
+  __shared__ float sg[SS_G][64];
+  const int il = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const size_t i = (size_t)blockIdx.x * 64 + il;
   float a = 0.f;
-  for (int s = 0; s < nsplit; ++s) a += part[(size_t)s * n + i];
-  out[i] = a;
+  if (i < n)
+    for (int s = g; s < nsplit; s += SS_G) a += part[(size_t)s * n + i];
+  sg[g][il] = a;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    float t = sg[0][il];
+#pragma unroll
+    for (int k = 1; k < SS_G; ++k) t += sg[k][il];
+    out[i] = t;
+  }
 }
 
 // ------------------------------------------------- first layer (one input channel), fp32
@@ -300,21 +311,32 @@ conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ 
   const int t = threadIdx.x;
   const int pb = blockIdx.x * px_per_blk, pe = min(npx, pb + px_per_blk);
   const int HW = H * W;
-  // thread t: channel co = t % cout, pixel lane t / cout
+  // thread t: channel co = t % cout, pixel lane t / cout; the pixel's image, row and column
+  // are stepped along (no division per pixel)
   const int lanes = 256 / cout;
   const int co = t % cout, pl = t / cout;
   float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (pl < lanes) {
-    for (int p = pb + pl; p < pe; p += lanes) {
+  if (pl < lanes && pb + pl < pe) {
+    int p = pb + pl;
+    int b = p / HW, r = (p - b * HW) / W, c = p - b * HW - r * W;
+    for (; p < pe; p += lanes) {
       const float d = bf2f(dz[(size_t)p * cout + co]);
-      const int b = p / HW, rem = p - b * HW, r = rem / W, c = rem - r * W;
+      const float* img = fbp + (size_t)b * HW;
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int yy = r + tap / 3 - 1, xx = c + tap % 3 - 1;
         if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          acc[tap] = fmaf(d, fbp[(size_t)b * HW + (size_t)yy * W + xx] * inv_s, acc[tap]);
+          acc[tap] = fmaf(d, img[yy * W + xx] * inv_s, acc[tap]);
       }
       acc[9] += d;
+      c += lanes;
+      while (c >= W) {
+        c -= W;
+        if (++r == H) {
+          r = 0;
+          ++b;
+        }
+      }
     }
   }
 #pragma unroll
@@ -328,16 +350,26 @@ conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ 
   }
 }
 
-// dw[co][tap] = sum_blk part[blk][co*10 + tap], db[co] = sum_blk part[blk][co*10 + 9]
-__global__ void conv_in_reduce_kernel(const float* __restrict__ part, int nblk, int cout,
-                                      float* __restrict__ dw, float* __restrict__ db) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= cout * 10) return;
+// dw[co][tap] = sum_blk part[blk][co*10 + tap], db[co] = sum_blk part[blk][co*10 + 9];
+// one block per output, fixed-order strided sums then a fixed-order tree
+__global__ void __launch_bounds__(256)
+conv_in_reduce_kernel(const float* __restrict__ part, int nblk, int cout, float* __restrict__ dw,
+                      float* __restrict__ db) {
+  __shared__ float sh[256];
+  const int o = blockIdx.x, t = threadIdx.x;
   float a = 0.f;
-  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * cout * 10 + o];
-  const int co = o / 10, k = o - co * 10;
-  if (k < 9) dw[co * 9 + k] = a;
-  else db[co] = a;
+  for (int b = t; b < nblk; b += 256) a += part[(size_t)b * cout * 10 + o];
+  sh[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int co = o / 10, k = o - co * 10;
+    if (k < 9) dw[co * 9 + k] = sh[0];
+    else db[co] = sh[0];
+  }
 }
 
 // ------------------------------------------------------------ pooling and upsampling
@@ -610,9 +642,9 @@ hipError_t nn_conv3x3_wgrad(const uint16_t* dz, int ldz, const uint16_t* x, int 
   hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(pl.ntn, pl.ntc, pl.nsplit), dim3(256), 0, st, dz,
                      ldz, x, ldx, part, partb, cin, cout, H, W, npx, pl.px_per_split);
   const size_t nw = (size_t)cout * 9 * cin;
-  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(nw, 64)), dim3(64 * SS_G), 0, st, part,
                      pl.nsplit, nw, dw);
-  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(cout, 256)), dim3(256), 0, st, partb,
+  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(cout, 64)), dim3(64 * SS_G), 0, st, partb,
                      pl.nsplit, (size_t)cout, db);
   return hipGetLastError();
 }
@@ -626,7 +658,8 @@ hipError_t nn_conv_in(const float* fbp, float inv_s, const float* w, const float
   return hipGetLastError();
 }
 
-int nn_conv_in_wgrad_blocks(int npx) { return (npx + 4095) / 4096; }
+constexpr int CIN_WG_PX = 1024;  // pixels per block of the first-layer weight gradient
+int nn_conv_in_wgrad_blocks(int npx) { return (npx + CIN_WG_PX - 1) / CIN_WG_PX; }
 
 hipError_t nn_conv_in_wgrad(const uint16_t* dz, const float* fbp, float inv_s, float* dw,
                             float* db, int cout, int B, int H, int W, float* scratch,
@@ -635,9 +668,9 @@ hipError_t nn_conv_in_wgrad(const uint16_t* dz, const float* fbp, float inv_s, f
   const int npx = B * H * W, nb = nn_conv_in_wgrad_blocks(npx);
   if ((size_t)nb * cout * 10 > scratch_floats) return hipErrorInvalidValue;
   hipLaunchKernelGGL(conv_in_wgrad_kernel, dim3(nb), dim3(256), 256 * 10 * sizeof(float), st, dz,
-                     fbp, inv_s, scratch, cout, H, W, npx, 4096);
-  hipLaunchKernelGGL(conv_in_reduce_kernel, dim3(blocks_for((size_t)cout * 10, 256)), dim3(256), 0,
-                     st, scratch, nb, cout, dw, db);
+                     fbp, inv_s, scratch, cout, H, W, npx, CIN_WG_PX);
+  hipLaunchKernelGGL(conv_in_reduce_kernel, dim3(cout * 10), dim3(256), 0, st, scratch, nb, cout,
+                     dw, db);
   return hipGetLastError();
 }
 
