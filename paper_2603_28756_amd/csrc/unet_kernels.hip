@@ -192,29 +192,37 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* _
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int pl = t >> 3, cg = (t & 7) * 8;
-  // this thread's column group of the x tile: tap and channel are fixed over the loop
+  // staging: threads 0..127 read dz, threads 128..255 read x; each takes two adjacent
+  // pixels (2 pp, 2 pp + 1) of one 8-channel group and writes each channel's pair of pixels
+  // as one 32-bit LDS word (the tiles are stored [channel][pixel])
+  const int half = t >> 7, pp = (t & 127) >> 3, cg = (t & 7) * 8;
+  // the column group of the x tile: tap and channel are fixed over the loop
   const int n = n0 + cg;
   const int tap = n < nn ? n / cin : 0, ci = n - tap * cin;
   const int ky = tap / 3 - 1, kx = tap % 3 - 1;
   float bsum = 0.f;
   const int HW = H * W;
+  uint16_t(*dst)[WG_K + WG_PAD] = half ? sb : sa;
   for (int p0 = pb; p0 < pe; p0 += WG_K) {
-    const int p = p0 + pl;
-    u16x8 va = {0, 0, 0, 0, 0, 0, 0, 0}, vb = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (p < pe) {
-      if (co0 + cg < cout) va = ld8(dz + (size_t)p * ldz + co0 + cg);
-      if (n < nn) {
-        const int b = p / HW, rem = p - b * HW, yy = rem / W + ky, xx = rem - (rem / W) * W + kx;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          vb = ld8(x + ((size_t)b * HW + (size_t)yy * W + xx) * ldx + ci);
+    u16x8 v[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = p0 + 2 * pp + e;
+      v[e] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (p < pe) {
+        if (half == 0) {
+          if (co0 + cg < cout) v[e] = ld8(dz + (size_t)p * ldz + co0 + cg);
+        } else if (n < nn) {
+          const int b = p / HW, rem = p - b * HW, yy = rem / W + ky, xx = rem - (rem / W) * W + kx;
+          if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+            v[e] = ld8(x + ((size_t)b * HW + (size_t)yy * W + xx) * ldx + ci);
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      sa[cg + j][pl] = va[j];
-      sb[cg + j][pl] = vb[j];
-    }
+    for (int j = 0; j < 8; ++j)
+      *reinterpret_cast<uint32_t*>(&dst[cg + j][2 * pp]) =
+          (uint32_t)v[0][j] | ((uint32_t)v[1][j] << 16);
     __syncthreads();
     if (blockIdx.x == 0 && t < 64) {
 #pragma unroll 8
