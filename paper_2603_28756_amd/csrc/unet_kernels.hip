@@ -203,8 +203,21 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* _
   float bsum = 0.f;
   const int HW = H * W;
   uint16_t(*dst)[WG_K + WG_PAD] = half ? sb : sa;
-  for (int p0 = pb; p0 < pe; p0 += WG_K) {
-    u16x8 v[2];
+  // image coordinates (slice, row, column) of the two pixels, stepped by WG_K per chunk so
+  // that the loop divides only once
+  int cb[2], cy[2], cx[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int p = pb + 2 * pp + e;
+    cb[e] = p / HW;
+    const int rem = p - cb[e] * HW;
+    cy[e] = rem / W;
+    cx[e] = rem - cy[e] * W;
+  }
+  // the chunk at p0 into registers; the next chunk's loads are issued before the current
+  // chunk's products so that their latency is hidden behind them
+  u16x8 v[2];
+  auto load_chunk = [&](int p0) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int p = p0 + 2 * pp + e;
@@ -213,17 +226,29 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* _
         if (half == 0) {
           if (co0 + cg < cout) v[e] = ld8(dz + (size_t)p * ldz + co0 + cg);
         } else if (n < nn) {
-          const int b = p / HW, rem = p - b * HW, yy = rem / W + ky, xx = rem - (rem / W) * W + kx;
+          const int yy = cy[e] + ky, xx = cx[e] + kx;
           if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-            v[e] = ld8(x + ((size_t)b * HW + (size_t)yy * W + xx) * ldx + ci);
+            v[e] = ld8(x + ((size_t)cb[e] * HW + (size_t)yy * W + xx) * ldx + ci);
+        }
+      }
+      cx[e] += WG_K;
+      while (cx[e] >= W) {
+        cx[e] -= W;
+        if (++cy[e] == H) {
+          cy[e] = 0;
+          ++cb[e];
         }
       }
     }
+  };
+  load_chunk(pb);
+  for (int p0 = pb; p0 < pe; p0 += WG_K) {
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       *reinterpret_cast<uint32_t*>(&dst[cg + j][2 * pp]) =
           (uint32_t)v[0][j] | ((uint32_t)v[1][j] << 16);
     __syncthreads();
+    if (p0 + WG_K < pe) load_chunk(p0 + WG_K);
     if (blockIdx.x == 0 && t < 64) {
 #pragma unroll 8
       for (int k = 0; k < WG_K; ++k) bsum += bf2f(sa[t][k]);
