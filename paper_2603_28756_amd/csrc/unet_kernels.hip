@@ -171,7 +171,8 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
 
 // ------------------------------------------------------------------ 3x3 conv, weights
 // part[s][co][n] = sum over the pixels of split s of dz[p, co] x[p + tap(n), ci(n)],
-// n = tap * cin + ci; partb[s][co] = sum over the same pixels of dz[p, co].  A block owns a
+// n = tap * cin + ci; partb[s][co] = sum over the same pixels of dz[p, co].  This kernel serves
+// widths that are not a multiple of 32 (the haloed kernel below takes the others).  A block owns a
 // 64 x 64 tile of (co, n) and one pixel split; 32-pixel steps are staged through LDS
 // transposed so that the K dimension (pixels) is contiguous for the matrix-core operands.
 constexpr int WG_K = 32, WG_PAD = 8;
@@ -279,9 +280,113 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* _
   if (blockIdx.x == 0 && t < 64 && co0 + t < cout) partb[(size_t)s * cout + co0 + t] = bsum;
 }
 
+// The same weight gradient over haloed row tiles (W a multiple of 32): a block owns 32 output
+// channels x 32 input channels x all 9 taps and one pixel split, walked in 32-pixel chunks
+// of one image row.  Per chunk it stages dz [32 co][32 pixels] and the input rows y-1, y, y+1
+// at columns x0-1 .. x0+32 of its 32 channels, so that each input value is fetched once per
+// row rather than once per tap; a tap's column shift is taken from an aligned 16-byte read
+// and the 32-bit word after it.  Wave w: co tile w & 1, ci tile w >> 1, all 9 taps.
+constexpr int WH_Q = 40;  // staged columns per row (34 used)
+
+TOMO_DEV u16x8 shift_cols(u16x8 lo, uint32_t next, int s) {
+  const uint4 d = __builtin_bit_cast(uint4, lo);
+  if (s == 0) return lo;
+  if (s == 2) return __builtin_bit_cast(u16x8, make_uint4(d.y, d.z, d.w, next));
+  return __builtin_bit_cast(u16x8, make_uint4((d.x >> 16) | (d.y << 16), (d.y >> 16) | (d.z << 16),
+                                              (d.z >> 16) | (d.w << 16), (d.w >> 16) | (next << 16)));
+}
+
+__global__ void __launch_bounds__(256)
+conv3x3_wgrad_halo_kernel(const uint16_t* __restrict__ dz, int ldz, const uint16_t* __restrict__ x,
+                          int ldx, float* __restrict__ part, float* __restrict__ partb, int cin,
+                          int cout, int H, int W, int npx, int px_per_split) {
+  __shared__ __align__(16) uint16_t sa[32][WG_K + WG_PAD];  // [co][pixel]
+  __shared__ __align__(16) uint16_t sx[32][3][WH_Q];        // [ci][row][column + 1]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int ci0 = blockIdx.x * 32, co0 = blockIdx.y * 32, s = blockIdx.z;
+  const int nn = 9 * cin;
+  const int pb = s * px_per_split, pe = min(npx, pb + px_per_split);
+  const int HW = H * W;
+  // chunk position (slice, row, first column), stepped by 32 pixels
+  int cb = pb / HW, cy = (pb - cb * HW) / W, cx = pb - cb * HW - cy * W;
+  // staging items: dz (threads 0..127: pixel t >> 2, channels 8 (t & 3) ..), input
+  // (items t and t + 256 below 408: channel group i & 3, row/column (i >> 2) / 34, % 34)
+  u16x8 vd, vx[2];
+  auto load_chunk = [&](int p0) {
+    if (t < 128) vd = ld8(dz + (size_t)(p0 + (t >> 2)) * ldz + co0 + 8 * (t & 3));
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = t + 256 * e;
+      vx[e] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (i < 408) {
+        const int rq = i >> 2, r = rq / 34, q = rq - 34 * r;
+        const int yy = cy + r - 1, xx = cx + q - 1;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          vx[e] = ld8(x + ((size_t)cb * HW + (size_t)yy * W + xx) * ldx + ci0 + 8 * (i & 3));
+      }
+    }
+    cx += WG_K;
+    if (cx == W) {
+      cx = 0;
+      if (++cy == H) {
+        cy = 0;
+        ++cb;
+      }
+    }
+  };
+  f32x4 acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  const int cot = wave & 1, cit = wave >> 1, kq = (lane >> 4) * 8;
+  load_chunk(pb);
+  for (int p0 = pb; p0 < pe; p0 += WG_K) {
+    if (t < 128) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sa[8 * (t & 3) + j][t >> 2] = vd[j];
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = t + 256 * e;
+      if (i < 408) {
+        const int rq = i >> 2, r = rq / 34, q = rq - 34 * r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sx[8 * (i & 3) + j][r][q] = vx[e][j];
+      }
+    }
+    __syncthreads();
+    if (p0 + WG_K < pe) load_chunk(p0 + WG_K);
+    if (blockIdx.x == 0 && t < 32) {
+#pragma unroll 8
+      for (int k = 0; k < WG_K; ++k) bsum += bf2f(sa[t][k]);
+    }
+    const u16x8 a = ld8(&sa[16 * cot + (lane & 15)][kq]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const uint16_t* row = &sx[16 * cit + (lane & 15)][r][kq];
+      const u16x8 lo = ld8(row);
+      const uint32_t next = *reinterpret_cast<const uint32_t*>(row + 8);
+#pragma unroll
+      for (int sh = 0; sh < 3; ++sh) acc[3 * r + sh] = mfma(a, shift_cols(lo, next, sh), acc[3 * r + sh]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int col = tap * cin + ci0 + 16 * cit + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = co0 + 16 * cot + 4 * (lane >> 4) + r;
+      part[((size_t)s * cout + co) * nn + col] = acc[tap][r];
+    }
+  }
+  if (blockIdx.x == 0 && t < 32) partb[(size_t)s * cout + co0 + t] = bsum;
+}
+
 // out[i] = sum_s part[s][i] in a fixed order: a block takes 64 outputs; thread group g (of
 // SS_G) sums the splits g, g + SS_G, ... in order, then the group sums are added in order.
-constexpr int SS_G = 4;
+// Few outputs (the bias, small layers) take 16 groups so that the launch still fills the chip.
+template <int SS_G>
 __global__ void __launch_bounds__(64 * SS_G)
 sum_splits_kernel(const float* __restrict__ part, int nsplit, size_t n, float* __restrict__ out) {
   __shared__ float sg[SS_G][64];
@@ -647,12 +752,23 @@ hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float
   return hipGetLastError();
 }
 
+static void launch_sum_splits(const float* part, int nsplit, size_t n, float* out, hipStream_t st) {
+  const unsigned nb = blocks_for(n, 64);
+  if (nb < 512)
+    hipLaunchKernelGGL(sum_splits_kernel<16>, dim3(nb), dim3(64 * 16), 0, st, part, nsplit, n, out);
+  else
+    hipLaunchKernelGGL(sum_splits_kernel<4>, dim3(nb), dim3(64 * 4), 0, st, part, nsplit, n, out);
+}
+
 WgradPlan nn_wgrad_plan(int cin, int cout, int npx) {
   WgradPlan pl;
   pl.ntn = (9 * cin + 63) / 64;
   pl.ntc = (cout + 63) / 64;
-  // about 2048 blocks, at least 256 pixels per split, a multiple of the 32-pixel step
-  int ns = 2048 / (pl.ntn * pl.ntc);
+  // about 960 blocks of the haloed kernel's (cin / 32) x (cout / 32) tiles (5 fit a CU at its
+  // register use: 960 to 1280 blocks were fastest, fewer splits also shorten the split sums),
+  // at least 256 pixels per split, a multiple of the 32-pixel step
+  const int tiles = (cin / 32) * (cout / 32);
+  int ns = 960 / (tiles > 0 ? tiles : 1);
   if (ns < 1) ns = 1;
   int per = (npx + ns - 1) / ns;
   if (per < 256) per = 256;
@@ -672,13 +788,15 @@ hipError_t nn_conv3x3_wgrad(const uint16_t* dz, int ldz, const uint16_t* x, int 
   if (pl.scratch_floats > scratch_floats) return hipErrorInvalidValue;
   float* part = scratch;
   float* partb = scratch + (size_t)pl.nsplit * cout * 9 * cin;
-  hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(pl.ntn, pl.ntc, pl.nsplit), dim3(256), 0, st, dz,
-                     ldz, x, ldx, part, partb, cin, cout, H, W, npx, pl.px_per_split);
+  if (W % WG_K == 0)
+    hipLaunchKernelGGL(conv3x3_wgrad_halo_kernel, dim3(cin / 32, cout / 32, pl.nsplit), dim3(256),
+                       0, st, dz, ldz, x, ldx, part, partb, cin, cout, H, W, npx, pl.px_per_split);
+  else
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(pl.ntn, pl.ntc, pl.nsplit), dim3(256), 0, st,
+                       dz, ldz, x, ldx, part, partb, cin, cout, H, W, npx, pl.px_per_split);
   const size_t nw = (size_t)cout * 9 * cin;
-  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(nw, 64)), dim3(64 * SS_G), 0, st, part,
-                     pl.nsplit, nw, dw);
-  hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(cout, 64)), dim3(64 * SS_G), 0, st, partb,
-                     pl.nsplit, (size_t)cout, db);
+  launch_sum_splits(part, pl.nsplit, nw, dw, st);
+  launch_sum_splits(partb, pl.nsplit, (size_t)cout, db, st);
   return hipGetLastError();
 }
 

@@ -72,7 +72,11 @@ def test_conv3x3_masked_input_gradient_form():
     _ulp_close(_np(out), ref)
 
 
-@pytest.mark.parametrize("B,H,W,cin,cout", [(2, 5, 70, 32, 64), (2, 64, 96, 64, 32), (1, 9, 17, 96, 96)])
+# widths that are multiples of 32 take the haloed row-tile kernel: one-row images (both halo
+# rows outside), 32-pixel rows (both halo columns outside, chunks crossing slices) and several
+# channel tiles on both sides; the other widths take the per-tap kernel
+@pytest.mark.parametrize("B,H,W,cin,cout", [(2, 5, 70, 32, 64), (2, 64, 96, 64, 32), (1, 9, 17, 96, 96),
+                                            (3, 1, 32, 96, 64), (2, 7, 64, 32, 96), (1, 40, 128, 64, 64)])
 def test_conv3x3_weight_gradient(B, H, W, cin, cout):
     from paper_2603_28756_amd import tomo
     rng = np.random.default_rng(B * H + W)
