@@ -441,32 +441,43 @@ conv_in_kernel(const float* __restrict__ fbp, float inv_s, const float* __restri
   }
 }
 
-// part[blk][co*10 + k] (k < 9: weight of tap k, k = 9: bias) over the pixels of block blk
+// part[blk][co*10 + k] (k < 9: weight of tap k, k = 9: bias) over the pixels of block blk.
+// Thread t takes channels 8 g .. 8 g + 7 (g = t % tpp, tpp = cout / 8, a power of two) of
+// pixel lane t / tpp: one 16-byte read of dz and the 9 neighbours per pixel, whose image,
+// row and column are stepped along (no division per pixel).  The lanes of a wave that hold
+// the same channels are combined by butterfly shuffles, then the 4 waves in order.
 __global__ void __launch_bounds__(256)
 conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ fbp, float inv_s,
                      float* __restrict__ part, int cout, int H, int W, int npx, int px_per_blk) {
-  extern __shared__ float sacc[];  // [256 threads][10]
-  const int t = threadIdx.x;
+  extern __shared__ float sred[];  // [4 waves][tpp][80]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int tpp = cout >> 3, g = t & (tpp - 1), pl = t / tpp, lanes = 256 / tpp;
   const int pb = blockIdx.x * px_per_blk, pe = min(npx, pb + px_per_blk);
   const int HW = H * W;
-  // thread t: channel co = t % cout, pixel lane t / cout; the pixel's image, row and column
-  // are stepped along (no division per pixel)
-  const int lanes = 256 / cout;
-  const int co = t % cout, pl = t / cout;
-  float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (pl < lanes && pb + pl < pe) {
+  float acc[8][10];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[j][k] = 0.f;
+  if (pb + pl < pe) {
     int p = pb + pl;
     int b = p / HW, r = (p - b * HW) / W, c = p - b * HW - r * W;
     for (; p < pe; p += lanes) {
-      const float d = bf2f(dz[(size_t)p * cout + co]);
+      const u16x8 dv = ld8(dz + (size_t)p * cout + 8 * g);
       const float* img = fbp + (size_t)b * HW;
+      float nb9[9];
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int yy = r + tap / 3 - 1, xx = c + tap % 3 - 1;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          acc[tap] = fmaf(d, img[yy * W + xx] * inv_s, acc[tap]);
+        nb9[tap] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? img[yy * W + xx] * inv_s : 0.f;
       }
-      acc[9] += d;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float d = bf2f(dv[j]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) acc[j][tap] = fmaf(d, nb9[tap], acc[j][tap]);
+        acc[j][9] += d;
+      }
       c += lanes;
       while (c >= W) {
         c -= W;
@@ -478,12 +489,22 @@ conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ 
     }
   }
 #pragma unroll
-  for (int k = 0; k < 10; ++k) sacc[t * 10 + k] = acc[k];
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+      for (int off = tpp; off < 64; off <<= 1) acc[j][k] += __shfl_xor(acc[j][k], off);
+  if (lane < tpp) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sred[(wave * tpp + lane) * 80 + j * 10 + k] = acc[j][k];
+  }
   __syncthreads();
   for (int o = t; o < cout * 10; o += 256) {
-    const int c = o / 10, k = o - c * 10;
+    const int co = o / 10, k = o - co * 10, cg = co >> 3, j = co & 7;
     float a = 0.f;
-    for (int l = 0; l < lanes; ++l) a += sacc[(l * cout + c) * 10 + k];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) a += sred[(w * tpp + cg) * 80 + j * 10 + k];
     part[(size_t)blockIdx.x * cout * 10 + o] = a;
   }
 }
@@ -809,17 +830,18 @@ hipError_t nn_conv_in(const float* fbp, float inv_s, const float* w, const float
   return hipGetLastError();
 }
 
-constexpr int CIN_WG_PX = 1024;  // pixels per block of the first-layer weight gradient
+constexpr int CIN_WG_PX = 2048;  // pixels per block of the first-layer weight gradient
 int nn_conv_in_wgrad_blocks(int npx) { return (npx + CIN_WG_PX - 1) / CIN_WG_PX; }
 
 hipError_t nn_conv_in_wgrad(const uint16_t* dz, const float* fbp, float inv_s, float* dw,
                             float* db, int cout, int B, int H, int W, float* scratch,
                             size_t scratch_floats, hipStream_t st) {
-  if (cout > 256 || 256 % cout) return hipErrorInvalidValue;
+  // 8 channels per thread, cout / 8 threads per pixel (a power of two, at most 32)
+  if (cout < 8 || cout > 256 || cout % 8 || ((cout / 8) & (cout / 8 - 1))) return hipErrorInvalidValue;
   const int npx = B * H * W, nb = nn_conv_in_wgrad_blocks(npx);
   if ((size_t)nb * cout * 10 > scratch_floats) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(conv_in_wgrad_kernel, dim3(nb), dim3(256), 256 * 10 * sizeof(float), st, dz,
-                     fbp, inv_s, scratch, cout, H, W, npx, CIN_WG_PX);
+  hipLaunchKernelGGL(conv_in_wgrad_kernel, dim3(nb), dim3(256), 4 * (cout / 8) * 80 * sizeof(float),
+                     st, dz, fbp, inv_s, scratch, cout, H, W, npx, CIN_WG_PX);
   hipLaunchKernelGGL(conv_in_reduce_kernel, dim3(cout * 10), dim3(256), 0, st, scratch, nb, cout,
                      dw, db);
   return hipGetLastError();
