@@ -629,14 +629,15 @@ __global__ void head_kernel(const uint16_t* __restrict__ d, const float* __restr
 }
 
 // dr = 2 (r - (target - fbp)/s) / npx; dD[p, c] = hw[c] dr (D > 0); per block: sum of the
-// squared residual (float64), sum dr, sum dr D[:, c] -> part[blk][C + 2]
+// squared residual (float64), sum dr, sum dr D[:, c] -> part[blk][C + 2].  Each sum is taken
+// over a wave by butterfly shuffles, then over the 4 waves in order after one barrier.
 __global__ void __launch_bounds__(256)
 head_back_kernel(const float* __restrict__ r, const float* __restrict__ fbp,
                  const float* __restrict__ target, float inv_s, const uint16_t* __restrict__ d,
                  const float* __restrict__ hw, uint16_t* __restrict__ dd, double* __restrict__ part,
                  int C, int npx) {
-  __shared__ double sh[256];
-  const int t = threadIdx.x;
+  extern __shared__ double sh[];  // [4 waves][C + 2]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int p = blockIdx.x * 256 + t;
   double sq = 0.0;
   float dr = 0.f;
@@ -661,15 +662,13 @@ head_back_kernel(const float* __restrict__ r, const float* __restrict__ fbp,
       else if (k == -1) v = dr;
       else v = (double)dr * bf2f(d[(size_t)p * C + k]);
     }
-    sh[t] = v;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (t < o) sh[t] += sh[t + o];
-      __syncthreads();
-    }
-    if (t == 0) part[(size_t)blockIdx.x * (C + 2) + (k + 2)] = sh[0];
-    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) sh[wave * (C + 2) + k + 2] = v;
   }
+  __syncthreads();
+  for (int k = t; k < C + 2; k += 256)
+    part[(size_t)blockIdx.x * (C + 2) + k] =
+        (sh[k] + sh[(C + 2) + k]) + (sh[2 * (C + 2) + k] + sh[3 * (C + 2) + k]);
 }
 
 // fixed-order sums of head_back partials (block k sums column k): loss (mean), head weight
@@ -893,8 +892,8 @@ hipError_t nn_head_back(const float* r, const float* fbp, const float* target, f
                         float* ghb, double* loss, int C, int npx, hipStream_t st) {
   if (C + 2 > 1024) return hipErrorInvalidValue;
   const int nb = nn_head_back_blocks(npx);
-  hipLaunchKernelGGL(head_back_kernel, dim3(nb), dim3(256), 0, st, r, fbp, target, inv_s, d, hw, dd,
-                     part, C, npx);
+  hipLaunchKernelGGL(head_back_kernel, dim3(nb), dim3(256), 4 * (C + 2) * sizeof(double), st, r,
+                     fbp, target, inv_s, d, hw, dd, part, C, npx);
   hipLaunchKernelGGL(head_reduce_kernel, dim3(C + 2), dim3(256), 0, st, part, nb, C, npx, ghw, ghb,
                      loss);
   return hipGetLastError();
