@@ -646,24 +646,38 @@ head_back_kernel(const float* __restrict__ r, const float* __restrict__ fbp,
     sq = (double)diff * diff;
     dr = 2.f * diff / (float)npx;
   }
-  // gradient of the last activation
-  for (int c0 = 0; c0 < C && p < npx; c0 += 8) {
-    const u16x8 v = ld8(d + (size_t)p * C + c0);
-    u16x8 o;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = f2bf(bf2f(v[k]) > 0.f ? hw[c0 + k] * dr : 0.f);
-    st8(dd + (size_t)p * C + c0, o);
-  }
-  // block sums: [0] squared residual, [1] dr, [2 + c] dr D[:, c]
-  for (int k = -2; k < C; ++k) {
-    double v = 0.0;
+  // gradient of the last activation, and the sums dr D[:, c] of the 8 channels of each read
+  // (all lanes take part in the shuffles; lanes past the end add zeros)
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
     if (p < npx) {
-      if (k == -2) v = sq;
-      else if (k == -1) v = dr;
-      else v = (double)dr * bf2f(d[(size_t)p * C + k]);
+      v = ld8(d + (size_t)p * C + c0);
+      u16x8 o;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) o[k] = f2bf(bf2f(v[k]) > 0.f ? hw[c0 + k] * dr : 0.f);
+      st8(dd + (size_t)p * C + c0, o);
     }
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) sh[wave * (C + 2) + k + 2] = v;
+    double a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = (double)dr * bf2f(v[k]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] += __shfl_xor(a[k], off);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sh[wave * (C + 2) + 2 + c0 + k] = a[k];
+    }
+  }
+  double a0 = sq, a1 = dr;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off);
+    a1 += __shfl_xor(a1, off);
+  }
+  if (lane == 0) {
+    sh[wave * (C + 2)] = a0;
+    sh[wave * (C + 2) + 1] = a1;
   }
   __syncthreads();
   for (int k = t; k < C + 2; k += 256)
@@ -890,7 +904,7 @@ int nn_head_back_blocks(int npx) { return (npx + 255) / 256; }
 hipError_t nn_head_back(const float* r, const float* fbp, const float* target, float inv_s,
                         const uint16_t* d, const float* hw, uint16_t* dd, double* part, float* ghw,
                         float* ghb, double* loss, int C, int npx, hipStream_t st) {
-  if (C + 2 > 1024) return hipErrorInvalidValue;
+  if (C % 8 || C + 2 > 1024) return hipErrorInvalidValue;
   const int nb = nn_head_back_blocks(npx);
   hipLaunchKernelGGL(head_back_kernel, dim3(nb), dim3(256), 4 * (C + 2) * sizeof(double), st, r,
                      fbp, target, inv_s, d, hw, dd, part, C, npx);
