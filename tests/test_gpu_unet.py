@@ -60,10 +60,11 @@ def test_conv3x3_forward_relu(cin, cout, W, off):
     assert np.all(got[..., cout:] == 0.0)  # untouched channels beyond cout
 
 
-def test_conv3x3_masked_input_gradient_form():
+@pytest.mark.parametrize("co", [32, 96])
+def test_conv3x3_masked_input_gradient_form(co):
     from paper_2603_28756_amd import tomo
     rng = np.random.default_rng(9)
-    B, H, W, ci, co = 3, 7, 40, 64, 32
+    B, H, W, ci = 3, 7, 40, 64
     dz = _bf(rng.standard_normal((B, H, W, ci)))
     w = _bf(rng.standard_normal((co, 3, 3, ci)) / 20)
     mask = _bf(rng.standard_normal((B, H, W, co)))
