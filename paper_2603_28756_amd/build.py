@@ -42,12 +42,6 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
     os.replace(tmp, LIB)
-    # standalone VALU issue-rate probe (the transcendental weight of the prior's ALU roofline)
-    probe = os.path.join(LIBDIR, "valu_probe")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", os.path.join(CSRC, "valu_probe.hip"), "-o", probe]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{res.stderr}")
     if verbose:
         print(f"built {LIB}")
     return LIB

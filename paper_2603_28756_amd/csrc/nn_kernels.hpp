@@ -27,6 +27,7 @@ struct WgradPlan {
   size_t scratch_floats = 0;
 };
 WgradPlan nn_wgrad_plan(int cin, int cout, int npx);
+size_t nn_wgrad_scratch_bound(int cin, int cout, int max_npx);
 // dw [cout][3][3][cin] = sum_p dz[p, co] x[p + tap, ci]; db [cout] = sum_p dz[p, co].
 hipError_t nn_conv3x3_wgrad(const uint16_t* dz, int ldz, const uint16_t* x, int ldx, float* dw,
                             float* db, int cin, int cout, int B, int H, int W, float* scratch,

@@ -23,6 +23,7 @@ thread_local std::string g_last_error;
 constexpr size_t kAlign = 256;
 constexpr int kMaxLevels = 6;
 constexpr int kPowerIters = 30;
+constexpr size_t kMaxGraphs = 24;  // cached three-iteration graph executables per plan
 constexpr int kMinFft = 32, kMaxHot = 4096, kMaxGrid = 8192;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -536,6 +537,14 @@ tomo_status get_graph(tomo_plan p, int level, int ik, int ikm1, int inext, const
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(p, TOMO_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  // The key holds the caller's history pointers, so a caller passing fresh history buffers
+  // would grow the cache without bound: keep the most recent kMaxGraphs executables (the
+  // evicted one may still be queued on the internal stream, which is drained first).
+  if (p->graphs.size() >= kMaxGraphs) {
+    HIPCHK(p, hipStreamSynchronize(p->gstream));
+    (void)hipGraphExecDestroy(p->graphs.front().exec);
+    p->graphs.erase(p->graphs.begin());
+  }
   p->graphs.push_back({{level, ik * 9 + ikm1 * 3 + inext, p->nz, hist, rhist, hist != nullptr}, exec});
   *out = exec;
   return TOMO_OK;

@@ -158,9 +158,10 @@ void layout(tomo_unet u) {
     int l;
     if (i < (size_t)2 * u->L) l = (int)i / 2;
     else l = u->L - 2 - (int)(i - 2 * u->L) / 2;
+    // every batch 1..maxB must fit: bound over all pixel counts up to the largest
     const size_t npx = (size_t)u->maxB * (u->H >> l) * (u->W >> l);
-    const WgradPlan pl = nn_wgrad_plan(u->convs[i].cin, u->convs[i].cout, (int)npx);
-    if (pl.scratch_floats > scratch) scratch = pl.scratch_floats;
+    const size_t need = nn_wgrad_scratch_bound(u->convs[i].cin, u->convs[i].cout, (int)npx);
+    if (need > scratch) scratch = need;
   }
   const int npx0 = u->maxB * u->H * u->W;
   const size_t in_scr = (size_t)nn_conv_in_wgrad_blocks(npx0) * u->C0 * 10;

@@ -442,16 +442,19 @@ conv_in_kernel(const float* __restrict__ fbp, float inv_s, const float* __restri
 }
 
 // part[blk][co*10 + k] (k < 9: weight of tap k, k = 9: bias) over the pixels of block blk.
-// Thread t takes channels 8 g .. 8 g + 7 (g = t % tpp, tpp = cout / 8, a power of two) of
-// pixel lane t / tpp: one 16-byte read of dz and the 9 neighbours per pixel, whose image,
-// row and column are stepped along (no division per pixel).  The lanes of a wave that hold
-// the same channels are combined by butterfly shuffles, then the 4 waves in order.
+// Thread t takes channels 8 g .. 8 g + 7 (g = t % tpp2, tpp2 = cout / 8 rounded up to a power
+// of two; threads with 8 g >= cout hold zeros) of pixel lane t / tpp2: one 16-byte read of dz
+// and the 9 neighbours per pixel, whose image, row and column are stepped along (no division
+// per pixel).  The lanes of a wave that hold the same channels are combined by butterfly
+// shuffles, then the 4 waves in order.
 __global__ void __launch_bounds__(256)
 conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ fbp, float inv_s,
-                     float* __restrict__ part, int cout, int H, int W, int npx, int px_per_blk) {
-  extern __shared__ float sred[];  // [4 waves][tpp][80]
+                     float* __restrict__ part, int cout, int tpp2, int H, int W, int npx,
+                     int px_per_blk) {
+  extern __shared__ float sred[];  // [4 waves][tpp2][80]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int tpp = cout >> 3, g = t & (tpp - 1), pl = t / tpp, lanes = 256 / tpp;
+  const int g = t & (tpp2 - 1), pl = t / tpp2, lanes = 256 / tpp2;
+  const bool has_ch = 8 * g < cout;
   const int pb = blockIdx.x * px_per_blk, pe = min(npx, pb + px_per_blk);
   const int HW = H * W;
   float acc[8][10];
@@ -459,7 +462,7 @@ conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ 
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[j][k] = 0.f;
-  if (pb + pl < pe) {
+  if (has_ch && pb + pl < pe) {
     int p = pb + pl;
     int b = p / HW, r = (p - b * HW) / W, c = p - b * HW - r * W;
     for (; p < pe; p += lanes) {
@@ -492,19 +495,19 @@ conv_in_wgrad_kernel(const uint16_t* __restrict__ dz, const float* __restrict__ 
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int k = 0; k < 10; ++k)
-      for (int off = tpp; off < 64; off <<= 1) acc[j][k] += __shfl_xor(acc[j][k], off);
-  if (lane < tpp) {
+      for (int off = tpp2; off < 64; off <<= 1) acc[j][k] += __shfl_xor(acc[j][k], off);
+  if (lane < tpp2) {
 #pragma unroll
     for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int k = 0; k < 10; ++k) sred[(wave * tpp + lane) * 80 + j * 10 + k] = acc[j][k];
+      for (int k = 0; k < 10; ++k) sred[(wave * tpp2 + lane) * 80 + j * 10 + k] = acc[j][k];
   }
   __syncthreads();
   for (int o = t; o < cout * 10; o += 256) {
     const int co = o / 10, k = o - co * 10, cg = co >> 3, j = co & 7;
     float a = 0.f;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) a += sred[(w * tpp + cg) * 80 + j * 10 + k];
+    for (int w = 0; w < 4; ++w) a += sred[(w * tpp2 + cg) * 80 + j * 10 + k];
     part[(size_t)blockIdx.x * cout * 10 + o] = a;
   }
 }
@@ -813,6 +816,18 @@ WgradPlan nn_wgrad_plan(int cin, int cout, int npx) {
   return pl;
 }
 
+// per >= ceil(npx / ns) gives nsplit <= ns, and per >= 256 gives nsplit <= ceil(npx / 256),
+// so this bounds the scratch of every pixel count up to max_npx (nsplit is not monotone in
+// npx because per is rounded to the 32-pixel step).
+size_t nn_wgrad_scratch_bound(int cin, int cout, int max_npx) {
+  const int tiles = (cin / 32) * (cout / 32);
+  int ns = 960 / (tiles > 0 ? tiles : 1);
+  if (ns < 1) ns = 1;
+  const int by_px = (max_npx + 255) / 256;
+  const int nsplit = by_px < ns ? by_px : ns;
+  return (size_t)nsplit * cout * (9 * cin + 1);
+}
+
 hipError_t nn_conv3x3_wgrad(const uint16_t* dz, int ldz, const uint16_t* x, int ldx, float* dw,
                             float* db, int cin, int cout, int B, int H, int W, float* scratch,
                             size_t scratch_floats, hipStream_t st) {
@@ -849,12 +864,14 @@ int nn_conv_in_wgrad_blocks(int npx) { return (npx + CIN_WG_PX - 1) / CIN_WG_PX;
 hipError_t nn_conv_in_wgrad(const uint16_t* dz, const float* fbp, float inv_s, float* dw,
                             float* db, int cout, int B, int H, int W, float* scratch,
                             size_t scratch_floats, hipStream_t st) {
-  // 8 channels per thread, cout / 8 threads per pixel (a power of two, at most 32)
-  if (cout < 8 || cout > 256 || cout % 8 || ((cout / 8) & (cout / 8 - 1))) return hipErrorInvalidValue;
+  // 8 channels per thread, cout / 8 threads per pixel rounded up to a power of two (<= 32)
+  if (cout < 8 || cout > 256 || cout % 8) return hipErrorInvalidValue;
+  int tpp2 = 1;
+  while (tpp2 < cout / 8) tpp2 <<= 1;
   const int npx = B * H * W, nb = nn_conv_in_wgrad_blocks(npx);
   if ((size_t)nb * cout * 10 > scratch_floats) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(conv_in_wgrad_kernel, dim3(nb), dim3(256), 4 * (cout / 8) * 80 * sizeof(float),
-                     st, dz, fbp, inv_s, scratch, cout, H, W, npx, CIN_WG_PX);
+  hipLaunchKernelGGL(conv_in_wgrad_kernel, dim3(nb), dim3(256), 4 * tpp2 * 80 * sizeof(float),
+                     st, dz, fbp, inv_s, scratch, cout, tpp2, H, W, npx, CIN_WG_PX);
   hipLaunchKernelGGL(conv_in_reduce_kernel, dim3(cout * 10), dim3(256), 0, st, scratch, nb, cout,
                      dw, db);
   return hipGetLastError();

@@ -89,8 +89,8 @@ def test_conv3x3_weight_gradient(B, H, W, cin, cout):
     assert np.linalg.norm(_np(db) - rb) / np.linalg.norm(rb) < 1e-5
 
 
-def _net_case(levels=3, H=48, W=40, B=2, seed=0):
-    arch = U.Arch(levels=levels, base=32)
+def _net_case(levels=3, H=48, W=40, B=2, seed=0, base=32):
+    arch = U.Arch(levels=levels, base=base)
     rng = np.random.default_rng(seed)
     theta = U.init_params(arch, seed) + 0.01 * rng.standard_normal(arch.n_params())
     theta = theta.astype(np.float32).astype(np.float64)
@@ -117,12 +117,16 @@ def test_network_forward(levels, H, W):
     assert np.linalg.norm(r_gpu - r_exact) / np.linalg.norm(r_exact) < 5e-2
 
 
-@pytest.mark.parametrize("levels,H,W", [(3, 48, 40), (2, 32, 96)])
-def test_network_loss_and_gradient(levels, H, W):
+# (levels, H, W, base channels, max_batch, batch).  128 x 128 at batch 5 of 8 needs more
+# weight-gradient split scratch than the full batch (the split count is not monotone in the
+# pixel count); 96 base channels give 12 first-layer channel groups (not a power of two).
+@pytest.mark.parametrize("levels,H,W,base,max_batch,B", [
+    (3, 48, 40, 32, 2, 2), (2, 32, 96, 32, 2, 2), (2, 128, 128, 32, 8, 5), (2, 32, 64, 96, 2, 2)])
+def test_network_loss_and_gradient(levels, H, W, base, max_batch, B):
     from paper_2603_28756_amd import tomo
-    arch, theta, fbp, target = _net_case(levels, H, W, seed=levels)
+    arch, theta, fbp, target = _net_case(levels, H, W, B=B, seed=levels, base=base)
     s = 0.9
-    net = tomo.UNet(H, W, levels=levels, base=32, max_batch=2)
+    net = tomo.UNet(H, W, levels=levels, base=base, max_batch=max_batch)
     net.set_params(torch.as_tensor(theta, dtype=torch.float32))
     loss, g = net.loss_grad(torch.as_tensor(fbp, dtype=torch.float32, device=dev()).contiguous(),
                             torch.as_tensor(target, dtype=torch.float32, device=dev()).contiguous(), s)
