@@ -97,6 +97,21 @@ tomo_status tomo_nn_conv3x3_wgrad(const uint16_t* dz, int32_t ldz, const uint16_
                                   int32_t height, int32_t width, float* scratch,
                                   size_t scratch_floats, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): tomo_nn_conv3x3_wgrad with the split partial sums in
+ * a static device array of TOMO_NN_WGRAD_NOALLOC_MAX_FLOATS floats (36 MiB) that the library
+ * holds on every GPU it runs on until the process ends, instead of caller scratch.  Same
+ * arguments, kernels and bit-identical results otherwise.  The caller still passes dz, x, dw
+ * and db; hip_stream must belong to the current device.  The first call on a device looks up
+ * the array's address on that device.  Calls that overlap on one GPU (other streams, other threads) share the
+ * array and race; serialise them.  Errors: INVALID_ARG, WORKSPACE_TOO_SMALL (the shape needs more
+ * split sums than the array holds; tomo_nn_wgrad_scratch gives the count), HIP. */
+#define TOMO_NN_WGRAD_NOALLOC_MAX_FLOATS 9437184
+tomo_status tomo_nn_conv3x3_wgrad_noalloc(const uint16_t* dz, int32_t ldz, const uint16_t* x,
+                                          int32_t ldx, float* dw, float* db, int32_t cin,
+                                          int32_t cout, int32_t batch, int32_t height,
+                                          int32_t width, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

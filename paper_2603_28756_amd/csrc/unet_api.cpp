@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -472,6 +473,60 @@ tomo_status tomo_nn_conv3x3_wgrad(const uint16_t* dz, int32_t ldz, const uint16_
     return nfail(nullptr, TOMO_ERR_WORKSPACE_TOO_SMALL, "scratch too small");
   const hipError_t e = nn_conv3x3_wgrad(dz, ldz, x, ldx, dw, db, cin, cout, batch, height, width,
                                         scratch, scratch_floats, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return nfail(nullptr, TOMO_ERR_HIP, "conv3x3 wgrad: %s", hipGetErrorString(e));
+  return TOMO_OK;
+}
+
+// ---- weight gradient without caller scratch ------------------------------------------------
+// The split partial sums of tomo_nn_conv3x3_wgrad_noalloc live in this file-scope device array
+// (one copy per GPU, held until the process ends).  Host code never passes its name to a
+// kernel: the device address is looked up once per device with hipGetSymbolAddress and kept.
+// Every split partial is written before it is summed, so nothing needs clearing between calls.
+static __device__ __align__(256) float wgrad_scratch[TOMO_NN_WGRAD_NOALLOC_MAX_FLOATS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_on_current_device(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(wgrad_scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+tomo_status tomo_nn_conv3x3_wgrad_noalloc(const uint16_t* dz, int32_t ldz, const uint16_t* x,
+                                          int32_t ldx, float* dw, float* db, int32_t cin,
+                                          int32_t cout, int32_t batch, int32_t height,
+                                          int32_t width, void* hip_stream) {
+  if (!dz || !x || !dw || !db) return nfail(nullptr, TOMO_ERR_INVALID_ARG, "NULL array");
+  if (cin % 32 || cout % 32 || cin < 32 || cout < 32 || ldz < cout || ldx < cin || ldz % 8 || ldx % 8 ||
+      batch < 1 || height < 1 || width < 1)
+    return nfail(nullptr, TOMO_ERR_INVALID_ARG, "unsupported shape");
+  if ((reinterpret_cast<uintptr_t>(dz) | reinterpret_cast<uintptr_t>(x)) % 16)
+    return nfail(nullptr, TOMO_ERR_INVALID_ARG, "dz and x must be 16-byte aligned");
+  const size_t need = nn_wgrad_plan(cin, cout, batch * height * width).scratch_floats;
+  if (need > (size_t)TOMO_NN_WGRAD_NOALLOC_MAX_FLOATS)
+    return nfail(nullptr, TOMO_ERR_WORKSPACE_TOO_SMALL,
+                 "split sums need %zu floats, more than the %d of the static scratch", need,
+                 TOMO_NN_WGRAD_NOALLOC_MAX_FLOATS);
+  float* scr = nullptr;
+  hipError_t e = scratch_on_current_device(&scr);
+  if (e != hipSuccess)
+    return nfail(nullptr, TOMO_ERR_HIP, "static scratch address: %s", hipGetErrorString(e));
+  e = nn_conv3x3_wgrad(dz, ldz, x, ldx, dw, db, cin, cout, batch, height, width, scr,
+                       (size_t)TOMO_NN_WGRAD_NOALLOC_MAX_FLOATS, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return nfail(nullptr, TOMO_ERR_HIP, "conv3x3 wgrad: %s", hipGetErrorString(e));
   return TOMO_OK;
 }

@@ -18,6 +18,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libtomo.so")
 
 TOMO_OK = 0
+(TOMO_ERR_INVALID_ARG, TOMO_ERR_NO_DEVICE, TOMO_ERR_UNSUPPORTED_ARCH, TOMO_ERR_NO_WORKSPACE,
+ TOMO_ERR_WORKSPACE_TOO_SMALL, TOMO_ERR_NOT_READY, TOMO_ERR_HIP, TOMO_ERR_NONFINITE,
+ TOMO_ERR_INTERNAL) = range(1, 10)
 STATUS_NAMES = {
     0: "OK", 1: "INVALID_ARG", 2: "NO_DEVICE", 3: "UNSUPPORTED_ARCH", 4: "NO_WORKSPACE",
     5: "WORKSPACE_TOO_SMALL", 6: "NOT_READY", 7: "HIP", 8: "NONFINITE", 9: "INTERNAL",
@@ -131,6 +134,10 @@ EXPORTS = {
     "tomo_nn_conv3x3_wgrad": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "tomo_nn_conv3x3_wgrad_noalloc": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
+                                      ctypes.c_int),
     "tomo_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tomo_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
 }
@@ -494,4 +501,24 @@ def nn_conv3x3_wgrad(dz: torch.Tensor, x: torch.Tensor, cin: int, cout: int, dz_
                                           ctypes.c_void_p(dw.data_ptr()), ctypes.c_void_p(db.data_ptr()), cin, cout,
                                           B, H, W, ctypes.c_void_p(scratch.data_ptr()), n.value,
                                           ctypes.c_void_p(st)), None)
+    return dw, db
+
+
+def nn_conv3x3_wgrad_noalloc(dz: torch.Tensor, x: torch.Tensor, cin: int, cout: int,
+                             dz_ld: Optional[int] = None, x_ld: Optional[int] = None, stream=None,
+                             dw: Optional[torch.Tensor] = None, db: Optional[torch.Tensor] = None):
+    """Like nn_conv3x3_wgrad, with the split sums in the library's static device scratch."""
+    lib = load_library()
+    B, H, W = x.shape[0], x.shape[1], x.shape[2]
+    ldz = dz_ld if dz_ld is not None else dz.shape[3]
+    ldx = x_ld if x_ld is not None else x.shape[3]
+    if dw is None:
+        dw = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device=x.device)
+    if db is None:
+        db = torch.empty(cout, dtype=torch.float32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device).cuda_stream
+    _unet_check(lib.tomo_nn_conv3x3_wgrad_noalloc(ctypes.c_void_p(_bf16_ptr(dz)), ldz,
+                                                  ctypes.c_void_p(_bf16_ptr(x)), ldx,
+                                                  ctypes.c_void_p(dw.data_ptr()), ctypes.c_void_p(db.data_ptr()),
+                                                  cin, cout, B, H, W, ctypes.c_void_p(st)), None)
     return dw, db
