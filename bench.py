@@ -250,7 +250,8 @@ def run_learned(args) -> int:
     print(f"training: {train_s_time:.1f} s, loss {np.mean(losses[:20]):.3e} -> {np.mean(losses[-20:]):.3e}",
           file=sys.stderr, flush=True)
     del fbp, tgt
-    res = learned.compare_starts(pr, test_s, net, scale, dev, long_iters=2000, net_batch=args.infer_batch)
+    learned.record_domain(net, pr)
+    res = learned.compare_starts(pr, test_s, net, scale, dev, long_iters=2000)
     # 3x3 convolutions dominate: 2 x 9 cin cout flops per pixel at each level's resolution
     shapes = learned.layer_shapes(levels, 32)
     lvl = [l for l in range(levels) for _ in (0, 1)] + [l for l in range(levels - 2, -1, -1) for _ in (0, 1)]

@@ -65,8 +65,19 @@ typedef struct tomo_plan_s* tomo_plan;
 enum {
   TOMO_INIT_FBP = 0,   /* ramp-filtered back-projection, Sec. 2.2                    */
   TOMO_INIT_ZERO = 1,  /* constant zero image                                       */
-  TOMO_INIT_USER = 2   /* caller's image, read from x before iterating              */
+  TOMO_INIT_USER = 2,  /* caller's image, read from x before iterating              */
+  TOMO_INIT_LEARNED = 3 /* network start from the FBP image (tomo_nn.h), FBP fallback  */
 };
+
+/* Outcome of a learned start (tomo_recon_stats_t.learned_state). */
+enum {
+  TOMO_LEARNED_NOT_REQUESTED = 0, /* init was not TOMO_INIT_LEARNED                         */
+  TOMO_LEARNED_TESTED = 1,        /* the objective test chose per slice (learned_slices)    */
+  TOMO_LEARNED_OUT_OF_DOMAIN = 2  /* the plan's coarsest level is outside the network's
+                                     training domain: the FBP start was used              */
+};
+
+struct tomo_unet_s;  /* the network of tomo_nn.h */
 
 /* Geometry, discretisation and prior of one reconstruction problem.  All
  * fields are host values; the angle array is copied by tomo_plan_create(). */
@@ -124,6 +135,12 @@ typedef struct {
                              the objective at the point where iteration k evaluates its
                              gradient (computing it costs extra prior work)                */
   int32_t* restart_dev;   /* nullable device int32[sum(iters)]: 1 where restart fired     */
+  /* TOMO_INIT_LEARNED only (ignored otherwise): */
+  struct tomo_unet_s* unet; /* network with parameters set (tomo_nn.h); its images must be
+                             N_0 x N_0 (the coarsest level)                                */
+  float unet_scale;       /* input scale of the network, > 0 (tomo_unet_forward)           */
+  int32_t* init_choice_dev; /* nullable device int32[n_slices]: 1 where the network's start
+                             was kept, 0 where the FBP start was                           */
 } tomo_recon_opts_t;
 
 /* Host-side summary filled by tomo_reconstruct() when non-NULL. */
@@ -132,6 +149,8 @@ typedef struct {
   double lambda_pow[6];   /* power-iteration estimate of the largest eigenvalue of R*R     */
   int32_t n_restarts;     /* restarts over all levels                                       */
   int32_t nonfinite_iter; /* first global iteration with a non-finite value, or -1          */
+  int32_t learned_state;  /* TOMO_LEARNED_*                                                 */
+  int32_t learned_slices; /* slices started from the network's image                        */
 } tomo_recon_stats_t;
 
 /* Validate `geom`, bind the plan to the current HIP device and to `hip_stream`
@@ -184,16 +203,29 @@ tomo_status tomo_gradient(tomo_plan plan, const float* x, const float* b, float*
 
 /* Full reconstruction of `sino` into `x` through the grid hierarchy: per level
  * (coarse to fine) the projections are subsampled (every s-th bin, divided by
- * s), b = R* g is formed, the start is FBP / zero / the caller's image on the
- * coarsest level and the Lanczos-3 prolongation of the previous level above
- * it, and `iters[l]` accelerated gradient iterations with optional restart are
- * run (Sec. 2, Sec. 2.2, Sec. 2.3).  Computes the PSF first if it is not ready.
+ * s), b = R* g is formed, the start is FBP / zero / the caller's image / the
+ * learned start on the coarsest level and the Lanczos-3 prolongation of the
+ * previous level above it, and `iters[l]` accelerated gradient iterations with
+ * optional restart are run (Sec. 2, Sec. 2.2, Sec. 2.3).  Computes the PSF
+ * first if it is not ready.
+ * Learned start (extension of the FBP start of Sec. 2.2): the network maps the
+ * FBP image to a start; if the coarsest level lies outside the network's
+ * training domain (tomo_unet_set_domain; a network without one is outside) the
+ * FBP start is used.  Otherwise the float64 objective
+ *   1/2 <x, R*R x> - <x, R* g> + beta Phi(x)
+ * of both candidate starts is evaluated on the device and the FBP start is
+ * kept where the network's is larger (or not finite): per slice with the
+ * 8-neighbour prior (slices are then independent problems), for the whole
+ * volume with the 26-neighbour prior.  The network runs on its own stream,
+ * ordered after and before the plan's work by events.
  * sino: device [n_slices][n_angles][n_det].
  * x: device [n_slices][N][N] output; with TOMO_INIT_USER it is first read as
  *    the coarsest-level start image [n_slices][N_0][N_0] (contiguous).
  * stats_host: nullable; when given the call synchronises the plan's stream
  *    and fills it.  Without it, a non-finite iteration is not detected.
- * Errors: INVALID_ARG, NO_WORKSPACE, HIP, NONFINITE (only with stats_host). */
+ * Errors: INVALID_ARG (also: TOMO_INIT_LEARNED without a network or with
+ * unet_scale <= 0), NO_WORKSPACE, NOT_READY (network without parameters or
+ * workspace), HIP, NONFINITE (only with stats_host). */
 tomo_status tomo_reconstruct(tomo_plan plan, const float* sino, float* x,
                              const tomo_recon_opts_t* opts, tomo_recon_stats_t* stats_host);
 

@@ -4,8 +4,9 @@
  *
  * The paper starts the iteration from a ramp-filtered back-projection (Sec. 2.2, Eqs.
  * 12-14) and counts a better start as saved iterations (Sec. 3.2).  This network maps the
- * FBP image to a start closer to the converged reconstruction; tomo_reconstruct takes it
- * through TOMO_INIT_USER.
+ * FBP image to a start closer to the converged reconstruction; tomo_reconstruct runs it
+ * with TOMO_INIT_LEARNED (keeping the FBP start where the network's start has the larger
+ * objective, or outside the training domain), or takes its output through TOMO_INIT_USER.
  *
  * Network (levels L, base channels C; level l has C 2^l channels at H/2^l x W/2^l):
  *   u = fbp / scale;  E0a = relu(conv(u)), E0 = relu(conv(E0a));
@@ -73,6 +74,20 @@ tomo_status tomo_unet_loss_grad(tomo_unet net, const float* fbp, const float* ta
  * loss (device float64, nullable). */
 tomo_status tomo_unet_train_step(tomo_unet net, const float* fbp, const float* target,
                                  int32_t batch, float scale, float lr, double* loss);
+/* Training domain of a network: the problems whose reconstructions it was trained on.
+ * tomo_reconstruct with TOMO_INIT_LEARNED uses the network only on a coarsest level with
+ * N_0 == n (== height == width of the network), n_det_0 == n_det, centre c_0 within 1e-6 of
+ * center (NaN -> n_det / 2), n_angles_min <= n_angles <= n_angles_max, and the same prior
+ * (beta, p, sigma, T within a relative 1e-9, the same neighbourhood). */
+typedef struct {
+  int32_t n, n_det;
+  int32_t n_angles_min, n_angles_max;
+  double center;
+  double beta, p, sigma, T;
+  int32_t neighbours;
+} tomo_unet_domain_t;
+/* Record (domain != NULL) or clear (NULL) the training domain.  Errors: INVALID_ARG. */
+tomo_status tomo_unet_set_domain(tomo_unet net, const tomo_unet_domain_t* domain);
 tomo_status tomo_unet_destroy(tomo_unet net);
 const char* tomo_unet_last_error(tomo_unet net);
 

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libtomo.so")
-SOURCES = ["toeplitz_kernels.hip", "gridding_kernels.hip", "unet_kernels.hip", "tomo_api.cpp",
-           "unet_api.cpp"]
+SOURCES = ["toeplitz_kernels.hip", "gridding_kernels.hip", "unet_kernels.hip", "start_kernels.hip",
+           "tomo_api.cpp", "unet_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -101,6 +101,29 @@ hipError_t launch_batch_iteration(const BatchProb* probs, const int2* items, int
                                   int grid, hipStream_t st);
 hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st);
 
+// ---- start selection (learned start with FBP fallback) -----------------------------------
+// qGGMRF constants in float64 for the objective of a candidate start.
+struct ObjParams {
+  double beta;        // prior weight
+  double p;           // exponent p
+  double qmp;         // q - p
+  double inv_Tsigma;  // 1 / (T sigma)
+  double c_rho;       // 1 / (p sigma^p)
+  double w1, w2, w3;  // normalised neighbour weights: axis, face diagonal, body diagonal
+  int neighbours;     // 8 or 26
+  int quadratic;      // 1 when p == q
+};
+constexpr int kObjBlocks = 64;  // blocks per slice of the start objective
+// part [nz][kObjBlocks]: per-block float64 sums of 1/2 x T x - x b + beta (forward-pair rho).
+hipError_t launch_slice_objective(const float* x, const float* tx, const float* b, int N, int nz,
+                                  const ObjParams& op, double* part, hipStream_t st);
+// Per slice (per_slice = 1) or for the whole volume: keep xb where its objective (pb) does not
+// exceed xa's (pa) and is finite, copying it over xa; choice[z] (and choice_user[z], nullable)
+// receive 1 where xb was kept.
+hipError_t launch_select_start(const double* pa, const double* pb, int nz, int per_slice,
+                               float* xa, const float* xb, int N, int32_t* choice,
+                               int32_t* choice_user, hipStream_t st);
+
 // ---- tables and utilities ---------------------------------------------------------------
 hipError_t launch_twiddles_f32(cpx<float>* tw, int P, hipStream_t st);
 hipError_t launch_twiddles_f64(cpx<double>* tw, int P, hipStream_t st);

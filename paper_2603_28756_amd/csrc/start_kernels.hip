@@ -1,0 +1,125 @@
+// Choice of the start image when a learned start is offered (Sec. 2.2 takes the ramp-filtered
+// back-projection as the start; Sec. 3.2 counts a better start as iterations saved): the
+// float64 objective of a candidate start per slice, and the per-slice (or whole-volume)
+// choice between the network's start and the FBP start.
+//
+// Objective of a candidate x (Eq. 10 without the constant 1/2 <g, g>, plus the prior of
+// Eq. 5):  1/2 <x, T x> - <x, b> + beta Phi(x), Phi summed over unordered neighbour pairs,
+// each pair counted once at the voxel that precedes it (forward offsets), so that the sums
+// of all slices give the whole volume's objective also with the 26-neighbourhood.
+#include "kernels.hpp"
+
+namespace tomo {
+namespace {
+
+constexpr int SO_NT = 256;
+
+// rho(d) = |d|^p / (p sigma^p) * w / (1 + w),  w = (|d| / (T sigma))^(q - p)  (float64).
+TOMO_DEV double rho64(double d, const ObjParams& op) {
+  const double a = fabs(d);
+  if (a == 0.0) return 0.0;
+  const double w = op.quadratic ? 1.0 : pow(a * op.inv_Tsigma, op.qmp);
+  return op.c_rho * pow(a, op.p) * (w / (1.0 + w));
+}
+
+TOMO_DEV double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = SO_NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// part[z][blk]: this block's share of slice z's objective terms (fixed assignment of pixels
+// to threads and a fixed reduction tree: deterministic).
+__global__ __launch_bounds__(SO_NT) void slice_objective_kernel(
+    const float* __restrict__ x, const float* __restrict__ tx, const float* __restrict__ b,
+    int N, int nz, ObjParams op, double* __restrict__ part) {
+  __shared__ double sh[SO_NT];
+  const int z = blockIdx.y;
+  const idx_t plane = (idx_t)N * N;
+  const float* xz = x + z * plane;
+  const float* tz = tx + z * plane;
+  const float* bz = b + z * plane;
+  const bool up = op.neighbours == 26 && z + 1 < nz;
+  double data = 0.0, prior = 0.0;
+  for (int i = blockIdx.x * SO_NT + threadIdx.x; i < N * N; i += gridDim.x * SO_NT) {
+    const int r = i / N, c = i - r * N;
+    const double v = xz[i];
+    data += 0.5 * v * (double)tz[i] - v * (double)bz[i];
+    // in-plane forward offsets (0, 1), (1, -1), (1, 0), (1, 1)
+    if (c + 1 < N) prior += op.w1 * rho64(v - xz[i + 1], op);
+    if (r + 1 < N) {
+      const float* nx = xz + i + N;
+      prior += op.w1 * rho64(v - nx[0], op);
+      if (c > 0) prior += op.w2 * rho64(v - nx[-1], op);
+      if (c + 1 < N) prior += op.w2 * rho64(v - nx[1], op);
+    }
+    // the 9 offsets into the next slice (26-neighbourhood)
+    if (up) {
+      const float* nu = xz + plane + i;
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (r + dy < 0 || r + dy >= N) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (c + dx < 0 || c + dx >= N) continue;
+          const int k = (dy != 0) + (dx != 0);
+          const double w = k == 0 ? op.w1 : (k == 1 ? op.w2 : op.w3);
+          prior += w * rho64(v - nu[dy * N + dx], op);
+        }
+      }
+    }
+  }
+  const double s = block_sum(data + op.beta * prior, sh);
+  if (threadIdx.x == 0) part[(idx_t)z * gridDim.x + blockIdx.x] = s;
+}
+
+// Block z decides for slice z (per_slice) or for the whole volume (every block takes the same
+// decision from the same fixed-order sums): the network's start xb is kept unless its
+// objective exceeds the FBP start's or is not finite; a kept slice is copied over xa.
+__global__ __launch_bounds__(SO_NT) void select_start_kernel(
+    const double* __restrict__ pa, const double* __restrict__ pb, int nblk, int nz, int per_slice,
+    float* __restrict__ xa, const float* __restrict__ xb, int N, int32_t* __restrict__ choice,
+    int32_t* __restrict__ choice_user) {
+  __shared__ int keep;
+  const int z = blockIdx.x;
+  if (threadIdx.x == 0) {
+    const int z0 = per_slice ? z : 0, z1 = per_slice ? z + 1 : nz;
+    double fa = 0.0, fb = 0.0;
+    for (int zz = z0; zz < z1; ++zz)
+      for (int k = 0; k < nblk; ++k) {
+        fa += pa[(idx_t)zz * nblk + k];
+        fb += pb[(idx_t)zz * nblk + k];
+      }
+    keep = (isfinite(fb) && !(fb > fa)) ? 1 : 0;
+    choice[z] = keep;
+    if (choice_user) choice_user[z] = keep;
+  }
+  __syncthreads();
+  if (!keep) return;
+  const idx_t plane = (idx_t)N * N;
+  float* dst = xa + z * plane;
+  const float* src = xb + z * plane;
+  for (idx_t i = threadIdx.x; i < plane; i += SO_NT) dst[i] = src[i];
+}
+
+}  // namespace
+
+hipError_t launch_slice_objective(const float* x, const float* tx, const float* b, int N, int nz,
+                                  const ObjParams& op, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(slice_objective_kernel, dim3(kObjBlocks, nz), dim3(SO_NT), 0, st, x, tx, b,
+                     N, nz, op, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_start(const double* pa, const double* pb, int nz, int per_slice,
+                               float* xa, const float* xb, int N, int32_t* choice,
+                               int32_t* choice_user, hipStream_t st) {
+  hipLaunchKernelGGL(select_start_kernel, dim3(nz), dim3(SO_NT), 0, st, pa, pb, kObjBlocks, nz,
+                     per_slice, xa, xb, N, choice, choice_user);
+  return hipGetLastError();
+}
+
+}  // namespace tomo

@@ -12,7 +12,9 @@
 #include <vector>
 
 #include "../../include/tomo.h"
+#include "../../include/tomo_nn.h"
 #include "kernels.hpp"
+#include "unet_view.hpp"
 
 using namespace tomo;
 
@@ -59,6 +61,7 @@ struct tomo_plan_s {
   int nz = 0, n_levels = 1;
   std::vector<Level> lv;
   PriorParams pp{};
+  ObjParams op{};       // the same prior in float64 (objective of candidate starts)
   double rho2_0 = 0.0;  // rho''(0)
 
   // workspace
@@ -73,6 +76,7 @@ struct tomo_plan_s {
   size_t off_scratch = 0, scratch_bytes = 0;
   size_t off_gp = 0, off_ppartials = 0, off_y = 0;
   size_t off_cnt = 0, off_scan = 0, off_rampf = 0;
+  size_t off_objpart = 0, off_choice = 0;  // learned start: objective partials, choice
   bool fused_prior = false, grids_ready = false;
   bool tables_ready = false, psf_ready = false;
   std::string err;
@@ -84,6 +88,8 @@ struct tomo_plan_s {
   bool concurrent_prior = false;
   hipStream_t pstream = nullptr;
   hipEvent_t pev_fork = nullptr, pev_join = nullptr;
+  // learned start: the network's stream ordered after / before the plan's stream
+  hipEvent_t nev_fork = nullptr, nev_join = nullptr;
   struct GraphKey { int level, ik, nz; double* hist; int32_t* rhist; bool obj; };
   struct GraphEnt { GraphKey key; hipGraphExec_t exec; };
   std::vector<GraphEnt> graphs;
@@ -183,6 +189,8 @@ void layout(tomo_plan p) {
   size_t maxprior = 1;
   for (const Level& l : p->lv) maxprior = std::max(maxprior, (size_t)prior_blocks(l.n, p->nz));
   p->off_ppartials = take(maxprior * 4 * sizeof(double));
+  p->off_objpart = take(2 * (size_t)p->nz * kObjBlocks * sizeof(double));
+  p->off_choice = take((size_t)p->nz * sizeof(int32_t));
   const size_t npts_max = (size_t)na * (fin.nd - 1);
   p->off_ghat = take((size_t)p->nz * npts_max * sizeof(cpx<float>));
   p->off_dfttab = take((size_t)fin.nd * sizeof(cpx<float>));
@@ -550,6 +558,61 @@ tomo_status get_graph(tomo_plan p, int level, int ik, int ikm1, int inext, const
   return TOMO_OK;
 }
 
+// Is the coarsest level inside the network's training domain (tomo_unet_domain_t)?
+bool in_domain(tomo_plan p, const Level& l, const UnetView& v) {
+  if (v.height != l.n || v.width != l.n || !v.has_domain) return false;
+  const tomo_unet_domain_t& d = v.domain;
+  auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-9 * std::max(std::fabs(a), std::fabs(b)); };
+  const double dc = std::isnan(d.center) ? 0.5 * d.n_det : d.center;
+  return d.n == l.n && d.n_det == l.nd && std::fabs(l.c - dc) <= 1e-6 &&
+         p->g.n_angles >= d.n_angles_min && p->g.n_angles <= d.n_angles_max &&
+         close(d.beta, p->g.beta) && close(d.p, p->g.p) && close(d.sigma, p->g.sigma) &&
+         close(d.T, p->g.T) && d.neighbours == p->g.neighbours;
+}
+
+// Learned start on level l: the FBP image in xbuf(cur) is mapped by the network into
+// xbuf(alt); both starts' float64 objectives (T x into the y volume) decide, per slice with the
+// 8-neighbour prior or for the whole volume with the 26-neighbour prior, which one xbuf(cur)
+// holds afterwards (FBP unless the network's objective is not larger).
+tomo_status learned_start(tomo_plan p, const Level& l, const float* b, int cur, const UnetView& net,
+                          const tomo_recon_opts_t* o) {
+  hipStream_t st = p->stream;
+  float* xa = p->xbuf(cur);
+  float* xb = p->xbuf((cur + 1) % 3);
+  float* ty = p->at<float>(p->off_y);
+  const size_t plane = (size_t)l.n * l.n;
+  const bool fork = net.stream != st;
+  if (fork) {
+    if (!p->nev_fork) HIPCHK(p, hipEventCreateWithFlags(&p->nev_fork, hipEventDisableTiming));
+    if (!p->nev_join) HIPCHK(p, hipEventCreateWithFlags(&p->nev_join, hipEventDisableTiming));
+    HIPCHK(p, hipEventRecord(p->nev_fork, st));
+    HIPCHK(p, hipStreamWaitEvent(net.stream, p->nev_fork, 0));
+  }
+  for (int z0 = 0; z0 < p->nz; z0 += net.max_batch) {
+    const int m = std::min(net.max_batch, p->nz - z0);
+    const tomo_status s = tomo_unet_forward(o->unet, xa + z0 * plane, xb + z0 * plane, m, o->unet_scale);
+    if (s != TOMO_OK) return fail(p, s, "learned start: %s", tomo_unet_last_error(o->unet));
+  }
+  if (fork) {
+    HIPCHK(p, hipEventRecord(p->nev_join, net.stream));
+    HIPCHK(p, hipStreamWaitEvent(st, p->nev_join, 0));
+  }
+  double* pa = p->at<double>(p->off_objpart);
+  double* pb = pa + (size_t)p->nz * kObjBlocks;
+  const float* cand[2] = {xa, xb};
+  double* parts[2] = {pa, pb};
+  for (int k = 0; k < 2; ++k) {
+    HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, st));
+    int nb = 0;
+    tomo_status s = toeplitz_passes(p, l, MODE_POWER, p->nz, cand[k], cand[k], nullptr, ty, false, &nb);
+    if (s != TOMO_OK) return s;
+    HIPCHK(p, launch_slice_objective(cand[k], ty, b, l.n, p->nz, p->op, parts[k], st));
+  }
+  HIPCHK(p, launch_select_start(pa, pb, p->nz, p->g.neighbours == 8 ? 1 : 0, xa, xb, l.n,
+                                p->at<int32_t>(p->off_choice), o->init_choice_dev, st));
+  return TOMO_OK;
+}
+
 tomo_status validate_geom(const tomo_geometry_t* g) {
   if (!g) return fail(nullptr, TOMO_ERR_INVALID_ARG, "geometry is NULL");
   if (g->n < 16 || g->n > 2048 || (g->n & 1))
@@ -684,6 +747,17 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   pp.wts[3] = (float)(r3 / sum);
   pp.neighbours = geom->neighbours;
   pp.quadratic = pe == q ? 1 : 0;
+  ObjParams& op = p->op;
+  op.beta = geom->beta;
+  op.p = pe;
+  op.qmp = q - pe;
+  op.inv_Tsigma = 1.0 / (T * sg);
+  op.c_rho = 1.0 / (pe * std::pow(sg, pe));
+  op.w1 = r1 / sum;
+  op.w2 = r2 / sum;
+  op.w3 = r3 / sum;
+  op.neighbours = geom->neighbours;
+  op.quadratic = pe == q ? 1 : 0;
   p->rho2_0 = pe == q ? 1.0 / (2.0 * sg * sg) : 2.0 / (pe * std::pow(T, 2.0 - pe) * sg * sg);
 
   layout(p);
@@ -775,8 +849,16 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
                              const tomo_recon_opts_t* opts, tomo_recon_stats_t* stats) {
   if (!p || !sino || !x || !opts || !opts->iters) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
   if (!aligned(sino) || !aligned(x)) return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
-  if (opts->init < TOMO_INIT_FBP || opts->init > TOMO_INIT_USER)
+  if (opts->init < TOMO_INIT_FBP || opts->init > TOMO_INIT_LEARNED)
     return fail(p, TOMO_ERR_INVALID_ARG, "unknown init");
+  UnetView net;
+  if (opts->init == TOMO_INIT_LEARNED) {
+    if (!unet_view(opts->unet, &net)) return fail(p, TOMO_ERR_INVALID_ARG, "learned start without a network");
+    if (!(opts->unet_scale > 0.f) || !std::isfinite(opts->unet_scale))
+      return fail(p, TOMO_ERR_INVALID_ARG, "unet_scale must be > 0");
+    if (!net.ready) return fail(p, TOMO_ERR_NOT_READY, "network has no workspace or parameters");
+  }
+  int learned_state = TOMO_LEARNED_NOT_REQUESTED;
   if (opts->L_override < 0.0 || !std::isfinite(opts->L_override))
     return fail(p, TOMO_ERR_INVALID_ARG, "L_override must be >= 0");
   for (int l = 0; l < p->n_levels; ++l)
@@ -803,8 +885,14 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
     HIPCHK(p, launch_sumsq_strided(sino, (idx_t)p->nz * p->g.n_angles, l.nd, l.stride,
                                    1.0 / l.stride, p->partials(), sc + SC_GG, st));
     if (li == 0) {
-      if (opts->init == TOMO_INIT_FBP) {
+      if (opts->init == TOMO_INIT_FBP || opts->init == TOMO_INIT_LEARNED) {
         if ((s = backproject_level(p, l, sino, p->xbuf(cur), 1, true)) != TOMO_OK) return s;
+        if (opts->init == TOMO_INIT_LEARNED) {
+          learned_state = in_domain(p, l, net) ? TOMO_LEARNED_TESTED : TOMO_LEARNED_OUT_OF_DOMAIN;
+          if (learned_state == TOMO_LEARNED_TESTED &&
+              (s = learned_start(p, l, b, cur, net, opts)) != TOMO_OK)
+            return s;
+        }
       } else if (opts->init == TOMO_INIT_ZERO) {
         HIPCHK(p, launch_fill(p->xbuf(cur), (idx_t)vol, 0.0f, st));
       } else {
@@ -865,6 +953,14 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
     }
     stats->n_restarts = (int32_t)sv[SC_NRESTART];
     stats->nonfinite_iter = (int32_t)sv[SC_NONFINITE];
+    stats->learned_state = learned_state;
+    stats->learned_slices = 0;
+    if (learned_state == TOMO_LEARNED_TESTED) {
+      std::vector<int32_t> ch((size_t)p->nz);
+      HIPCHK(p, hipMemcpy(ch.data(), p->at<int32_t>(p->off_choice), ch.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost));
+      for (int32_t c : ch) stats->learned_slices += c;
+    }
     if (stats->nonfinite_iter >= 0)
       return fail(p, TOMO_ERR_NONFINITE, "non-finite value at iteration %d", stats->nonfinite_iter);
   }
@@ -1360,6 +1456,8 @@ tomo_status tomo_plan_destroy(tomo_plan p) {
   if (p->pev_join) (void)hipEventDestroy(p->pev_join);
   if (p->gev_in) (void)hipEventDestroy(p->gev_in);
   if (p->gev_out) (void)hipEventDestroy(p->gev_out);
+  if (p->nev_fork) (void)hipEventDestroy(p->nev_fork);
+  if (p->nev_join) (void)hipEventDestroy(p->nev_join);
   delete p;
   return TOMO_OK;
 }

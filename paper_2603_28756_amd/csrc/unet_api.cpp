@@ -14,6 +14,7 @@
 
 #include "tomo_nn.h"
 #include "nn_kernels.hpp"
+#include "unet_view.hpp"
 
 using namespace tomo;
 
@@ -45,6 +46,8 @@ struct tomo_unet_s {
   size_t off_r = 0, off_scratch = 0, scratch_floats = 0, off_hpart = 0, off_loss = 0;
   int64_t step = 0;
   bool params_ready = false;
+  bool has_domain = false;
+  tomo_unet_domain_t domain{};
   std::string err;
 
   template <typename T>
@@ -429,6 +432,21 @@ tomo_status tomo_unet_train_step(tomo_unet u, const float* fbp, const float* tar
   return prep_weights(u);
 }
 
+tomo_status tomo_unet_set_domain(tomo_unet u, const tomo_unet_domain_t* d) {
+  if (!u) return nfail(nullptr, TOMO_ERR_INVALID_ARG, "network is NULL");
+  if (!d) {
+    u->has_domain = false;
+    return TOMO_OK;
+  }
+  if (d->n < 1 || d->n_det < 2 || d->n_angles_min < 1 || d->n_angles_max < d->n_angles_min ||
+      !(d->beta >= 0.0) || !(d->p >= 1.0) || !(d->sigma > 0.0) || !(d->T > 0.0) ||
+      (d->neighbours != 8 && d->neighbours != 26))
+    return nfail(u, TOMO_ERR_INVALID_ARG, "invalid training domain");
+  u->domain = *d;
+  u->has_domain = true;
+  return TOMO_OK;
+}
+
 tomo_status tomo_unet_destroy(tomo_unet u) {
   delete u;
   return TOMO_OK;
@@ -476,6 +494,24 @@ tomo_status tomo_nn_conv3x3_wgrad(const uint16_t* dz, int32_t ldz, const uint16_
   if (e != hipSuccess) return nfail(nullptr, TOMO_ERR_HIP, "conv3x3 wgrad: %s", hipGetErrorString(e));
   return TOMO_OK;
 }
+
+}  // extern "C"
+
+namespace tomo {
+bool unet_view(tomo_unet u, UnetView* v) {
+  if (!u || !v) return false;
+  v->height = u->H;
+  v->width = u->W;
+  v->max_batch = u->maxB;
+  v->ready = u->ws != nullptr && u->params_ready;
+  v->has_domain = u->has_domain;
+  v->domain = u->domain;
+  v->stream = u->stream;
+  return true;
+}
+}  // namespace tomo
+
+extern "C" {
 
 // ---- weight gradient without caller scratch ------------------------------------------------
 // The split partial sums of tomo_nn_conv3x3_wgrad_noalloc live in this file-scope device array

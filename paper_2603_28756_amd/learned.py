@@ -5,8 +5,10 @@ a better start as iterations saved (Sec. 3.2).  Here a U-Net (include/tomo_nn.h)
 trained to map the FBP image to the method's own converged reconstruction, and the two
 starts are compared by the time to reach a relative objective gap
     r_k = (F(y_k) - F*) / (F(0) - F*) <= tol,
-F* being the lowest objective seen in long runs from both starts and F(0) = 1/2 <g, g>.
-A start whose objective exceeds the FBP start's is replaced by the FBP start (fallback).
+F* being the lowest objective seen in long runs from both starts and F(0) = 1/2 <g, g>
+(and, tighter, (F(y_k) - F*) / |F*| <= tol).  The learned start runs inside
+tomo_reconstruct (TOMO_INIT_LEARNED), which keeps the FBP start on every slice where the
+network's start has the larger objective, or everywhere outside the network's training domain.
 
 This module only sequences library calls (reconstruction plans, U-Net training steps);
 every arithmetic step runs in the HIP kernels.
@@ -128,10 +130,19 @@ def iterations_to_gap(hist: np.ndarray, f0: float, fstar: float, tol: float) -> 
     return int(hit[0]) if hit.size else None
 
 
+def record_domain(net: "tomo.UNet", pr: Problem, n_angles_min: Optional[int] = None,
+                  n_angles_max: Optional[int] = None):
+    """Record the training domain of a network trained on problems like `pr` (tomo_nn.h)."""
+    net.set_domain(pr.n, pr.n_det, n_angles_min or pr.n_angles, n_angles_max or pr.n_angles, pr.beta,
+                   p=pr.p, neighbours=pr.neighbours)
+
+
 def compare_starts(pr: Problem, sinos: np.ndarray, net: "tomo.UNet", scale: float, device,
-                   long_iters: int = 2000, tol: float = 1e-4, net_batch: int = 8) -> dict:
-    """Time to the relative gap `tol` from the FBP start and from the U-Net start on the
-    held-out slices `sinos` (solved together as one batch of independent slices)."""
+                   long_iters: int = 2000, tol: float = 1e-4, reps: int = 5) -> dict:
+    """Time to the relative gap `tol` from the FBP start and from the learned start
+    (tomo_reconstruct with TOMO_INIT_LEARNED: network inference, the per-slice objective test
+    and the FBP fallback all inside the call) on the held-out slices `sinos`, solved together
+    as one batch of independent slices.  The network's training domain must be recorded."""
     k = sinos.shape[0]
     plan = make_plan(pr, k, device)
     g = torch.from_numpy(np.ascontiguousarray(sinos)).to(device)
@@ -139,36 +150,39 @@ def compare_starts(pr: Problem, sinos: np.ndarray, net: "tomo.UNet", scale: floa
     hist0 = torch.zeros(1, dtype=torch.float64, device=device)
     plan.reconstruct(g, x, [1], init=tomo.INIT_ZERO, objective=hist0, stats=False)
     f0 = float(hist0.item())
-
+    learned_kw = {"unet": net, "unet_scale": scale}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fbp = torch.empty_like(x)
-    plan.backproject(g, fbp, ramp=True)  # warm-up
-    ev0.record()
-    plan.backproject(g, fbp, ramp=True)
-    ev1.record()
-    torch.cuda.synchronize(device)
-    fbp_ms = ev0.elapsed_time(ev1)
-    learned = infer(net, fbp, scale, net_batch)  # warm-up
-    ev0.record()
-    learned = infer(net, fbp, scale, net_batch)
-    ev1.record()
-    torch.cuda.synchronize(device)
-    unet_ms = ev0.elapsed_time(ev1)
 
-    def run(init, start):
+    def init_ms(init, **kw):
+        """Median time of a zero-iteration call: R* g plus the start (FBP, or FBP, network,
+        objective test and choice)."""
+        plan.reconstruct(g, x, [0], init=init, stats=False, **kw)  # warm-up
+        ts = []
+        for _ in range(reps):
+            ev0.record()
+            plan.reconstruct(g, x, [0], init=init, stats=False, **kw)
+            ev1.record()
+            torch.cuda.synchronize(device)
+            ts.append(ev0.elapsed_time(ev1))
+        return float(np.median(ts))
+
+    fbp_ms = init_ms(tomo.INIT_FBP)
+    learned_ms = init_ms(tomo.INIT_LEARNED, **learned_kw)
+
+    def run(init, **kw):
         h = torch.zeros(long_iters, dtype=torch.float64, device=device)
-        if start is not None:
-            x.copy_(start)
-        plan.reconstruct(g, x, [long_iters], init=init, objective=h, stats=False)
-        return h.cpu().numpy()
+        st = plan.reconstruct(g, x, [long_iters], init=init, objective=h, **kw)
+        return h.cpu().numpy(), st
 
-    h_fbp = run(tomo.INIT_FBP, None)
-    h_net = run(tomo.INIT_USER, learned)
+    h_fbp, _ = run(tomo.INIT_FBP)
+    h_net, st_net = run(tomo.INIT_LEARNED, **learned_kw)
     fstar = float(min(h_fbp.min(), h_net.min()))
     tail = abs(h_fbp[-1] - h_fbp[-long_iters // 4]) / abs(fstar)
-    fallback = bool(h_net[0] > h_fbp[0])
     k_fbp = iterations_to_gap(h_fbp, f0, fstar, tol)
-    k_net = k_fbp if fallback else iterations_to_gap(h_net, f0, fstar, tol)
+    k_net = iterations_to_gap(h_net, f0, fstar, tol)
+    # the same in the tighter measure (F - F*) / |F*|
+    k_fbp_abs = iterations_to_gap(h_fbp, fstar + abs(fstar), fstar, tol)
+    k_net_abs = iterations_to_gap(h_net, fstar + abs(fstar), fstar, tol)
 
     # per-iteration time of this batch (graph replay), from two run lengths
     def timed(iters):
@@ -179,13 +193,20 @@ def compare_starts(pr: Problem, sinos: np.ndarray, net: "tomo.UNet", scale: floa
         return ev0.elapsed_time(ev1)
     timed(50)
     it_ms = (timed(450) - timed(50)) / 400.0
-    t_fbp = fbp_ms + (k_fbp if k_fbp is not None else np.nan) * it_ms
-    t_net = fbp_ms + unet_ms + (k_net if k_net is not None else np.nan) * it_ms
+
+    def total(init, kk):
+        return init + (kk if kk is not None else np.nan) * it_ms
+    t_fbp, t_net = total(fbp_ms, k_fbp), total(learned_ms, k_net)
     return {
         "slices": k, "tol": tol, "F0": f0, "F_star": fstar, "F_star_tail_change": tail,
         "gap_at_start": {"fbp": (h_fbp[0] - fstar) / (f0 - fstar), "unet": (h_net[0] - fstar) / (f0 - fstar)},
-        "iterations": {"fbp": k_fbp, "unet": k_net}, "fallback_to_fbp": fallback,
-        "ms": {"fbp_start": fbp_ms, "unet_start": unet_ms, "iteration": it_ms,
-               "total_fbp": t_fbp, "total_unet": t_net},
+        "iterations": {"fbp": k_fbp, "unet": k_net},
+        "iterations_rel_fstar": {"fbp": k_fbp_abs, "unet": k_net_abs},
+        "learned_slices": st_net["learned_slices"], "learned_state": st_net["learned_state"],
+        "fallback_to_fbp": st_net["learned_slices"] < k,
+        "ms": {"fbp_start": fbp_ms, "learned_start": learned_ms, "iteration": it_ms,
+               "total_fbp": t_fbp, "total_unet": t_net,
+               "total_fbp_rel_fstar": total(fbp_ms, k_fbp_abs),
+               "total_unet_rel_fstar": total(learned_ms, k_net_abs)},
         "speedup": t_fbp / t_net if t_net and np.isfinite(t_net) else None,
     }

@@ -25,7 +25,8 @@ STATUS_NAMES = {
     0: "OK", 1: "INVALID_ARG", 2: "NO_DEVICE", 3: "UNSUPPORTED_ARCH", 4: "NO_WORKSPACE",
     5: "WORKSPACE_TOO_SMALL", 6: "NOT_READY", 7: "HIP", 8: "NONFINITE", 9: "INTERNAL",
 }
-INIT_FBP, INIT_ZERO, INIT_USER = 0, 1, 2
+INIT_FBP, INIT_ZERO, INIT_USER, INIT_LEARNED = 0, 1, 2, 3
+LEARNED_NOT_REQUESTED, LEARNED_TESTED, LEARNED_OUT_OF_DOMAIN = 0, 1, 2
 T_ROWS_FWD, T_COLS_CONV, T_ROWS_INV, T_FINALIZE, T_BACKPROJECT, T_PSF, T_PRIOR, T_COUNT = range(8)
 FLAG_NO_GRAPH = 1
 FLAG_FUSED_PRIOR = 2
@@ -55,6 +56,7 @@ class ReconOpts(ctypes.Structure):
         ("iters", ctypes.POINTER(ctypes.c_int32)), ("init", ctypes.c_int32),
         ("restart", ctypes.c_int32), ("L_override", ctypes.c_double),
         ("objective_dev", ctypes.c_void_p), ("restart_dev", ctypes.c_void_p),
+        ("unet", ctypes.c_void_p), ("unet_scale", ctypes.c_float), ("init_choice_dev", ctypes.c_void_p),
     ]
 
 
@@ -62,6 +64,16 @@ class ReconStats(ctypes.Structure):
     _fields_ = [
         ("L", ctypes.c_double * 6), ("lambda_pow", ctypes.c_double * 6),
         ("n_restarts", ctypes.c_int32), ("nonfinite_iter", ctypes.c_int32),
+        ("learned_state", ctypes.c_int32), ("learned_slices", ctypes.c_int32),
+    ]
+
+
+class UnetDomain(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_det", ctypes.c_int32), ("n_angles_min", ctypes.c_int32),
+        ("n_angles_max", ctypes.c_int32), ("center", ctypes.c_double), ("beta", ctypes.c_double),
+        ("p", ctypes.c_double), ("sigma", ctypes.c_double), ("T", ctypes.c_double),
+        ("neighbours", ctypes.c_int32),
     ]
 
 
@@ -123,6 +135,7 @@ EXPORTS = {
                              ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "tomo_unet_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
                               ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
+    "tomo_unet_set_domain": ([ctypes.c_void_p, ctypes.POINTER(UnetDomain)], ctypes.c_int),
     "tomo_unet_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "tomo_unet_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
     "tomo_nn_conv3x3": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -258,13 +271,18 @@ class Plan:
     def reconstruct(self, sino: torch.Tensor, x: torch.Tensor, iters: Sequence[int],
                     init: int = INIT_FBP, restart: bool = True, L_override: float = 0.0,
                     objective: Optional[torch.Tensor] = None,
-                    restarts: Optional[torch.Tensor] = None, stats: bool = True):
+                    restarts: Optional[torch.Tensor] = None, stats: bool = True,
+                    unet: Optional["UNet"] = None, unet_scale: float = 0.0,
+                    init_choice: Optional[torch.Tensor] = None):
         it = (ctypes.c_int32 * len(iters))(*[int(i) for i in iters])
         o = ReconOpts()
         o.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
         o.init, o.restart, o.L_override = init, int(restart), float(L_override)
         o.objective_dev = _ptr(objective)
         o.restart_dev = _ptr(restarts)
+        o.unet = unet._h.value if unet is not None else None
+        o.unet_scale = float(unet_scale)
+        o.init_choice_dev = _ptr(init_choice)
         st = ReconStats() if stats else None
         status = self._lib.tomo_reconstruct(self._h, _ptr(sino), _ptr(x), ctypes.byref(o),
                                             ctypes.byref(st) if st is not None else None)
@@ -272,7 +290,8 @@ class Plan:
         if st is None:
             return None
         return {"L": list(st.L)[: self.n_levels], "lambda_pow": list(st.lambda_pow)[: self.n_levels],
-                "n_restarts": st.n_restarts, "nonfinite_iter": st.nonfinite_iter}
+                "n_restarts": st.n_restarts, "nonfinite_iter": st.nonfinite_iter,
+                "learned_state": st.learned_state, "learned_slices": st.learned_slices}
 
     def psf_info(self, level: int = -1, with_spectrum: bool = True):
         level = self.n_levels - 1 if level < 0 else level
@@ -414,6 +433,18 @@ class UNet:
         if getattr(self, "_h", None) is not None and self._lib is not None:
             self._lib.tomo_unet_destroy(self._h)
             self._h = None
+
+    def set_domain(self, n: int, n_det: int, n_angles_min: int, n_angles_max: int, beta: float,
+                   p: float = 1.2, sigma: float = 0.1, T: float = 1.0, neighbours: int = 8,
+                   center: Optional[float] = None):
+        """Record the training domain (tomo_unet_domain_t) the learned start is used in."""
+        d = UnetDomain(int(n), int(n_det), int(n_angles_min), int(n_angles_max),
+                       float("nan") if center is None else float(center), float(beta), float(p),
+                       float(sigma), float(T), int(neighbours))
+        _unet_check(self._lib.tomo_unet_set_domain(self._h, ctypes.byref(d)), self._h)
+
+    def clear_domain(self):
+        _unet_check(self._lib.tomo_unet_set_domain(self._h, None), self._h)
 
     def set_params(self, theta: torch.Tensor):
         t = theta.to(device=self.device, dtype=torch.float32).contiguous()

@@ -54,3 +54,13 @@ def make_plan(n, nz, angles, n_det, center=None, neighbours=26, beta=0.01, p=1.2
 
 def oracle_prior(neighbours=26, p=1.2, sigma=0.1, T=1.0):
     return qg.QGGMRF(p=p, q=2.0, sigma=sigma, T=T, neighbours=neighbours)
+
+
+def objective_err(got, ref, sino) -> float:
+    """Largest objective difference relative to F(0) = <g, g>/2.  The Toeplitz-form objective
+    (Eq. 10) is a difference of terms of size ~<g, g>, so float32 operators leave an absolute
+    error of order 1e-7 <g, g> however small F itself becomes near the optimum."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    f0 = 0.5 * float(np.vdot(sino, sino))
+    return float(np.max(np.abs(got - ref)) / f0)

@@ -5,6 +5,8 @@ oversampling 2, P = 1024, 26 neighbours) is too large for the oracle to
 reconstruct in a test, so each operator is checked where the oracle can
 compute exact values:
 * F K and the step constant L in full (oracle PSF by direct sums, ~10-30 s);
+* T x and the whole gradient in full over all 64 slices (oracle padded-FFT product with the
+  oracle's F K, itself pinned to A^T A applied directly, and the oracle prior gradient);
 * R* g and FBP at sampled pixels of several slices (exact sums per pixel);
 * T x at sampled pixels of one slice (oracle A then A^T per pixel);
 * the full gradient at sampled voxels (T x, b and the prior one voxel at a time).
@@ -50,11 +52,17 @@ def _sample_pixels(rng, n, count):
     return ys, xs
 
 
-def test_fullsize_psf_spectrum_and_step(setup):
-    plan, geom = setup["plan"], setup["geom"]
+@pytest.fixture(scope="module")
+def oracle_fk(setup):
+    _, _, P = setup["plan"].level_dims(0)
+    return toeplitz.psf_spectrum(setup["geom"], P)
+
+
+def test_fullsize_psf_spectrum_and_step(setup, oracle_fk):
+    plan = setup["plan"]
     fk_gpu, L_gpu, lam_gpu = plan.psf_info()
     _, _, P = plan.level_dims(0)
-    fk = toeplitz.psf_spectrum(geom, P)
+    fk = oracle_fk
     assert rel_l2(to_np(fk_gpu), fk[:, : P // 2 + 1]) < 1e-5
     lam = solver.power_lambda(fk, WL.n, 30)
     assert abs(lam_gpu - lam) / lam < 1e-5
@@ -111,3 +119,26 @@ def test_fullsize_normal_operator_and_gradient_sampled(setup):
     norm = np.sqrt(parts[0]) + np.sqrt(parts[1]) + WL.beta * np.sqrt(parts[2])
     err = np.linalg.norm(np.concatenate(g_gpu) - np.concatenate(g_ref))
     assert err / norm < 1e-5
+
+
+def test_fullsize_normal_operator_and_gradient_full_arrays(setup, oracle_fk):
+    """T x and grad = T x - b + beta grad Phi(x) over the whole 64 x 512^2 volume."""
+    plan = setup["plan"]
+    rng = np.random.default_rng(23)
+    x = (setup["phantom"] + 0.05 * rng.standard_normal(setup["phantom"].shape)).astype(np.float32)
+    b = (0.5 * rng.standard_normal(x.shape)).astype(np.float32)
+    xd, bd = to_dev(x), to_dev(b)
+    tx = torch.empty_like(xd)
+    grad = torch.empty_like(xd)
+    plan.apply_normal(xd, tx)
+    plan.gradient(xd, bd, grad)
+    tx_np, grad_np = to_np(tx), to_np(grad)
+    del tx, grad, xd, bd
+    x64, b64 = x.astype(np.float64), b.astype(np.float64)
+    tref = toeplitz.apply(x64, oracle_fk, WL.n)
+    assert rel_l2(tx_np, tref) < 1e-5
+    pr = qg.QGGMRF(p=WL.p, q=WL.q, sigma=WL.sigma, T=WL.T, neighbours=WL.neighbours)
+    gphi = qg.gradient(x64, pr)
+    gref = tref - b64 + WL.beta * gphi
+    norm = np.linalg.norm(tref) + np.linalg.norm(b64) + WL.beta * np.linalg.norm(gphi)
+    assert np.linalg.norm(grad_np - gref) / norm < 1e-5

