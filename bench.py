@@ -12,18 +12,23 @@ value = N^2 * n_slices * iterations / (seconds per step)   [gradient voxel-updat
 
 roofline: the kernel class with the largest share of the step is timed live with
 HIP events on the plan's stream over a second pass of the same steps (events turn
-off graph replay, so they are kept out of the timed region).  For passes R and R' the
-algorithmic bytes per launch over the mean launch time are compared with the 8 TB/s
-HBM peak; pass C (two length-P FFTs per column) is bound by vector-ALU work, so its FFT
-flops (5 P log2 P per transform) per launch over its mean launch time are
-compared with the non-packed FP32 vector peak, 256 CUs x 64 lanes x 2 x 2.4 GHz =
-78.6 TFLOP/s; the prior kernel is bound by vector-ALU issue, so its
-algorithmic VALU lane-operations per launch (transcendentals weighted 2, their issue
-cost on gfx950 as measured by paper_2603_28756_amd/lib/valu_probe) over its mean launch
-time are compared with the chip's non-packed FP32 VALU issue rate,
+off graph replay, so they are kept out of the timed region); its algorithmic bytes per
+launch over the mean launch time are compared with the 8 TB/s HBM peak (the path is
+memory-bound by design).  Alongside, the ALU view of the two arithmetic-heavy kernels:
+pass C's FFT flops (5 P log2 P per transform) against the non-packed FP32 vector peak,
+256 CUs x 64 lanes x 2 x 2.4 GHz = 78.6 TFLOP/s, and the prior's algorithmic VALU
+lane-operations (transcendentals weighted 2, their measured issue cost on gfx950) against
 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
-cpu_baseline: the FP64 oracle's own iteration (Toeplitz product by numpy FFTs,
-prior, update) timed on a bounded slab of the same volume on the host.
+iteration_hbm: measured HBM bytes per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE summary,
+when it matches the current kernel sources) over the wall time of the graph-replayed
+iteration loop, against 8 TB/s; and the same for the compulsory 20.5 B/voxel and the
+three-pass 56 B/voxel model.  Precompute and iteration loop are also timed separately
+(median of 5).
+cpu_baseline: the FP64 oracle's own iteration (Toeplitz product by numpy FFTs, prior,
+update) on a 4-slice slab of the same volume, run in one process per host core (the box's
+CPU share) at once; plus the oracle's direct A^T(A x) against its Toeplitz product at
+N = 128 and 256 (the CPU analogue of the paper's direct-vs-Toeplitz comparison).  Both run
+in a child process that does not touch the GPU.
 """
 from __future__ import annotations
 
@@ -80,6 +85,13 @@ def read_traffic(cls: str):
     return found.get(cls)
 
 
+def iteration_traffic():
+    """Measured HBM bytes of one iteration (passes R, C, R', prior, finalize) from the counter
+    summary, or None when it does not match the current kernel sources."""
+    vals = [read_traffic(c) for c in ("rows_fwd", "cols_conv", "rows_inv", "prior", "finalize")]
+    return None if any(v is None for v in vals) else float(sum(vals))
+
+
 def prior_lane_ops(n: int, nz: int, neighbours: int) -> float:
     """Algorithmic VALU lane-operations of one prior launch.
 
@@ -125,12 +137,36 @@ def algorithmic_bytes(cls: str, n: int, nz: int, P: int, fused_prior: bool = Fal
     return float("nan")
 
 
-def cpu_baseline(wl, prob_np, iters: int = 3, slices: int = 4) -> dict:
-    """Oracle FISTA on a contiguous slab of `slices` slices, `iters` iterations."""
+_POOL_PROB = None   # the oracle problem each forked worker iterates on
+
+
+def _oracle_worker(arg):
+    iters, L = arg
+    from oracle import solver
+    x0 = _POOL_PROB.b * 0.0
+    t0 = time.perf_counter()
+    solver.fista(_POOL_PROB, x0, iters, L=L)
+    return time.perf_counter() - t0
+
+
+def cpu_share() -> int:
+    """Host cores this process may use, at most 16 (one GPU's share of the box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(wl, prob_np, iters: int = 5, slices: int = 4) -> dict:
+    """Oracle FISTA on a contiguous slab of `slices` slices, `iters` iterations, in one forked
+    process per core (each on its own copy of the slab); aggregate voxel-updates/s."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import geometry as G
     from oracle import prior as qg
     from oracle import radon, solver, toeplitz
+    global _POOL_PROB
     geom = G.Geometry(wl.n, prob_np["angles"], wl.n_det)
     z0 = wl.n_slices // 2 - slices // 2
     sino = prob_np["sino32"][z0:z0 + slices].astype(np.float64)
@@ -140,19 +176,72 @@ def cpu_baseline(wl, prob_np, iters: int = 3, slices: int = 4) -> dict:
     fk = toeplitz.psf_spectrum(geom, P)
     b = radon.adjoint(sino, geom)
     t_pre = time.perf_counter() - t0
-    prob = solver.Problem(geom, fk, b, float(np.vdot(sino, sino)), pr, wl.beta)
-    x0 = b * 0.0
-    L = solver.lipschitz(prob)
-    t0 = time.perf_counter()
-    solver.fista(prob, x0, iters, L=L)
-    t_it = time.perf_counter() - t0
-    vox = slices * wl.n * wl.n * iters
-    return {"value": vox / t_it, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{slices} of {wl.n_slices} slices (z {z0}..{z0 + slices - 1}), {iters} FISTA "
-                       f"iterations of the float64 oracle (numpy FFT Toeplitz product, 26-neighbour "
-                       f"prior, update), {t_it:.1f} s; oracle PSF spectrum + R*g precompute of the "
-                       f"slab took {t_pre:.1f} s and the step constant is not in the rate either"),
+    _POOL_PROB = solver.Problem(geom, fk, b, float(np.vdot(sino, sino)), pr, wl.beta)
+    L = solver.lipschitz(_POOL_PROB)
+    workers = cpu_share()
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        times = pool.map(_oracle_worker, [(iters, L)] * workers, chunksize=1)
+        wall = time.perf_counter() - t0
+    vox = workers * slices * wl.n * wl.n * iters
+    return {"value": vox / wall, "unit": "voxel-updates/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{workers} processes at once, each {iters} FISTA iterations of the float64 oracle "
+                       f"(numpy FFT Toeplitz product, {wl.neighbours}-neighbour prior, update) on a copy of "
+                       f"slices {z0}..{z0 + slices - 1} of the {wl.n_slices} x {wl.n}^2 volume; wall "
+                       f"{wall:.1f} s, per process {min(times):.1f}-{max(times):.1f} s; the oracle's PSF "
+                       f"spectrum and R* g of the slab ({t_pre:.1f} s) and its step constant are not in "
+                       f"the rate"),
+            "single_process_value": slices * wl.n * wl.n * iters / min(times),
             "host_cpus": os.cpu_count()}
+
+
+def cpu_direct_vs_toeplitz() -> dict:
+    """The oracle's direct A^T(A x) (exact non-uniform DFTs as dense products) against its
+    padded-FFT Toeplitz product on one slice, N = 128 (90 angles) and 256 (180 angles)."""
+    import numpy as np
+    import synth
+    from oracle import geometry as G
+    from oracle import radon, solver, toeplitz
+    out = []
+    for n, na in ((128, 90), (256, 180)):
+        nd = synth.detector_bins_for(n)
+        geom = G.Geometry(n, synth.uniform_angles(na), nd)
+        x = np.random.default_rng(n).standard_normal((n, n))
+        fk = toeplitz.psf_spectrum(geom, solver.pad_size(n))
+        t0 = time.perf_counter()
+        direct = radon.adjoint(radon.forward(x, geom), geom)
+        t_dir = time.perf_counter() - t0
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            toep = toeplitz.apply(x, fk, n)
+        t_toe = (time.perf_counter() - t0) / reps
+        out.append({"n": n, "n_angles": na, "n_det": nd, "direct_ms": 1e3 * t_dir,
+                    "toeplitz_ms": 1e3 * t_toe, "speedup": t_dir / t_toe,
+                    "rel_diff": float(np.linalg.norm(direct - toep) / np.linalg.norm(direct))})
+    return {"kind": "oracle", "precision": "f64", "cases": out}
+
+
+def run_cpu_only(args) -> int:
+    """Host-only measurements (no GPU is touched): one JSON line."""
+    import numpy as np
+    import synth
+    wl = synth.WORKLOADS[args.workload]
+    pr = synth.make_problem(wl.n, wl.n_slices, wl.n_angles, wl.n_det, wl.noise, wl.seed, wl.n_objects)
+    prob_np = {"angles": pr["angles"], "sino32": pr["sino"].astype(np.float32)}
+    print(json.dumps({"cpu_baseline": cpu_baseline(wl, prob_np),
+                      "cpu_direct_vs_toeplitz": cpu_direct_vs_toeplitz()}))
+    return 0
+
+
+def cpu_measurements(workload: str) -> dict:
+    """run_cpu_only in a child process started before or after the GPU work of this one."""
+    import subprocess
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only", "--workload", workload],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"cpu measurements failed:\n{res.stderr[-2000:]}")
+    return json.loads(res.stdout.strip().splitlines()[-1])
 
 
 def run_batch(args) -> int:
@@ -302,6 +391,8 @@ def main() -> int:
                     help="keep the default tile schedule instead of the autotuned one")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only the host measurements (oracle baseline, direct vs Toeplitz); no GPU")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -309,6 +400,8 @@ def main() -> int:
               "(this build runs the one-GPU share of a slice-axis sharding)", file=sys.stderr)
         return 2
 
+    if args.cpu_only:
+        return run_cpu_only(args)
     if args.workload == "learned_init_512":
         return run_learned(args)
     if args.workload == "batch_256":
@@ -335,7 +428,6 @@ def main() -> int:
     iters = list(wl.iterations) if not args.iters else [args.iters] * wl.levels
     pr = synth.make_problem(wl.n, wl.n_slices, wl.n_angles, wl.n_det, wl.noise, wl.seed, wl.n_objects)
     sino32 = pr["sino"].astype(np.float32)
-    prob_np = {"angles": pr["angles"], "sino32": sino32}
     sino = torch.from_numpy(sino32).to(dev)
     plan = tomo.Plan(wl.n, wl.n_slices, wl.n_angles, wl.n_det, angles=list(pr["angles"]),
                      n_levels=wl.levels, kb_width=wl.kb_width, kb_oversamp=wl.kb_oversamp,
@@ -390,6 +482,32 @@ def main() -> int:
     plan.timing_enable([])
     mean_hot_ms = ms_hot[hot] / max(cnt_hot[hot], 1)
 
+    # phases timed on their own (median of 5): the float64 precompute, R* g and FBP, and the
+    # iteration loop as the wall time of a full call minus a zero-iteration call (graph replay)
+    def ev_ms(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    tmp = torch.empty_like(x)
+    phases = {
+        "psf_spectrum_and_step_ms": ev_ms(plan.precompute_psf),
+        "backprojection_ms": ev_ms(lambda: plan.backproject(sino, tmp, ramp=False)),
+        "fbp_ms": ev_ms(lambda: plan.backproject(sino, tmp, ramp=True)),
+        "call_without_iterations_ms": ev_ms(
+            lambda: plan.reconstruct(sino, x, [0] * wl.levels, init=tomo.INIT_FBP, stats=False)),
+        "call_with_iterations_ms": ev_ms(
+            lambda: plan.reconstruct(sino, x, iters, init=tomo.INIT_FBP, stats=False)),
+    }
+    del tmp
+    loop_ms = phases["call_with_iterations_ms"] - phases["call_without_iterations_ms"]
+    phases["iteration_loop_ms"] = loop_ms
+    phases["iteration_wall_ms"] = loop_ms / sum(iters)
+
     total_iters = sum(iters)
     vox = wl.n * wl.n * wl.n_slices * total_iters
     value = vox / (ms_per_step * 1e-3)
@@ -398,28 +516,39 @@ def main() -> int:
     name = CLASS_NAMES[hot]
     alg = algorithmic_bytes(name, wl.n, wl.n_slices, P, args.fused_prior, args.concurrent_prior)
     traffic = read_traffic(name)
+    achieved = alg / (mean_hot_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg}
     if name == "prior":
         ops = prior_lane_ops(wl.n, wl.n_slices, wl.neighbours)
-        achieved = ops / (mean_hot_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "T lane-ops/s (VALU, FP32 non-packed)", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": traffic, "algorithmic_lane_ops_per_launch": ops,
-                "algorithmic_bytes_per_launch": alg,
-                "hbm_frac": alg / (mean_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        a_ops = ops / (mean_hot_ms * 1e-3) / 1e12
+        roof["alu"] = {"achieved": a_ops, "peak": VALU_PEAK_TOPS,
+                       "unit": "T lane-ops/s (VALU, FP32 non-packed)", "frac": a_ops / VALU_PEAK_TOPS,
+                       "algorithmic_lane_ops_per_launch": ops}
     elif name == "cols_conv":
         flops = cols_conv_flops(wl.n, wl.n_slices, P)
-        achieved = flops / (mean_hot_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s (FP32 vector, non-packed; FFT flops 5 P log2 P)",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": alg,
-                "hbm_frac": alg / (mean_hot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    else:
-        achieved = alg / (mean_hot_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": alg}
+        a_fl = flops / (mean_hot_ms * 1e-3) / 1e12
+        roof["alu"] = {"achieved": a_fl, "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s (FP32 vector, non-packed; FFT flops 5 P log2 P)",
+                       "frac": a_fl / FP32_PEAK_TFLOPS, "algorithmic_flops_per_launch": flops}
     roof.update({"mean_launch_ms": mean_hot_ms, "launches_timed": cnt_hot[hot]})
+    # whole iteration against HBM: measured bytes (counter summary) and the byte models
+    vox1 = float(wl.n * wl.n * wl.n_slices)
+    it_s = phases["iteration_wall_ms"] * 1e-3
+    meas = iteration_traffic()
+    iteration_hbm = {
+        "wall_ms": phases["iteration_wall_ms"],
+        "measured_bytes": meas,
+        "measured_frac": (meas / it_s / 1e9 / HBM_PEAK_GBS) if meas else None,
+        "design_bytes": sum(algorithmic_bytes(c, wl.n, wl.n_slices, P, args.fused_prior,
+                                              args.concurrent_prior)
+                            for c in ("rows_fwd", "cols_conv", "rows_inv", "prior")),
+        "model_56B_frac": 56.0 * vox1 / it_s / 1e9 / HBM_PEAK_GBS,
+        "compulsory_20_5B_frac": 20.5 * vox1 / it_s / 1e9 / HBM_PEAK_GBS,
+        "voxel_updates_per_s": vox1 / it_s,
+    }
+    iteration_hbm["design_frac"] = iteration_hbm["design_bytes"] / it_s / 1e9 / HBM_PEAK_GBS
     out = {
         "metric": "gradient voxel-updates/s",
         "value": value,
@@ -445,15 +574,17 @@ def main() -> int:
                                                 if args.concurrent_prior else "in sequence")),
         },
         "roofline": roof,
-        "iteration_ms": iter_ms,
-        "iteration_voxel_updates_per_s": wl.n * wl.n * wl.n_slices / (iter_ms * 1e-3),
-        "effective_hbm_frac_20B": 20.0 * wl.n * wl.n * wl.n_slices / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "iteration_hbm": iteration_hbm,
+        "phases_ms_median5": phases,
+        "iteration_kernel_ms": iter_ms,
         "breakdown_one_step": breakdown,
         "autotune": {"seconds": tune_s, "levels": tiles} if tiles else None,
         "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, prob_np)
+        cpu = cpu_measurements(args.workload)
+        out["cpu_baseline"] = cpu["cpu_baseline"]
+        out["cpu_direct_vs_toeplitz"] = cpu["cpu_direct_vs_toeplitz"]
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

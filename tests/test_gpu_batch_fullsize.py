@@ -2,8 +2,12 @@
 from {128, 192, 256, 384, 512, 768, 1024}, 30..360 angles and 1..5% noise, advanced by one
 persistent launch per iteration.  Every problem must stay finite with no tile wait timing
 out; one problem of every size is compared with its own single plan (<= 1e-6, only the
-float64 partial-sum order differs) and the smallest with the FP64 oracle (<= 1e-4).
+float64 partial-sum order differs) and with the FP64 oracle (<= 1e-4): the smallest width
+computed in the test, every width >= 192 against the stored oracle runs of
+tests/golden/batch_sizes.npz (written by tests/golden/make_golden.py from oracle/ only).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -49,3 +53,16 @@ def test_uneven_batch_of_256():
     prob = solver.build(geom, sino, oracle_prior(8), 0.01)
     ref = solver.fista(prob, ofbp.fbp(sino, geom), iters)
     assert rel_l2(to_np(xs[j]), ref.x) < 1e-4
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_sizes.npz"))
+    checked = []
+    for n, j in sorted(firsts.items()):
+        if n < 192:
+            continue
+        s_ref = float(gold[f"sino_sum_{j}"])
+        assert abs(float(np.sum(probs[j]["sino"].astype(np.float64))) - s_ref) <= 1e-9 * abs(s_ref)
+        err = rel_l2(to_np(xs[j]), gold[f"x_{j}"])
+        print(f"batch problem {j}: N {n}, {probs[j]['n_angles']} angles: rel-L2 vs oracle {err:.3e}",
+              flush=True)
+        assert err < 1e-4, (n, err)
+        checked.append(n)
+    assert checked == [192, 256, 384, 512, 768, 1024]
