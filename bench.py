@@ -259,6 +259,10 @@ def run_batch(args) -> int:
                        neighbours=8, beta=0.01, device=dev) for p in probs]
     batch = tomo.Batch(plans)
     sinos = [torch.from_numpy(p["sino"]).to(dev) for p in probs]
+    t0 = time.perf_counter()
+    schedule = batch.autotune(reps=5)   # per-size radix choice, once per batch
+    tune_s = time.perf_counter() - t0
+    print(f"batch schedule: {schedule} ({tune_s:.2f} s)", file=sys.stderr, flush=True)
     xs = [torch.empty((1, p["n"], p["n"]), dtype=torch.float32, device=dev) for p in probs]
     vox = float(sum(p["n"] ** 2 for p in probs))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -292,7 +296,15 @@ def run_batch(args) -> int:
                    "count_per_size": {str(n): sum(1 for p in probs if p["n"] == n) for n in sizes},
                    "angles": [min(p["n_angles"] for p in probs), max(p["n_angles"] for p in probs)],
                    "noise": [0.01, 0.05], "neighbours": 8, "kb_width": 6,
-                   "voxels_per_iteration": vox},
+                   "voxels_per_iteration": vox,
+                   "schedule": {"elements_per_thread_by_fft_size": schedule["sizes"],
+                                "tiles_per_item_by_fft_size": schedule["group"],
+                                "prior": ("inside pass R' (8 neighbours, each pair from both voxels)"
+                                          if schedule["fused_prior"] else "pair-shared prior phase"),
+                                "autotune_iter_ms": schedule["iter_ms"],
+                                "starting_schedule_iter_ms": schedule["base_ms"], "autotune_s": tune_s,
+                                "launch": "one persistent launch per iteration (prior, R, C, R' items "
+                                          "of all problems from one queue), graph-captured"}},
         "one_plan_at_a_time": {"ms_per_iteration": it_seq, "voxel_updates_per_s": vox / (it_seq * 1e-3)},
         "batching_speedup": it_seq / it_batch,
     }

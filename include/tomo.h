@@ -317,10 +317,10 @@ typedef struct {
 
 /* Group `n` single-level plans (each with its workspace attached, FFT size 256..2048, i.e.
  * 128 <= N <= 1024 at the default padding) into a batch advanced together: every iteration
- * of every problem runs in ONE persistent kernel launch that takes tiles of the three
- * Toeplitz passes of all problems from a phase-ordered queue (Sec. 2.1 and the accelerated
- * method of Sec. 2 applied to each problem independently; the prior is evaluated in the
- * inverse-row epilogue).  Problems keep their own geometry, prior, step constant, momentum
+ * of every problem runs in ONE persistent kernel launch that takes tiles from a phase-ordered
+ * queue: the pair-shared prior (which also forms y and beta grad Phi(y) - b), then the three
+ * Toeplitz passes, of all problems (Sec. 2.1 and the accelerated method of Sec. 2 applied to
+ * each problem independently).  Problems keep their own geometry, prior, step constant, momentum
  * and restart state.  The plans must outlive the batch and must not be used concurrently
  * with it.  Errors: INVALID_ARG, NO_DEVICE, HIP. */
 tomo_status tomo_batch_create(const tomo_plan* plans, int32_t n, void* hip_stream, tomo_batch* out);
@@ -336,6 +336,39 @@ tomo_status tomo_batch_set_workspace(tomo_batch batch, void* dev, size_t bytes);
  * Errors: INVALID_ARG, NO_WORKSPACE, HIP, NONFINITE / INTERNAL (with stats). */
 tomo_status tomo_batch_reconstruct(tomo_batch batch, const float* const* sinos, float* const* xs,
                                    int32_t iters, int32_t restart, tomo_batch_stats_t* stats);
+/* Transform schedule of a batch per FFT size P: each problem's passes R, C and R' use
+ * `elems` elements per thread (radix-elems Stockham stages, P / elems threads per transform,
+ * 256 / (P / elems) transforms per tile), 8 or 16 (default), and a queue item holds `group`
+ * consecutive tiles.  Every schedule computes the same transforms (the radix decomposition
+ * changes only their rounding). */
+#define TOMO_BATCH_MAX_SIZES 8
+typedef struct {
+  int32_t n_sizes;                      /* distinct FFT sizes in the batch                      */
+  int32_t pad[TOMO_BATCH_MAX_SIZES];    /* the sizes, increasing                                */
+  int32_t elems[TOMO_BATCH_MAX_SIZES];  /* elements per thread of each size: 8 or 16            */
+  int32_t group[TOMO_BATCH_MAX_SIZES];  /* tiles of passes R, C, R' per queue item, 1..64 (8)   */
+  int32_t fused_prior;                  /* 0: the pair-shared prior phase (default); 1: problems
+                                           with the 8-neighbour prior evaluate it inside pass R'
+                                           (each pair from both voxels, no prior phase, fewer
+                                           bytes moved); 26-neighbour problems keep the phase    */
+  float iter_ms;                        /* out (autotune): one batched iteration, chosen schedule */
+  float base_ms;                        /* out (autotune): the starting schedule above            */
+} tomo_batch_schedule_t;
+/* Time batched iterations (reps launches after a warm-up; reps <= 0 means 5) with the prior
+ * phase, 16 elements per thread and 8 tiles per item everywhere, then try the prior inside
+ * pass R' (when a problem has the 8-neighbour prior), 2, 16, 32 or 64 tiles per item for all
+ * sizes, per FFT size half or twice that, and per size 8 elements per thread, keeping each
+ * change that makes the whole iteration at least 3% faster (Sec. 2.1's padded FFTs,
+ * scheduled per size).
+ * Computes missing PSF spectra; overwrites every problem's iterates, b and scalars (call it
+ * before tomo_batch_reconstruct, which prepares them again).  Synchronises the batch stream.
+ * out: nullable.  Errors: INVALID_ARG, NO_WORKSPACE, HIP, INTERNAL. */
+tomo_status tomo_batch_autotune(tomo_batch batch, int32_t reps, tomo_batch_schedule_t* out);
+/* Set (set != NULL: fused_prior and pad/elems pairs, sizes not listed keep their choice) and/or
+ * read back (out != NULL) the schedule.  Errors: INVALID_ARG (a size not in the batch, elems not
+ * 8 or 16, fused_prior not 0 or 1). */
+tomo_status tomo_batch_schedule(tomo_batch batch, const tomo_batch_schedule_t* set,
+                                tomo_batch_schedule_t* out);
 tomo_status tomo_batch_destroy(tomo_batch batch);  /* NULL ok */
 
 /* Destroy a plan (NULL is accepted).  Does not free the caller's workspace. */

@@ -75,9 +75,15 @@ hipError_t launch_finalize(int mode, const double* partials, int nblocks,
 // One problem of a batch; every pointer lives in that problem's own plan workspace.
 struct BatchProb {
   int N, P, nz, neighbours;
-  int nR, nC, nRp;          // tiles of pass R, pass C, pass R'
+  int nPr, nR, nC, nRp;     // tiles of the prior phase, pass R, pass C, pass R'
+  int el;                   // elements per thread of the transforms (8 or 16)
+  int fused;                // 1: the prior inside pass R' (8 neighbours, no prior phase)
+  int grp;                  // tiles per queue item of passes R, C, R'
+  int iR, iC, iRp;          // queue items of pass R, pass C, pass R'
   int pad0;
   float* x[3];              // rotating iterates
+  float* y;                 // extrapolated point y (written by the prior phase)
+  float* gp;                // beta grad Phi(y) - b (written by the prior phase)
   const float* b;
   const float* fk;
   const float* fkn;
@@ -91,12 +97,15 @@ struct BatchProb {
   PriorParams pp;
 };
 constexpr int kBatchThreads = 256;
-// Tile counts of problem (N, P, nz) in the batched kernel.
-void batch_tile_counts(int N, int P, int nz, int* nR, int* nC, int* nRp);
+// Tile counts of problem (N, P, nz) in the batched kernel with `el` elements per thread.
+void batch_tile_counts(int N, int P, int nz, int el, int* nPr, int* nR, int* nC, int* nRp);
 bool batch_supports(int P);
-// items: int2 {prob | phase << 24, tile}, ordered by phase; ctl[0] = queue head, ctl[1] =
-// finished blocks, ctl[2] = error flag; cnt[3][nprob] = finished tiles per phase.
-hipError_t launch_batch_iteration(const BatchProb* probs, const int2* items, int n_items,
+// Resident blocks of the persistent batch kernel per compute unit (`fused`: the instantiation
+// that may evaluate the in-plane prior inside pass R').
+int batch_blocks_per_cu(bool fused);
+// items: int2 {prob | phase << 24, tile}, ordered by phase (prior, R, C, R'); ctl[0] = queue
+// head, ctl[1] = finished blocks, ctl[2] = error flag; cnt[4][nprob] = finished tiles per phase.
+hipError_t launch_batch_iteration(bool fused, const BatchProb* probs, const int2* items, int n_items,
                                   int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext,
                                   int grid, hipStream_t st);
 hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st);

@@ -79,12 +79,12 @@ constexpr int rows_fwd_lds() { return PAIRS * fft::row_region<P>() * 8; }
 
 // Block `blk` transforms row pairs blk*PAIRS .. blk*PAIRS+PAIRS-1 (counted over all slices).
 // y = x_k + mu (x_k - x_{k-1}), or s * x_k in power mode, or y = xk as given (MODE_FISTA_Y).
-template <int P, int PAIRS, int MODE>
+template <int P, int PAIRS, int MODE, int EL = kE>
 TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restrict__ xk,
                             const float* __restrict__ xkm1, float mu, float s,
                             cpx<float>* __restrict__ S1, const cpx<float>* __restrict__ tw, int N,
                             int n_pairs) {
-  using PL = fft::Plan<P, kE>;
+  using PL = fft::Plan<P, EL>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int REG = fft::row_region<P>();
   constexpr int H = P / 2;
@@ -165,12 +165,12 @@ template <int P, int TC>
 constexpr int cols_conv_lds() { return P * TC * 8; }
 
 // Column tile `bx` (columns bx*TC .. bx*TC+TC-1) of slice z.
-template <int P, int TC>
+template <int P, int TC, int EL = kE>
 TOMO_DEV void cols_conv_body(unsigned char* smem, int bx, int z,
                              const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
                              const float* __restrict__ fk, const float* __restrict__ fkn,
                              const cpx<float>* __restrict__ tw, int N) {
-  using PL = fft::Plan<P, kE>;
+  using PL = fft::Plan<P, EL>;
   using IPL = fft::RevPlan<PL>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int H = P / 2;
@@ -273,12 +273,17 @@ cols_conv_kernel(const cpx<float>* __restrict__ S1, cpx<float>* __restrict__ S2,
 // 0, S, ..., 7 S) fall on disjoint bank ranges for both 32-lane halves (32 banks) and the
 // whole wave (64 banks); every access of a wave to its own block shifted by a constant (a
 // neighbour offset) is then free of bank conflicts.
-constexpr int PR_TX = 32, PR_TY = 16, PR_ZC = 16;  // tile columns, rows, slices
-constexpr int PR_NT = PR_TX * PR_TY;                       // one voxel per thread
-constexpr int PR_WX = PR_TX / 8;                           // 8 x 8 wave blocks per tile row
-constexpr int PR_HX = PR_TX + 2, PR_HY = PR_TY + 2, PR_HA = PR_HX * PR_HY;  // halo tile
-constexpr int PR_S = PR_TX == 32 ? 40 : 24, PR_PA = PR_HY * PR_S;  // LDS row stride, plane
-static_assert(PR_TX == 16 || PR_TX == 32, "tile width");
+constexpr int PR_TX = 32, PR_TY = 16, PR_ZC = 16;  // tile columns (volume kernel), rows, slices
+constexpr int PR_NT = PR_TX * PR_TY;                 // one voxel per thread
+// Tile shape of width TX (32 for the volume kernel, 16 for the 256-thread batch phase).
+template <int TX_>
+struct PriorShape {
+  static_assert(TX_ == 16 || TX_ == 32, "tile width");
+  static constexpr int TX = TX_, TY = PR_TY, NT = TX * TY;
+  static constexpr int WX = TX / 8;                                  // 8 x 8 wave blocks per tile row
+  static constexpr int HX = TX + 2, HY = TY + 2, HA = HX * HY;       // halo tile
+  static constexpr int S = TX == 32 ? 40 : 24, PA = HY * S;          // LDS row stride, plane
+};
 
 // rho'(d) / c_grad and rho(d) for q = 2, arranged for few instructions:
 //   rho'(d) / c_grad = d r (1 + (q/p - 1) r),  r = 1 / (1 + w),
@@ -296,27 +301,29 @@ TOMO_DEV void qggmrf_unit(float d, const PriorParams& pp, float& rp, float& rv) 
   if constexpr (VAL) rv = pp.c_val2 * d * d * r;
 }
 
-template <int NB>
+template <int NB, int TX = PR_TX>
 struct PriorLds {
-  float Y[2][PR_PA];
-  float fin[4][PR_PA];
-  float fz[NB == 26 ? 9 : 1][PR_PA];
-  double sred[(PR_NT / 64) * 4];
+  using SH = PriorShape<TX>;
+  float Y[2][SH::PA];
+  float fin[4][SH::PA];
+  float fz[NB == 26 ? 9 : 1][SH::PA];
+  double sred[(SH::NT / 64) * 4];
 };
 
 // YG: also store y and write gp - b in place of gp (b = bvec), and with OBJ sum <y, b>, for
 // a FISTA step whose passes R and R' then read y and gp - b instead of x_{k-1}, b and gp.
-template <int NB, bool OBJ, bool QUAD, bool EDGE, bool YG>
-TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
+template <int NB, bool OBJ, bool QUAD, bool EDGE, bool YG, int TXW = PR_TX>
+TOMO_DEV void prior_tile(PriorLds<NB, TXW>& L, const float* __restrict__ xk,
                          const float* __restrict__ xkm1, float* __restrict__ gp,
                          const float* __restrict__ bvec, float* __restrict__ yout,
                          double* __restrict__ part_out, int N, int nz, int c0, int r0, int z0,
                          float mu, bool fista, const PriorParams& pp) {
-  constexpr int HX = PR_HX, HY = PR_HY, HA = PR_HA, S = PR_S, TX = PR_TX, TY = PR_TY;
+  using SH = PriorShape<TXW>;
+  constexpr int HX = SH::HX, HY = SH::HY, HA = SH::HA, S = SH::S, TX = SH::TX, TY = SH::TY;
   const int t = threadIdx.x;
   // own voxel: wave w covers rows 8 (w / WX) .. +7 and columns 8 (w % WX) .. +7 of the tile
   const int wv = t >> 6, ln = t & 63;
-  const int tr = 8 * (wv / PR_WX) + (ln >> 3), tc = 8 * (wv % PR_WX) + (ln & 7);
+  const int tr = 8 * (wv / SH::WX) + (ln >> 3), tc = 8 * (wv % SH::WX) + (ln & 7);
   const int s = (tr + 1) * S + tc + 1;  // own position in a plane buffer
   const int z1 = min(z0 + PR_ZC, nz);
   // neighbour weights with beta and the rho' prefactor folded in
@@ -354,7 +361,7 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
     else if (t == j3 + 1) { x_a = 0; x_b = HX - 1; x_o = 6; }
     else if (t == j3 + 2) { x_a = HY - 1; x_b = 0; x_o = 2; }
     else if (t == j3 + 3) { x_a = HY - 1; x_b = HX - 1; x_o = 0; }
-    static_assert(j3 + 4 <= PR_NT && 3 * TX + 3 * TY + 2 <= PR_NT, "one item per thread");
+    static_assert(j3 + 4 <= SH::NT && 3 * TX + 3 * TY + 2 <= SH::NT, "one item per thread");
   }
   // resolve the items once: start and end positions, activity and validity
   int in_pos = 0, in_q = 0, x_pos = 0, x_q = 0;
@@ -387,7 +394,7 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
   }
   // plane loads: the (at most two) halo elements of this thread, read row by row from
   // global memory (coalesced) and placed at their padded plane positions
-  const int e1 = t + PR_NT;
+  const int e1 = t + SH::NT;
   const bool has_e1 = e1 < HA;
   int g0, g1 = 0, l0, l1 = 0;
   bool v0 = true, v1 = true;
@@ -549,7 +556,7 @@ TOMO_DEV void prior_tile(PriorLds<NB>& L, const float* __restrict__ xk,
     if (NB == 26) cur = 1 - cur;
     __syncthreads();
   }
-  if (part_out) block_sum4<PR_NT>(phi, yb, 0.0, 0.0, part_out, L.sred);
+  if (part_out) block_sum4<SH::NT>(phi, yb, 0.0, 0.0, part_out, L.sred);
 }
 
 template <int NB, bool OBJ, bool QUAD, bool YG>
@@ -577,9 +584,9 @@ prior_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
 }
 
 // --------------------------------------------------------------------------------- pass R'
-template <int P, int PAIRS, int NB>
+template <int P, int PAIRS, int NB, int EL = kE>
 struct RowsInvLds {
-  static constexpr int TPF = P / kE, NT = PAIRS * TPF, RB = 2 * PAIRS, H = P / 2;
+  static constexpr int TPF = P / EL, NT = PAIRS * TPF, RB = 2 * PAIRS, H = P / 2;
   static constexpr int CW = 64;
   static constexpr int ZD = (NB == 26) ? 3 : 1;
   static constexpr int YT = NB == 0 ? 1 : ZD * (RB + 2) * (CW + 2);
@@ -600,15 +607,15 @@ struct RowsInvLds {
 
 // Block `blk` handles rows r0 .. r0+2*PAIRS-1 of one slice (blk counted over all slices);
 // its four float64 partial sums go to part_out[0..3].
-template <int P, int PAIRS, int MODE, int NB, bool OBJ>
+template <int P, int PAIRS, int MODE, int NB, bool OBJ, int EL = kE>
 TOMO_DEV void rows_inv_body(unsigned char* smem, int blk, const cpx<float>* __restrict__ S2,
                             const float* __restrict__ xk, const float* __restrict__ xkm1,
                             const float* __restrict__ bvec, const float* __restrict__ gpv,
                             float* __restrict__ out, double* __restrict__ part_out, float mu,
                             float invL, const cpx<float>* __restrict__ tw, int N, int nz,
                             const PriorParams& pp) {
-  using PL = fft::Plan<P, kE>;
-  using LY = RowsInvLds<P, PAIRS, NB>;
+  using PL = fft::Plan<P, EL>;
+  using LY = RowsInvLds<P, PAIRS, NB, EL>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int NT = LY::NT, RB = LY::RB, H = LY::H;
   constexpr int REG = fft::row_region<P>();
@@ -921,35 +928,48 @@ finalize_kernel(const double* __restrict__ partials, int nblocks,
 
 // ------------------------------------------------------------------- batched iteration
 // One persistent launch advances every problem of a batch by one iteration.  Blocks take
-// tiles from a queue ordered by phase (pass R tiles of all problems, then pass C, then pass
-// R'); a pass-C tile of problem j first waits until all pass-R tiles of j are finished, a
-// pass-R' tile until all pass-C tiles of j are.  Every tile waited on sits earlier in the queue
-// and was taken by a block that is already running and never waits on a later tile, so the
-// waits end; each is also bounded and raises ctl[2] instead of spinning forever.  The block
-// finishing the last pass-R' tile of a problem runs that problem's float64 finalize.  The last
-// block to leave resets the queue for the next launch.
+// tiles from a queue ordered by phase: the pair-shared prior tiles of all problems (which also
+// write y and gp - b), then pass R, pass C and pass R'.  A tile of phase h > 0 of problem j
+// first waits until every phase h - 1 tile of j is finished.  Every tile waited on sits earlier
+// in the queue and was taken by a block that is already running and never waits on a later
+// tile, so the waits end; each is also bounded and raises ctl[2] instead of spinning forever.
+// The block finishing the last pass-R' tile of a problem runs that problem's float64
+// finalize.  The last block to leave resets the queue for the next launch.
+//
+// Each problem's transforms use EL = 8 or 16 elements per thread (its FFT radix schedule),
+// chosen per FFT size by the batch autotuner; a tile of every phase is one 256-thread block.
 constexpr int BT = kBatchThreads;
 
-template <int P>
-constexpr int bt_tpf() { return P / kE; }
-template <int P>
-constexpr int bt_pairs() { return BT / bt_tpf<P>() < 1 ? 1 : BT / bt_tpf<P>(); }
-template <int P>
-constexpr int bt_tc() { return BT / bt_tpf<P>() < 1 ? 1 : BT / bt_tpf<P>(); }
+template <int P, int EL>
+constexpr int bt_tpf() { return P / EL; }
+template <int P, int EL>
+constexpr int bt_pairs() { return BT / bt_tpf<P, EL>() < 1 ? 1 : BT / bt_tpf<P, EL>(); }
+template <int P, int EL>
+constexpr int bt_tc() { return bt_pairs<P, EL>(); }
 
-template <int P>
-constexpr int batch_lds_p() {
-  constexpr int a = rows_fwd_lds<P, bt_pairs<P>()>();
-  constexpr int b = cols_conv_lds<P, bt_tc<P>()>();
-  constexpr int c = RowsInvLds<P, bt_pairs<P>(), 26>::BYTES;
-  constexpr int d = RowsInvLds<P, bt_pairs<P>(), 8>::BYTES;
-  constexpr int m1 = a > b ? a : b;
-  constexpr int m2 = c > d ? c : d;
-  return m1 > m2 ? m1 : m2;
+template <int P, int EL>
+constexpr int batch_lds_pe() {
+  constexpr int a = rows_fwd_lds<P, bt_pairs<P, EL>()>();
+  constexpr int b = cols_conv_lds<P, bt_tc<P, EL>()>();
+  constexpr int c = RowsInvLds<P, bt_pairs<P, EL>(), 0, EL>::BYTES;
+  constexpr int m = a > b ? a : b;
+  return m > c ? m : c;
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int kBatchLds = cmax(cmax(batch_lds_p<256>(), batch_lds_p<512>()),
-                               cmax(batch_lds_p<1024>(), batch_lds_p<2048>()));
+template <int P>
+constexpr int batch_lds_p() { return cmax(batch_lds_pe<P, 8>(), batch_lds_pe<P, 16>()); }
+constexpr int kBatchLds =
+    cmax(cmax(cmax(batch_lds_p<256>(), batch_lds_p<512>()), cmax(batch_lds_p<1024>(), batch_lds_p<2048>())),
+         cmax(cmax((int)sizeof(PriorLds<26, 16>), (int)sizeof(PriorLds<8, 16>)), 4 * BT * 8));
+// with the in-plane prior evaluated inside pass R' (8-neighbour problems, no prior phase)
+template <int P>
+constexpr int batch_lds_fused_p() {
+  return cmax(RowsInvLds<P, bt_pairs<P, 8>(), 8, 8>::BYTES, RowsInvLds<P, bt_pairs<P, 16>(), 8, 16>::BYTES);
+}
+constexpr int kBatchLdsFused =
+    cmax(kBatchLds, cmax(cmax(batch_lds_fused_p<256>(), batch_lds_fused_p<512>()),
+                         cmax(batch_lds_fused_p<1024>(), batch_lds_fused_p<2048>())));
+static_assert(PriorShape<16>::NT == BT, "a batch prior tile is one block");
 
 TOMO_DEV void bounded_wait(const int* ctr, int target, int* err) {
   if (threadIdx.x == 0) {
@@ -965,47 +985,123 @@ TOMO_DEV void bounded_wait(const int* ctr, int target, int* err) {
   __syncthreads();
 }
 
-// Each (P, phase) body is its own non-inlined function so that its registers are allocated
-// on their own rather than across every variant the persistent kernel can dispatch to.
-template <int P>
-__device__ __attribute__((noinline)) void batch_phase_r(unsigned char* smem, int tile,
-                                                        const BatchProb* pb, int ik, int ikm1) {
-  constexpr int PAIRS = bt_pairs<P>();
+// Each phase body is its own non-inlined function so that its registers are allocated on
+// their own rather than across every variant the persistent kernel can dispatch to.
+// A prior item is a strip of up to BP_SUB tiles of 16 x 16 voxels along a row band (and a
+// chunk of PR_ZC slices), transformed one tile after the other by the same block: few queue
+// items per problem however small its tiles are.
+constexpr int BP_SUB = 16;
+
+template <int NB, bool QUAD>
+__device__ __attribute__((noinline)) void batch_phase_prior(unsigned char* smem, int tile,
+                                                            const BatchProb* pb, int ik, int ikm1) {
+  using SH = PriorShape<16>;
+  const int N = pb->N;
+  const int ntx = (N + SH::TX - 1) / SH::TX, nty = (N + SH::TY - 1) / SH::TY;
+  const int nst = (ntx + BP_SUB - 1) / BP_SUB;  // strips per row band
+  const int strip = tile % nst, band = tile / nst;
+  const int r0 = (band % nty) * SH::TY, z0 = (band / nty) * PR_ZC;
   const float mu = (float)pb->scal[SC_MU];
-  rows_fwd_body<P, PAIRS, MODE_FISTA>(smem, tile, pb->x[ik], pb->x[ikm1], mu, 1.f, pb->S1, pb->tw,
-                                      pb->N, pb->nz * (pb->N / 2));
+  auto& L = *reinterpret_cast<PriorLds<NB, 16>*>(smem);
+  const int tx1 = min(ntx, (strip + 1) * BP_SUB);
+  for (int tx = strip * BP_SUB; tx < tx1; ++tx) {
+    const int c0 = tx * SH::TX;
+    const bool interior = r0 >= 1 && c0 >= 1 && r0 + SH::TY + 1 <= N && c0 + SH::TX + 1 <= N;
+    if (interior)
+      prior_tile<NB, false, QUAD, false, true, 16>(L, pb->x[ik], pb->x[ikm1], pb->gp, pb->b, pb->y,
+                                                   nullptr, N, pb->nz, c0, r0, z0, mu, true, pb->pp);
+    else
+      prior_tile<NB, false, QUAD, true, true, 16>(L, pb->x[ik], pb->x[ikm1], pb->gp, pb->b, pb->y,
+                                                  nullptr, N, pb->nz, c0, r0, z0, mu, true, pb->pp);
+    __syncthreads();  // the next tile rewrites the plane buffers
+  }
 }
 
-template <int P>
-__device__ __attribute__((noinline)) void batch_phase_c(unsigned char* smem, int tile,
+// A queue item of passes R, C and R' is a run of pb->grp consecutive tiles (the last run of a
+// problem may be shorter), transformed one after the other by the same block.
+TOMO_DEV void item_tiles(int item, int grp, int ntiles, int* t0, int* t1) {
+  *t0 = item * grp;
+  *t1 = min(ntiles, *t0 + grp);
+}
+
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_r(unsigned char* smem, int item,
+                                                        const BatchProb* pb, int ik, int ikm1) {
+  int t0, t1;
+  item_tiles(item, pb->grp, pb->nR, &t0, &t1);
+  const float mu = (float)pb->scal[SC_MU];
+  for (int tile = t0; tile < t1; ++tile) {
+    if (tile > t0) __syncthreads();  // the previous tile's rows are read from LDS
+    if (pb->fused)  // no prior phase: form y = x_k + mu (x_k - x_{k-1}) here
+      rows_fwd_body<P, bt_pairs<P, EL>(), MODE_FISTA, EL>(smem, tile, pb->x[ik], pb->x[ikm1], mu, 1.f,
+                                                          pb->S1, pb->tw, pb->N, pb->nz * (pb->N / 2));
+    else
+      rows_fwd_body<P, bt_pairs<P, EL>(), MODE_FISTA_Y, EL>(smem, tile, pb->y, pb->y, 0.f, 1.f, pb->S1,
+                                                            pb->tw, pb->N, pb->nz * (pb->N / 2));
+  }
+}
+
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_c(unsigned char* smem, int item,
                                                         const BatchProb* pb) {
-  constexpr int TC = bt_tc<P>();
+  constexpr int TC = bt_tc<P, EL>();
   constexpr int ncol = (P / 2) / TC;
-  const int z = tile / ncol;
-  cols_conv_body<P, TC>(smem, tile - z * ncol, z, pb->S1, pb->S2, pb->fk, pb->fkn, pb->tw, pb->N);
+  int t0, t1;
+  item_tiles(item, pb->grp, pb->nC, &t0, &t1);
+  for (int tile = t0; tile < t1; ++tile) {
+    if (tile > t0) __syncthreads();
+    const int z = tile / ncol;
+    cols_conv_body<P, TC, EL>(smem, tile - z * ncol, z, pb->S1, pb->S2, pb->fk, pb->fkn, pb->tw, pb->N);
+  }
 }
 
-template <int P, int NB>
-__device__ __attribute__((noinline)) void batch_phase_rp(unsigned char* smem, int tile,
-                                                         const BatchProb* pb, int ik, int ikm1,
-                                                         int inext) {
-  constexpr int PAIRS = bt_pairs<P>();
+// pass R' of a step whose y and gp - b were written by the prior phase (x_{k-1} slot: y)
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_rp(unsigned char* smem, int item,
+                                                         const BatchProb* pb, int ik, int inext) {
+  int t0, t1;
+  item_tiles(item, pb->grp, pb->nRp, &t0, &t1);
+  const float invL = (float)pb->scal[SC_INVL];
+  for (int tile = t0; tile < t1; ++tile) {
+    if (tile > t0) __syncthreads();
+    rows_inv_body<P, bt_pairs<P, EL>(), MODE_FISTA_Y, 0, false, EL>(
+        smem, tile, pb->S2, pb->x[ik], pb->y, nullptr, pb->gp, pb->x[inext],
+        pb->partials + (idx_t)tile * 4, 0.f, invL, pb->tw, pb->N, pb->nz, pb->pp);
+  }
+}
+
+// pass R' with the in-plane prior evaluated over a neighbour tile in its epilogue (each pair
+// from both of its voxels): the 8-neighbour problems of a batch scheduled without prior phase
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_rp_fused(unsigned char* smem, int item,
+                                                               const BatchProb* pb, int ik, int ikm1,
+                                                               int inext) {
+  int t0, t1;
+  item_tiles(item, pb->grp, pb->nRp, &t0, &t1);
   const float mu = (float)pb->scal[SC_MU];
   const float invL = (float)pb->scal[SC_INVL];
-  const PriorParams pp = pb->pp;
-  rows_inv_body<P, PAIRS, MODE_FISTA, NB, false>(smem, tile, pb->S2, pb->x[ik], pb->x[ikm1],
-                                                 pb->b, nullptr, pb->x[inext],
-                                                 pb->partials + (idx_t)tile * 4, mu, invL,
-                                                 pb->tw, pb->N, pb->nz, pp);
+  for (int tile = t0; tile < t1; ++tile) {
+    if (tile > t0) __syncthreads();
+    rows_inv_body<P, bt_pairs<P, EL>(), MODE_FISTA, 8, false, EL>(
+        smem, tile, pb->S2, pb->x[ik], pb->x[ikm1], pb->b, nullptr, pb->x[inext],
+        pb->partials + (idx_t)tile * 4, mu, invL, pb->tw, pb->N, pb->nz, pb->pp);
+  }
 }
 
-template <int P>
+template <int P, int EL, bool FUSED>
+TOMO_DEV void batch_tile_pe(unsigned char* smem, int phase, int item, const BatchProb* pb, int ik,
+                            int ikm1, int inext) {
+  if (phase == 1) batch_phase_r<P, EL>(smem, item, pb, ik, ikm1);
+  else if (phase == 2) batch_phase_c<P, EL>(smem, item, pb);
+  else if (FUSED && pb->fused) batch_phase_rp_fused<P, EL>(smem, item, pb, ik, ikm1, inext);
+  else batch_phase_rp<P, EL>(smem, item, pb, ik, inext);
+}
+
+template <int P, bool FUSED>
 TOMO_DEV void batch_tile(unsigned char* smem, int phase, int tile, const BatchProb* pb, int ik,
                          int ikm1, int inext) {
-  if (phase == 0) batch_phase_r<P>(smem, tile, pb, ik, ikm1);
-  else if (phase == 1) batch_phase_c<P>(smem, tile, pb);
-  else if (pb->neighbours == 26) batch_phase_rp<P, 26>(smem, tile, pb, ik, ikm1, inext);
-  else batch_phase_rp<P, 8>(smem, tile, pb, ik, ikm1, inext);
+  if (pb->el == 8) batch_tile_pe<P, 8, FUSED>(smem, phase, tile, pb, ik, ikm1, inext);
+  else batch_tile_pe<P, 16, FUSED>(smem, phase, tile, pb, ik, ikm1, inext);
 }
 
 // Float64 reduction of one problem's partial sums and its momentum / restart update (the same
@@ -1053,10 +1149,16 @@ TOMO_DEV void batch_finalize(const BatchProb& pb, double* sh /* [4][BT] */) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(BT)
+// At most 168 VGPRs (3 waves per SIMD): the non-inlined phase bodies keep a small call frame in
+// scratch instead of raising the register count to 182 (2 waves); a tighter bound (4 waves)
+// grows the frames and was measured slower.
+// FUSED: the instantiation whose 8-neighbour problems may take the prior inside pass R'
+// (more LDS per block).
+template <bool FUSED>
+__global__ void __launch_bounds__(BT, 3)
 batch_iter_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ items,
                   int n_items, int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext) {
-  __shared__ __align__(16) unsigned char smem[kBatchLds > 4 * BT * 8 ? kBatchLds : 4 * BT * 8];
+  __shared__ __align__(16) unsigned char smem[FUSED ? kBatchLdsFused : kBatchLds];
   __shared__ int s_item, s_fin;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1);
@@ -1066,20 +1168,32 @@ batch_iter_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ 
     const int2 d = items[it];
     const int j = d.x & 0xffffff, ph = d.x >> 24, tile = d.y;
     const BatchProb& pb = probs[j];
-    if (ph == 1) bounded_wait(&cnt[j], pb.nR, &ctl[2]);
-    if (ph == 2) bounded_wait(&cnt[nprob + j], pb.nC, &ctl[2]);
-    switch (pb.P) {
-      case 256: batch_tile<256>(smem, ph, tile, &pb, ik, ikm1, inext); break;
-      case 512: batch_tile<512>(smem, ph, tile, &pb, ik, ikm1, inext); break;
-      case 1024: batch_tile<1024>(smem, ph, tile, &pb, ik, ikm1, inext); break;
-      case 2048: batch_tile<2048>(smem, ph, tile, &pb, ik, ikm1, inext); break;
-      default: break;
+    if (ph > 0) {
+      const int need = ph == 1 ? pb.nPr : (ph == 2 ? pb.iR : pb.iC);
+      bounded_wait(&cnt[(ph - 1) * nprob + j], need, &ctl[2]);
+    }
+    if (ph == 0) {
+      if (pb.neighbours == 26) {
+        if (pb.pp.quadratic) batch_phase_prior<26, true>(smem, tile, &pb, ik, ikm1);
+        else batch_phase_prior<26, false>(smem, tile, &pb, ik, ikm1);
+      } else {
+        if (pb.pp.quadratic) batch_phase_prior<8, true>(smem, tile, &pb, ik, ikm1);
+        else batch_phase_prior<8, false>(smem, tile, &pb, ik, ikm1);
+      }
+    } else {
+      switch (pb.P) {
+        case 256: batch_tile<256, FUSED>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+        case 512: batch_tile<512, FUSED>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+        case 1024: batch_tile<1024, FUSED>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+        case 2048: batch_tile<2048, FUSED>(smem, ph, tile, &pb, ik, ikm1, inext); break;
+        default: break;
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();  // publish this tile's results before counting it
       const int done = atomicAdd(&cnt[ph * nprob + j], 1);
-      s_fin = (ph == 2 && done == pb.nRp - 1) ? 1 : 0;
+      s_fin = (ph == 3 && done == pb.iRp - 1) ? 1 : 0;
       if (s_fin) __threadfence();  // see every other tile's partial sums
     }
     __syncthreads();
@@ -1093,7 +1207,7 @@ batch_iter_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ 
       // every other block has left the loop: reset the queue for the next launch
       ctl[0] = 0;
       ctl[1] = 0;
-      for (int i = 0; i < 3 * nprob; ++i) cnt[i] = 0;
+      for (int i = 0; i < 4 * nprob; ++i) cnt[i] = 0;
       __threadfence();
     }
   }
@@ -1283,20 +1397,36 @@ int cols_tile_width(int P) { return col_tc(P); }
 
 bool batch_supports(int P) { return P >= 256 && P <= 2048; }
 
-void batch_tile_counts(int N, int P, int nz, int* nR, int* nC, int* nRp) {
-  const int tpf = P / kE;
+void batch_tile_counts(int N, int P, int nz, int el, int* nPr, int* nR, int* nC, int* nRp) {
+  const int tpf = P / el;
   const int pairs = BT / tpf < 1 ? 1 : BT / tpf;
   const int tc = pairs;
+  using SH = PriorShape<16>;
+  const int ntx = (N + SH::TX - 1) / SH::TX;
+  *nPr = ((ntx + BP_SUB - 1) / BP_SUB) * ((N + SH::TY - 1) / SH::TY) * ((nz + PR_ZC - 1) / PR_ZC);
   *nR = (nz * (N / 2) + pairs - 1) / pairs;
   *nC = nz * ((P / 2) / tc);
   *nRp = nz * ((N + 2 * pairs - 1) / (2 * pairs));
 }
 
-hipError_t launch_batch_iteration(const BatchProb* probs, const int2* items, int n_items,
+int batch_blocks_per_cu(bool fused) {
+  int nb = 0;
+  const hipError_t e =
+      fused ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_iter_kernel<true>, BT, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_iter_kernel<false>, BT, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_batch_iteration(bool fused, const BatchProb* probs, const int2* items, int n_items,
                                   int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext,
                                   int grid, hipStream_t st) {
-  hipLaunchKernelGGL(batch_iter_kernel, dim3(grid), dim3(BT), 0, st, probs, items, n_items, ctl,
-                     cnt, nprob, ik, ikm1, inext);
+  if (fused)
+    hipLaunchKernelGGL(batch_iter_kernel<true>, dim3(grid), dim3(BT), 0, st, probs, items, n_items,
+                       ctl, cnt, nprob, ik, ikm1, inext);
+  else
+    hipLaunchKernelGGL(batch_iter_kernel<false>, dim3(grid), dim3(BT), 0, st, probs, items, n_items,
+                       ctl, cnt, nprob, ik, ikm1, inext);
   return hipGetLastError();
 }
 

@@ -26,6 +26,8 @@ constexpr size_t kAlign = 256;
 constexpr int kMaxLevels = 6;
 constexpr int kPowerIters = 30;
 constexpr size_t kMaxGraphs = 24;  // cached three-iteration graph executables per plan
+constexpr int kBatchDefaultGroup = 8;  // tiles per queue item of a batch before autotuning
+constexpr int kBatchMaxGroup = 64;
 constexpr int kMinFft = 32, kMaxHot = 4096, kMaxGrid = 8192;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -1005,9 +1007,15 @@ tomo_status tomo_lanczos_prolong(const float* in, float* out, int32_t n, int32_t
 struct tomo_batch_s {
   std::vector<tomo_plan> plans;
   hipStream_t stream = nullptr;
-  int device = 0, grid = 0;
+  int device = 0, grid = 0, grid_fused = 0;
+  bool fused = false;          // 8-neighbour problems take the prior inside pass R'
   std::vector<BatchProb> probs;
   std::vector<int2> items;
+  std::vector<int> order;      // problems by decreasing FFT size (queue order within a phase)
+  std::vector<int> sizes;      // distinct FFT sizes, increasing
+  std::vector<int> size_el;    // elements per thread chosen for each size
+  std::vector<int> size_grp;   // tiles per queue item chosen for each size
+  size_t items_cap = 0;        // items the workspace holds (every size at 8 elements per thread)
   char* ws = nullptr;
   size_t need = 0, off_probs = 0, off_items = 0, off_ctl = 0, off_cnt = 0;
   hipStream_t gstream = nullptr;
@@ -1068,13 +1076,116 @@ tomo_status batch_prepare(tomo_batch bt, int j, const float* sino, int restart) 
   return s;
 }
 
+// Tile counts and the phase-ordered work list for the current per-size schedule.
+void batch_build_items(tomo_batch b) {
+  const int n = (int)b->plans.size();
+  for (int j = 0; j < n; ++j) {
+    BatchProb& d = b->probs[j];
+    const size_t si = std::lower_bound(b->sizes.begin(), b->sizes.end(), d.P) - b->sizes.begin();
+    d.el = b->size_el[si];
+    d.fused = b->fused && d.neighbours == 8 ? 1 : 0;
+    d.grp = b->size_grp[si];
+    batch_tile_counts(d.N, d.P, d.nz, d.el, &d.nPr, &d.nR, &d.nC, &d.nRp);
+    if (d.fused) d.nPr = 0;
+    d.iR = (d.nR + d.grp - 1) / d.grp;
+    d.iC = (d.nC + d.grp - 1) / d.grp;
+    d.iRp = (d.nRp + d.grp - 1) / d.grp;
+  }
+  b->items.clear();
+  for (int ph = 0; ph < 4; ++ph)
+    for (int j : b->order) {
+      const BatchProb& d = b->probs[j];
+      const int cntp = ph == 0 ? d.nPr : ph == 1 ? d.iR : ph == 2 ? d.iC : d.iRp;
+      for (int t = 0; t < cntp; ++t) b->items.push_back(make_int2(j | (ph << 24), t));
+    }
+}
+
+// Copy the work list and the problem descriptors (whose tile counts and element choice must
+// match the list) to the workspace; a captured graph holds the old item count.
+tomo_status batch_upload_items(tomo_batch b) {
+  if (b->items.size() > b->items_cap) return bfail(b, TOMO_ERR_INTERNAL, "work list exceeds its capacity");
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(int2),
+                            hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(), b->probs.size() * sizeof(BatchProb),
+                            hipMemcpyHostToDevice, b->stream));
+  // the host vectors are rebuilt by the next schedule change: finish the copies first
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  return TOMO_OK;
+}
+
+// Device pointers of every problem (its plan's workspace).
+void batch_fill_descriptors(tomo_batch b) {
+  for (size_t j = 0; j < b->plans.size(); ++j) {
+    tomo_plan p = b->plans[j];
+    const Level& l = p->lv[0];
+    BatchProb& d = b->probs[j];
+    for (int i = 0; i < 3; ++i) d.x[i] = p->xbuf(i);
+    d.y = p->at<float>(p->off_y);
+    d.gp = p->at<float>(p->off_gp);
+    d.b = p->at<float>(l.off_b);
+    d.fk = p->at<float>(l.off_fk);
+    d.fkn = p->at<float>(l.off_fkn);
+    d.S1 = p->S1();
+    d.S2 = p->S2(l);
+    d.partials = p->partials();
+    d.scal = p->scal();
+    d.tw = p->tw32(l.P);
+    d.hist = nullptr;
+    d.rhist = nullptr;
+    d.pp = p->pp;
+  }
+}
+
+tomo_status batch_launch(tomo_batch bt, int ik, int ikm1, int inext, hipStream_t st);
+
+// Mean time of one batched iteration over `reps` launches (after one warm-up) with the current
+// schedule, on state prepared by tomo_batch_autotune.
+tomo_status batch_time(tomo_batch b, int reps, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  hipStream_t st = b->stream;
+  const int n = (int)b->plans.size();
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_ctl), 4, 0, st));
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 4 * (idx_t)n, 0, st));
+  int ik = 0, ikm1 = 0, inext = 1;
+  for (int r = -1; r < reps; ++r) {
+    if (r == 0) BHIPCHK(b, hipEventRecord(e0, st));
+    if (tomo_status s = batch_launch(b, ik, ikm1, inext, st); s != TOMO_OK) return s;
+    ikm1 = ik;
+    ik = inext;
+    inext = 3 - ik - ikm1;
+  }
+  BHIPCHK(b, hipEventRecord(e1, st));
+  BHIPCHK(b, hipEventSynchronize(e1));
+  float t = 0.f;
+  BHIPCHK(b, hipEventElapsedTime(&t, e0, e1));
+  int ctl[4];
+  BHIPCHK(b, hipMemcpy(ctl, b->ws + b->off_ctl, sizeof ctl, hipMemcpyDeviceToHost));
+  if (ctl[2]) return bfail(b, TOMO_ERR_INTERNAL, "a tile wait timed out while timing");
+  *ms = t / (float)reps;
+  return TOMO_OK;
+}
+
+void batch_report(tomo_batch b, tomo_batch_schedule_t* out) {
+  std::memset(out, 0, sizeof *out);
+  out->n_sizes = (int32_t)b->sizes.size();
+  out->fused_prior = b->fused ? 1 : 0;
+  for (size_t i = 0; i < b->sizes.size() && i < TOMO_BATCH_MAX_SIZES; ++i) {
+    out->pad[i] = b->sizes[i];
+    out->elems[i] = b->size_el[i];
+    out->group[i] = b->size_grp[i];
+  }
+}
+
 tomo_status batch_launch(tomo_batch bt, int ik, int ikm1, int inext, hipStream_t st) {
   const int nprob = (int)bt->plans.size();
-  BHIPCHK(bt, launch_batch_iteration(reinterpret_cast<const BatchProb*>(bt->ws + bt->off_probs),
+  BHIPCHK(bt, launch_batch_iteration(bt->fused, reinterpret_cast<const BatchProb*>(bt->ws + bt->off_probs),
                                      reinterpret_cast<const int2*>(bt->ws + bt->off_items),
                                      (int)bt->items.size(), reinterpret_cast<int*>(bt->ws + bt->off_ctl),
                                      reinterpret_cast<int*>(bt->ws + bt->off_cnt), nprob, ik, ikm1,
-                                     inext, bt->grid, st));
+                                     inext, bt->fused ? bt->grid_fused : bt->grid, st));
   return TOMO_OK;
 }
 
@@ -1104,11 +1215,13 @@ tomo_status tomo_batch_create(const tomo_plan* plans, int32_t n, void* hip_strea
   b->plans.assign(plans, plans + n);
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->device = dev;
-  b->grid = prop.multiProcessorCount * 2;  // two resident 256-thread blocks per CU
-  // work list: all pass-R tiles, then pass C, then pass R'; larger transforms first
-  std::vector<int> order(n);
-  for (int j = 0; j < n; ++j) order[j] = j;
-  std::stable_sort(order.begin(), order.end(),
+  // every resident 256-thread block takes tiles until the queue is empty
+  b->grid = prop.multiProcessorCount * batch_blocks_per_cu(false);
+  b->grid_fused = prop.multiProcessorCount * batch_blocks_per_cu(true);
+  // work list: all prior tiles, then pass R, pass C and pass R'; larger transforms first
+  b->order.resize(n);
+  for (int j = 0; j < n; ++j) b->order[j] = j;
+  std::stable_sort(b->order.begin(), b->order.end(),
                    [&](int a, int c) { return plans[a]->lv[0].P > plans[c]->lv[0].P; });
   b->probs.resize(n);
   for (int j = 0; j < n; ++j) {
@@ -1119,14 +1232,18 @@ tomo_status tomo_batch_create(const tomo_plan* plans, int32_t n, void* hip_strea
     d.P = l.P;
     d.nz = plans[j]->nz;
     d.neighbours = plans[j]->g.neighbours;
-    batch_tile_counts(l.n, l.P, d.nz, &d.nR, &d.nC, &d.nRp);
+    b->sizes.push_back(l.P);
   }
-  for (int ph = 0; ph < 3; ++ph)
-    for (int j : order) {
-      const BatchProb& d = b->probs[j];
-      const int cntp = ph == 0 ? d.nR : ph == 1 ? d.nC : d.nRp;
-      for (int t = 0; t < cntp; ++t) b->items.push_back(make_int2(j | (ph << 24), t));
-    }
+  std::sort(b->sizes.begin(), b->sizes.end());
+  b->sizes.erase(std::unique(b->sizes.begin(), b->sizes.end()), b->sizes.end());
+  // capacity: 8 elements per thread and one tile per item give the most items
+  b->size_el.assign(b->sizes.size(), 8);
+  b->size_grp.assign(b->sizes.size(), 1);
+  batch_build_items(b);
+  b->items_cap = b->items.size();
+  b->size_el.assign(b->sizes.size(), 16);
+  b->size_grp.assign(b->sizes.size(), kBatchDefaultGroup);
+  batch_build_items(b);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -1134,9 +1251,9 @@ tomo_status tomo_batch_create(const tomo_plan* plans, int32_t n, void* hip_strea
     return o;
   };
   b->off_probs = take(n * sizeof(BatchProb));
-  b->off_items = take(b->items.size() * sizeof(int2));
+  b->off_items = take(b->items_cap * sizeof(int2));
   b->off_ctl = take(4 * sizeof(int));
-  b->off_cnt = take(3 * (size_t)n * sizeof(int));
+  b->off_cnt = take(4 * (size_t)n * sizeof(int));
   b->need = off;
   *out = b;
   return TOMO_OK;
@@ -1157,10 +1274,9 @@ tomo_status tomo_batch_set_workspace(tomo_batch b, void* dev, size_t bytes) {
     b->gexec = nullptr;
   }
   b->ws = static_cast<char*>(dev);
-  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(int2),
-                            hipMemcpyHostToDevice, b->stream));
+  if (tomo_status s = batch_upload_items(b); s != TOMO_OK) return s;
   BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_ctl), 4, 0, b->stream));
-  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 3 * (idx_t)b->plans.size(), 0,
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 4 * (idx_t)b->plans.size(), 0,
                              b->stream));
   BHIPCHK(b, hipStreamSynchronize(b->stream));
   return TOMO_OK;
@@ -1178,28 +1294,12 @@ tomo_status tomo_batch_reconstruct(tomo_batch b, const float* const* sinos, floa
   tomo_status s;
   for (int j = 0; j < n; ++j)
     if ((s = batch_prepare(b, j, sinos[j], restart)) != TOMO_OK) return s;
-  for (int j = 0; j < n; ++j) {
-    tomo_plan p = b->plans[j];
-    const Level& l = p->lv[0];
-    BatchProb& d = b->probs[j];
-    for (int i = 0; i < 3; ++i) d.x[i] = p->xbuf(i);
-    d.b = p->at<float>(l.off_b);
-    d.fk = p->at<float>(l.off_fk);
-    d.fkn = p->at<float>(l.off_fkn);
-    d.S1 = p->S1();
-    d.S2 = p->S2(l);
-    d.partials = p->partials();
-    d.scal = p->scal();
-    d.tw = p->tw32(l.P);
-    d.hist = nullptr;
-    d.rhist = nullptr;
-    d.pp = p->pp;
-  }
+  batch_fill_descriptors(b);
   hipStream_t st = b->stream;
   BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(), n * sizeof(BatchProb),
                             hipMemcpyHostToDevice, st));
   BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_ctl), 4, 0, st));
-  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 3 * (idx_t)n, 0, st));
+  BHIPCHK(b, launch_fill_int(reinterpret_cast<int*>(b->ws + b->off_cnt), 4 * (idx_t)n, 0, st));
   int ik = 0, ikm1 = 0, inext = 1, k = 0;
   while (k < iters) {
     if (k >= 1 && iters - k >= 3) {
@@ -1271,6 +1371,143 @@ tomo_status tomo_batch_reconstruct(tomo_batch b, const float* const* sinos, floa
     stats->wait_timeouts = ctl[2] != 0;
     if (stats->wait_timeouts) return bfail(b, TOMO_ERR_INTERNAL, "a batch tile gave up waiting");
     if (stats->n_nonfinite) return bfail(b, TOMO_ERR_NONFINITE, "%d problems went non-finite", stats->n_nonfinite);
+  }
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_schedule(tomo_batch b, const tomo_batch_schedule_t* set,
+                                tomo_batch_schedule_t* out) {
+  if (!b) return bfail(b, TOMO_ERR_INVALID_ARG, "batch is NULL");
+  if (set) {
+    // earlier asynchronous copies may still read the host descriptors rebuilt below
+    if (b->ws) BHIPCHK(b, hipStreamSynchronize(b->stream));
+    if (set->fused_prior != 0 && set->fused_prior != 1)
+      return bfail(b, TOMO_ERR_INVALID_ARG, "fused_prior must be 0 or 1");
+    std::vector<int> el = b->size_el, grp = b->size_grp;
+    for (int i = 0; i < set->n_sizes && i < TOMO_BATCH_MAX_SIZES; ++i) {
+      const auto it = std::find(b->sizes.begin(), b->sizes.end(), set->pad[i]);
+      if (it == b->sizes.end()) return bfail(b, TOMO_ERR_INVALID_ARG, "no problem with FFT size %d", set->pad[i]);
+      if (set->elems[i] != 8 && set->elems[i] != 16)
+        return bfail(b, TOMO_ERR_INVALID_ARG, "elements per thread must be 8 or 16");
+      if (set->group[i] < 1 || set->group[i] > kBatchMaxGroup)
+        return bfail(b, TOMO_ERR_INVALID_ARG, "tiles per item must be in 1..%d", kBatchMaxGroup);
+      el[it - b->sizes.begin()] = set->elems[i];
+      grp[it - b->sizes.begin()] = set->group[i];
+    }
+    b->size_el = el;
+    b->size_grp = grp;
+    b->fused = set->fused_prior == 1;
+    batch_build_items(b);
+    if (b->ws) {
+      BHIPCHK(b, hipSetDevice(b->device));
+      if (tomo_status s = batch_upload_items(b); s != TOMO_OK) return s;
+    }
+  }
+  if (out) batch_report(b, out);
+  return TOMO_OK;
+}
+
+tomo_status tomo_batch_autotune(tomo_batch b, int32_t reps, tomo_batch_schedule_t* out) {
+  if (!b) return bfail(b, TOMO_ERR_INVALID_ARG, "batch is NULL");
+  if (!b->ws) return bfail(b, TOMO_ERR_NO_WORKSPACE, "no workspace attached");
+  if (reps <= 0) reps = 5;
+  BHIPCHK(b, hipSetDevice(b->device));
+  hipStream_t st = b->stream;
+  BHIPCHK(b, hipStreamSynchronize(st));  // earlier copies may still read the host descriptors
+  // state to iterate on: tables and PSF of every problem, zero iterates, b and prior buffers
+  for (tomo_plan p : b->plans) {
+    hipStream_t keep = p->stream;
+    p->stream = st;
+    tomo_status s = ensure_tables(p);
+    if (s == TOMO_OK && !p->psf_ready) s = tomo_precompute_psf(p);
+    p->stream = keep;
+    if (s != TOMO_OK) return bfail(b, s, "autotune setup: %s", p->err.c_str());
+    const Level& l = p->lv[0];
+    const idx_t vol = (idx_t)p->nz * l.n * l.n;
+    float* bufs[6] = {p->xbuf(0), p->xbuf(1), p->xbuf(2), p->at<float>(p->off_y),
+                      p->at<float>(p->off_gp), p->at<float>(l.off_b)};
+    for (float* f : bufs) BHIPCHK(b, launch_fill(f, vol, 0.0f, st));
+    double* sc = p->scal();
+    BHIPCHK(b, launch_set_scalars(sc, 0, SC_COUNT, nullptr, 0.0, st));
+    BHIPCHK(b, launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st));
+    BHIPCHK(b, launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / l.L, st));
+    BHIPCHK(b, launch_set_scalars(sc, SC_NONFINITE, 1, nullptr, -1.0, st));
+  }
+  batch_fill_descriptors(b);
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_probs, b->probs.data(), b->plans.size() * sizeof(BatchProb),
+                            hipMemcpyHostToDevice, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIPCHK(b, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, TOMO_ERR_HIP, "hipEventCreate failed");
+  }
+  // coordinate descent: the prior scheme first (the pair-shared prior phase, or for
+  // 8-neighbour problems the prior inside pass R'), then one size at a time 8 instead of 16
+  // elements per thread, each change kept where the whole batched iteration gets at least 3%
+  // faster
+  tomo_status s = TOMO_OK;
+  float best = 0.f, base = 0.f;
+  b->size_el.assign(b->sizes.size(), 16);
+  b->size_grp.assign(b->sizes.size(), kBatchDefaultGroup);
+  b->fused = false;
+  batch_build_items(b);
+  s = batch_upload_items(b);
+  if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &best);
+  base = best;
+  bool any8 = false;
+  for (tomo_plan p : b->plans) any8 = any8 || p->g.neighbours == 8;
+  if (s == TOMO_OK && any8) {
+    b->fused = true;
+    batch_build_items(b);
+    float t = 0.f;
+    s = batch_upload_items(b);
+    if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &t);
+    if (s == TOMO_OK && t < 0.97f * best) best = t;
+    else b->fused = false;
+  }
+  // tiles per queue item: the same for every size first, then each size halved or doubled
+  auto try_groups = [&](const std::vector<int>& g) {
+    const std::vector<int> prev = b->size_grp;
+    b->size_grp = g;
+    batch_build_items(b);
+    float t = 0.f;
+    s = batch_upload_items(b);
+    if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &t);
+    if (s == TOMO_OK && t < 0.97f * best) best = t;
+    else b->size_grp = prev;
+  };
+  for (int g : {2, 8, 16, 32, 64})
+    if (s == TOMO_OK) try_groups(std::vector<int>(b->sizes.size(), g));
+  for (size_t i = 0; s == TOMO_OK && i < b->sizes.size(); ++i)
+    for (int f : {2, -2}) {
+      std::vector<int> g = b->size_grp;
+      g[i] = f > 0 ? g[i] * 2 : g[i] / 2;
+      if (s == TOMO_OK && g[i] >= 1 && g[i] <= kBatchMaxGroup) try_groups(g);
+    }
+  for (size_t i = 0; s == TOMO_OK && i < b->sizes.size(); ++i) {
+    b->size_el[i] = 8;
+    batch_build_items(b);
+    float t = 0.f;
+    s = batch_upload_items(b);
+    if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &t);
+    if (s == TOMO_OK && t < 0.97f * best) {
+      best = t;
+    } else {
+      b->size_el[i] = 16;
+    }
+  }
+  if (s == TOMO_OK) {
+    batch_build_items(b);
+    s = batch_upload_items(b);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != TOMO_OK) return s;
+  if (out) {
+    batch_report(b, out);
+    out->iter_ms = best;
+    out->base_ms = base;
   }
   return TOMO_OK;
 }

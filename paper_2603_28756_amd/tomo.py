@@ -82,6 +82,23 @@ class BatchStats(ctypes.Structure):
                 ("wait_timeouts", ctypes.c_int32)]
 
 
+BATCH_MAX_SIZES = 8
+
+
+class BatchSchedule(ctypes.Structure):
+    _fields_ = [("n_sizes", ctypes.c_int32), ("pad", ctypes.c_int32 * BATCH_MAX_SIZES),
+                ("elems", ctypes.c_int32 * BATCH_MAX_SIZES), ("group", ctypes.c_int32 * BATCH_MAX_SIZES),
+                ("fused_prior", ctypes.c_int32),
+                ("iter_ms", ctypes.c_float), ("base_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        k = self.n_sizes
+        return {"sizes": {int(self.pad[i]): int(self.elems[i]) for i in range(k)},
+                "group": {int(self.pad[i]): int(self.group[i]) for i in range(k)},
+                "fused_prior": bool(self.fused_prior),
+                "iter_ms": float(self.iter_ms), "base_ms": float(self.base_ms)}
+
+
 class Tiles(ctypes.Structure):
     _fields_ = [("rows_fwd", ctypes.c_int32), ("cols_conv", ctypes.c_int32), ("rows_inv", ctypes.c_int32),
                 ("fwd_pairs", ctypes.c_int32), ("col_tile", ctypes.c_int32), ("inv_pairs", ctypes.c_int32),
@@ -121,6 +138,9 @@ EXPORTS = {
     "tomo_batch_set_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
     "tomo_batch_reconstruct": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                 ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(BatchStats)], ctypes.c_int),
+    "tomo_batch_autotune": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(BatchSchedule)], ctypes.c_int),
+    "tomo_batch_schedule": ([ctypes.c_void_p, ctypes.POINTER(BatchSchedule), ctypes.POINTER(BatchSchedule)],
+                            ctypes.c_int),
     "tomo_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "tomo_unet_create": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -381,6 +401,28 @@ class Batch:
         _check(self._lib.tomo_batch_reconstruct(self._h, sp, xp, int(iters), int(restart), ctypes.byref(st)))
         return {"n_nonfinite": st.n_nonfinite, "n_restarts": st.n_restarts,
                 "wait_timeouts": st.wait_timeouts}
+
+    def autotune(self, reps: int = 5) -> dict:
+        out = BatchSchedule()
+        _check(self._lib.tomo_batch_autotune(self._h, int(reps), ctypes.byref(out)))
+        return out.as_dict()
+
+    def schedule(self, set_to: Optional[dict] = None, fused_prior: bool = False,
+                 group: Optional[dict] = None) -> dict:
+        """Read (and with set_to = {pad: elems} first set, with the prior scheme and the tiles
+        per item {pad: group}, default 8) the schedule."""
+        st = None
+        if set_to is not None:
+            st = BatchSchedule()
+            st.fused_prior = int(fused_prior)
+            st.n_sizes = len(set_to)
+            for i, (p, e) in enumerate(sorted(set_to.items())):
+                st.pad[i], st.elems[i] = int(p), int(e)
+                st.group[i] = int((group or {}).get(p, 8))
+        out = BatchSchedule()
+        _check(self._lib.tomo_batch_schedule(self._h, ctypes.byref(st) if st is not None else None,
+                                             ctypes.byref(out)))
+        return out.as_dict()
 
     def close(self):
         if getattr(self, "_h", None):

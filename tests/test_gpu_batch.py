@@ -2,9 +2,10 @@
 iteration over the pass tiles of every problem) against the same problems run one plan at a
 time, and a small subset against the FP64 oracle.
 
-The batched kernel groups rows and columns into tiles differently from the per-plan kernels,
-which changes only the order of the float64 partial sums, so batched and per-plan results
-agree to ~1e-7 (not bit for bit); parity with the oracle is <= 1e-4 after 20 iterations.
+The batched kernel groups rows, columns and prior tiles differently from the per-plan kernels
+(and may run a transform size with radix-8 instead of radix-16 stages), which changes only the
+rounding order, so batched and per-plan results agree to ~1e-7 (not bit for bit); parity with
+the oracle is <= 1e-4 after 20 iterations.
 """
 import numpy as np
 import pytest
@@ -59,6 +60,60 @@ def test_batch_matches_single_plans_and_oracle():
         prob = solver.build(geom, sino, oracle_prior(8), 0.01)
         ref = solver.fista(prob, ofbp.fbp(sino, geom), iters)
         assert rel_l2(got[k], ref.x) < 1e-4
+
+
+def test_batch_schedules_and_autotune():
+    """Every per-size schedule (8 or 16 elements per thread) computes the same iteration; the
+    autotuner's choice is one of them and is kept for the next reconstruction."""
+    from paper_2603_28756_amd import tomo
+    iters = 20
+    items = _setup()
+    plans = [make_plan(n, 1, ang, nd, neighbours=8) for n, na, nd, sino, ang in items]
+    pads = sorted({p.level_dims(0)[2] for p in plans})
+    batch = tomo.Batch(plans)
+    sinos = [to_dev(it[3]) for it in items]
+    outs = {}
+    for el, fused in ((16, False), (8, False), (16, True), (8, True)):
+        sch = batch.schedule({p: el for p in pads}, fused_prior=fused)
+        assert sch["sizes"] == {p: el for p in pads} and sch["fused_prior"] == fused
+        xs = [torch.empty((1, it[0], it[0]), dtype=torch.float32, device=dev()) for it in items]
+        st = batch.reconstruct(sinos, xs, iters)
+        assert st["wait_timeouts"] == 0 and st["n_nonfinite"] == 0
+        outs[el, fused] = [to_np(x) for x in xs]
+    # radix-8 and radix-16 stages round differently (~1e-7 per transform), and so do the two
+    # prior schemes (pair sums in another order); over 20 iterations the iterate sequences
+    # drift apart by ~1e-6, far inside the oracle bound
+    for key in ((8, False), (16, True), (8, True)):
+        for a, b in zip(outs[16, False], outs[key]):
+            assert rel_l2(b, a) < 1e-5
+    # tiles per queue item change only which block transforms a tile: bit-identical results
+    for grp in (1, 64):
+        sch = batch.schedule({p: 16 for p in pads}, fused_prior=True, group={p: grp for p in pads})
+        assert sch["group"] == {p: grp for p in pads}
+        xs = [torch.empty((1, it[0], it[0]), dtype=torch.float32, device=dev()) for it in items]
+        assert batch.reconstruct(sinos, xs, iters)["wait_timeouts"] == 0
+        for x, a in zip(xs, outs[16, True]):
+            assert np.array_equal(to_np(x), a)
+    mixed = {p: (8 if i % 2 else 16) for i, p in enumerate(pads)}
+    assert batch.schedule(mixed, group={p: 1 + i for i, p in enumerate(pads)})["sizes"] == mixed
+    tuned = batch.autotune(reps=3)
+    assert set(tuned["sizes"]) == set(pads) and set(tuned["sizes"].values()) <= {8, 16}
+    assert tuned["iter_ms"] > 0 and tuned["iter_ms"] <= tuned["base_ms"] * 1.0001
+    assert batch.schedule()["sizes"] == tuned["sizes"]
+    xs = [torch.empty((1, it[0], it[0]), dtype=torch.float32, device=dev()) for it in items]
+    st = batch.reconstruct(sinos, xs, iters)
+    assert st["wait_timeouts"] == 0
+    for x, a in zip(xs, outs[16, False]):
+        assert rel_l2(to_np(x), a) < 1e-5
+    n, na, nd, sino, ang = items[1]
+    geom = oracle_geom(n, ang, nd)
+    prob = solver.build(geom, sino, oracle_prior(8), 0.01)
+    ref = solver.fista(prob, ofbp.fbp(sino, geom), iters)
+    assert rel_l2(to_np(xs[1]), ref.x) < 1e-4
+    with pytest.raises(tomo.TomoError):
+        batch.schedule({128: 8})  # no problem of that FFT size
+    with pytest.raises(tomo.TomoError):
+        batch.schedule({pads[0]: 4})
 
 
 def test_batch_rejects_unsupported_sizes():
