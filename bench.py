@@ -380,6 +380,80 @@ def run_learned(args) -> int:
     return 0
 
 
+def run_direct(args) -> int:
+    """Toeplitz gradient (passes R, C, R', prior, finalize; PSF precomputed once) against the
+    direct gradient R*(R x - g) + beta grad Phi (both non-uniform transforms every call) over
+    image widths: median launch-to-finish time of each on the same inputs, and their relative
+    difference.  One JSON line."""
+    import numpy as np
+    import synth
+    import torch
+    from paper_2603_28756_amd import tomo
+    dev = torch.device("cuda", 0)
+    nz, na, reps = 8, 180, 10
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def med_ms(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            ev0.record()
+            fn()
+            ev1.record()
+            torch.cuda.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        return float(np.median(ts))
+
+    cases = []
+    for n in (128, 256, 512, 1024, 2048):
+        nd = synth.detector_bins_for(n)
+        pr = synth.make_problem(n, nz, na, nd, 0.01, 40 + n, 20)
+        sino = torch.from_numpy(pr["sino"].astype(np.float32)).to(dev)
+        rng = np.random.default_rng(n)
+        x = torch.from_numpy((pr["phantom"] + 0.05 * rng.standard_normal(pr["phantom"].shape))
+                             .astype(np.float32)).to(dev)
+        plan = tomo.Plan(n, nz, na, nd, angles=list(pr["angles"]), kb_width=6, neighbours=26, device=dev)
+        plan.precompute_psf()
+        b = torch.empty_like(x)
+        plan.backproject(sino, b, ramp=False)
+        g_t, g_d, tx = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+        o_t = torch.zeros(1, dtype=torch.float64, device=dev)
+        o_d = torch.zeros(1, dtype=torch.float64, device=dev)
+        t_toe = med_ms(lambda: plan.gradient(x, b, g_t, o_t))
+        t_dir = med_ms(lambda: plan.gradient_direct(x, sino, g_d, o_d))
+        plan.apply_normal(x, tx)
+        torch.cuda.synchronize()
+        gt, gd = g_t.double(), g_d.double()
+        d_terms = float(torch.linalg.norm(gd - gt) / (torch.linalg.norm(tx.double()) + torch.linalg.norm(b.double())))
+        d_grad = float(torch.linalg.norm(gd - gt) / torch.linalg.norm(gt))
+        half_gg = 0.5 * float(torch.sum(sino.double() ** 2))
+        d_loss = abs(float(o_d.item()) - float(o_t.item()) - half_gg) / half_gg
+        cases.append({"n": n, "n_det": nd, "toeplitz_ms": t_toe, "direct_ms": t_dir,
+                      "speedup": t_dir / t_toe, "grad_rel_diff_of_terms": d_terms,
+                      "grad_rel_diff": d_grad, "loss_rel_diff_of_F0": d_loss})
+        print(f"N {n}: Toeplitz {t_toe:.3f} ms, direct {t_dir:.3f} ms, gradient difference {d_terms:.2e} "
+              f"of the terms ({d_grad:.2e} of the gradient), loss {d_loss:.2e}", file=sys.stderr, flush=True)
+        del plan, x, b, g_t, g_d, tx, sino
+        torch.cuda.empty_cache()
+    big = cases[-1]
+    out = {
+        "metric": "gradient time, Toeplitz vs direct (two non-uniform transforms)",
+        "value": big["direct_ms"] / big["toeplitz_ms"], "unit": "x (direct / Toeplitz time at 2048^2)",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": big["toeplitz_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "direct_vs_toeplitz", "slices": nz, "n_angles": na, "kb_width": 6,
+                   "oversampling": 2, "neighbours": 26, "widths": [c["n"] for c in cases],
+                   "toeplitz": "PSF spectrum precomputed once, not timed; one gradient = passes R, C, R', "
+                               "prior, float64 objective",
+                   "direct": "forward projection (deapodise, grid FFT, KB interpolation, radial inverse DFT), "
+                             "residual, back-projection (radial DFT, KB gridding, grid IFFT, crop), prior, "
+                             "float64 objective"},
+        "cases": cases,
+    }
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,6 +492,8 @@ def main() -> int:
         return run_learned(args)
     if args.workload == "batch_256":
         return run_batch(args)
+    if args.workload == "direct_vs_toeplitz":
+        return run_direct(args)
 
     import numpy as np
     import torch

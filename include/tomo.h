@@ -201,6 +201,26 @@ tomo_status tomo_apply_normal(tomo_plan plan, const float* x, float* out);
 tomo_status tomo_gradient(tomo_plan plan, const float* x, const float* b, float* grad,
                           double* obj_dev);
 
+/* sino_out = R x (Sec. 2, Eq. 3: R f = F^-1 NUFFT2 f) on the finest grid, the direct forward
+ * projection: the image is deapodised and embedded in the oversampled Kaiser-Bessel grid, the
+ * grid is forward-FFT'd, interpolated at the polar samples k_il = (l / n_det)(cos, sin)(theta_i)
+ * (the transpose of the back-projection's gridding), and each angle's radial spectrum is
+ * inverse-transformed along the detector, keeping the real part.  R and tomo_backproject's R*
+ * are adjoint up to float32 rounding.  Needs no PSF.
+ * x: device [n_slices][N][N]; sino_out: device [n_slices][n_angles][n_det].
+ * Errors: INVALID_ARG, NO_WORKSPACE, HIP. */
+tomo_status tomo_forward_project(tomo_plan plan, const float* x, float* sino_out);
+
+/* grad = R*(R x - g) + beta grad Phi(x) on the finest grid, evaluated directly with both
+ * non-uniform transforms (Sec. 2, Eqs. 3-4 and 7) instead of the Toeplitz product of Sec. 2.1,
+ * for comparison with tomo_gradient (which needs b = R* g and the PSF).
+ * x, grad: device [n_slices][N][N] (grad must not alias x); sino: device
+ * [n_slices][n_angles][n_det].  obj_dev: nullable device float64[1] receiving
+ * 1/2 ||R x - g||^2 + beta Phi(x) (Eq. 5).
+ * Errors: INVALID_ARG, NO_WORKSPACE, HIP. */
+tomo_status tomo_gradient_direct(tomo_plan plan, const float* x, const float* sino, float* grad,
+                                 double* obj_dev);
+
 /* Full reconstruction of `sino` into `x` through the grid hierarchy: per level
  * (coarse to fine) the projections are subsampled (every s-th bin, divided by
  * s), b = R* g is formed, the start is FBP / zero / the caller's image / the

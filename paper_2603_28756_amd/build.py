@@ -14,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libtomo.so")
 SOURCES = ["toeplitz_kernels.hip", "gridding_kernels.hip", "unet_kernels.hip", "start_kernels.hip",
+           "direct_kernels.hip",
            "tomo_api.cpp", "unet_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.

@@ -133,6 +133,24 @@ hipError_t launch_select_start(const double* pa, const double* pb, int nz, int p
                                float* xa, const float* xb, int N, int32_t* choice,
                                int32_t* choice_user, hipStream_t st);
 
+// ---- direct (non-Toeplitz) forward projection ----------------------------------------------
+// grid[z][cell], slices z0 .. z0+nzb-1: deapodised image embedded at offset -N/2 (mod M).
+hipError_t launch_embed_deapod(const float* f, cpx<float>* grid, const float* inv, int N, int M,
+                               int z0, int nzb, hipStream_t st);
+// fhat[z][p] = KB interpolation of the forward-FFT'd grid at sample p (transpose of the gather).
+hipError_t launch_interp(const cpx<float>* grid, const int2* g0, const float* wx, const float* wy,
+                         cpx<float>* fhat, int npts, int M, int W, int z0, int nzb, hipStream_t st);
+// out[row][j] = Re (1/nd) sum_l fhat[row][l] exp(+2 pi i l (j - c)/nd) (- sino[row][j] when given,
+// then part[blocks] = partial sums of out^2).
+int radial_idft_blocks(int nd, int rows);
+hipError_t launch_radial_idft(const cpx<float>* fhat, const float* sino, float* out, double* part,
+                              int nd, int rows, const cpx<float>* tab, const cpx<float>* post,
+                              hipStream_t st);
+hipError_t launch_add(float* a, const float* b, idx_t n, hipStream_t st);
+// out[0] = 1/2 sum rpart + beta sum_k ppart[k][0]
+hipError_t launch_direct_objective(const double* rpart, int nr, const double* ppart, int np,
+                                   double beta, double* out, hipStream_t st);
+
 // ---- tables and utilities ---------------------------------------------------------------
 hipError_t launch_twiddles_f32(cpx<float>* tw, int P, hipStream_t st);
 hipError_t launch_twiddles_f64(cpx<double>* tw, int P, hipStream_t st);

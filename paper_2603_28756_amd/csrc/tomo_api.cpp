@@ -79,6 +79,7 @@ struct tomo_plan_s {
   size_t off_gp = 0, off_ppartials = 0, off_y = 0;
   size_t off_cnt = 0, off_scan = 0, off_rampf = 0;
   size_t off_objpart = 0, off_choice = 0;  // learned start: objective partials, choice
+  size_t off_resid = 0, off_rpart = 0;      // direct gradient: residual sinogram, its partials
   bool fused_prior = false, grids_ready = false;
   bool tables_ready = false, psf_ready = false;
   std::string err;
@@ -192,6 +193,8 @@ void layout(tomo_plan p) {
   for (const Level& l : p->lv) maxprior = std::max(maxprior, (size_t)prior_blocks(l.n, p->nz));
   p->off_ppartials = take(maxprior * 4 * sizeof(double));
   p->off_objpart = take(2 * (size_t)p->nz * kObjBlocks * sizeof(double));
+  p->off_resid = take((size_t)p->nz * na * fin.nd * sizeof(float));
+  p->off_rpart = take((size_t)radial_idft_blocks(fin.nd, p->nz * na) * sizeof(double));
   p->off_choice = take((size_t)p->nz * sizeof(int32_t));
   const size_t npts_max = (size_t)na * (fin.nd - 1);
   p->off_ghat = take((size_t)p->nz * npts_max * sizeof(cpx<float>));
@@ -615,6 +618,40 @@ tomo_status learned_start(tomo_plan p, const Level& l, const float* b, int cur, 
   return TOMO_OK;
 }
 
+// out = R x on the finest level (Sec. 2, Eq. 3); with sino, out = R x - sino and the partial
+// sums of its squares go to rpart.  The radial spectra reuse the back-projection's sample
+// buffer ([slice][sample] here) and the grids its scratch.
+tomo_status forward_project_impl(tomo_plan p, const float* x, float* out, const float* sino,
+                                 double* rpart) {
+  hipStream_t st = p->stream;
+  tomo_status s = ensure_tables(p);
+  if (s == TOMO_OK) s = ensure_grids(p);
+  if (s != TOMO_OK) return s;
+  const Level& l = p->lv.back();
+  const GridGeom gg = bp_geom(p, l);
+  int2* g0 = p->at<int2>(p->off_g0);
+  float* wx = p->at<float>(p->off_wx);
+  float* wy = p->at<float>(p->off_wy);
+  cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
+  cpx<float>* post = p->at<cpx<float>>(p->off_post);
+  HIPCHK(p, launch_point_table<float>(p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+  HIPCHK(p, launch_radial_tables(tab, post, p->at<float>(p->off_rampf), gg, 0, st));
+  cpx<float>* fhat = p->at<cpx<float>>(p->off_ghat);
+  const int npts = p->g.n_angles * (l.nd - 1);
+  const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
+  const int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / slice_grid);
+  if (chunk < 1) return fail(p, TOMO_ERR_INTERNAL, "scratch too small for one grid slice");
+  cpx<float>* grid = p->at<cpx<float>>(p->off_scratch);
+  for (int z0 = 0; z0 < p->nz; z0 += chunk) {
+    const int zc = std::min(chunk, p->nz - z0);
+    HIPCHK(p, launch_embed_deapod(x, grid, p->at<float>(l.off_deapod), l.n, l.M, z0, zc, st));
+    HIPCHK(p, launch_fft2d_f32(grid, l.M, zc, -1, p->tw32(l.M), st));
+    HIPCHK(p, launch_interp(grid, g0, wx, wy, fhat, npts, l.M, p->g.kb_width, z0, zc, st));
+  }
+  HIPCHK(p, launch_radial_idft(fhat, sino, out, rpart, l.nd, p->nz * p->g.n_angles, tab, post, st));
+  return TOMO_OK;
+}
+
 tomo_status validate_geom(const tomo_geometry_t* g) {
   if (!g) return fail(nullptr, TOMO_ERR_INVALID_ARG, "geometry is NULL");
   if (g->n < 16 || g->n > 2048 || (g->n & 1))
@@ -844,6 +881,41 @@ tomo_status tomo_gradient(tomo_plan p, const float* x, const float* b, float* gr
     return s;
   HIPCHK(p, launch_finalize(MODE_GRAD, p->partials(), nb, p->at<double>(p->off_ppartials), npr,
                             p->scal(), nullptr, nullptr, obj_dev, p->stream));
+  return TOMO_OK;
+}
+
+tomo_status tomo_forward_project(tomo_plan p, const float* x, float* sino_out) {
+  if (!p || !x || !sino_out) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(x) || !aligned(sino_out)) return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  HIPCHK(p, hipSetDevice(p->device));
+  return forward_project_impl(p, x, sino_out, nullptr, nullptr);
+}
+
+tomo_status tomo_gradient_direct(tomo_plan p, const float* x, const float* sino, float* grad,
+                                 double* obj_dev) {
+  if (!p || !x || !sino || !grad) return fail(p, TOMO_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(x) || !aligned(sino) || !aligned(grad))
+    return fail(p, TOMO_ERR_INVALID_ARG, "arrays must be 256-byte aligned");
+  if (grad == x) return fail(p, TOMO_ERR_INVALID_ARG, "grad must not alias x");
+  tomo_status s = check_ws(p);
+  if (s != TOMO_OK) return s;
+  HIPCHK(p, hipSetDevice(p->device));
+  hipStream_t st = p->stream;
+  const Level& l = p->lv.back();
+  float* resid = p->at<float>(p->off_resid);
+  double* rpart = p->at<double>(p->off_rpart);
+  if ((s = forward_project_impl(p, x, resid, sino, rpart)) != TOMO_OK) return s;
+  if ((s = backproject_level(p, l, resid, grad, 0)) != TOMO_OK) return s;
+  float* gp = p->at<float>(p->off_gp);
+  double* pp = p->at<double>(p->off_ppartials);
+  HIPCHK(p, launch_prior(MODE_GRAD, p->g.neighbours, obj_dev != nullptr, x, x, p->scal(), gp, nullptr,
+                         nullptr, pp, l.n, p->nz, p->pp, st));
+  HIPCHK(p, launch_add(grad, gp, (idx_t)p->nz * l.n * l.n, st));
+  if (obj_dev)
+    HIPCHK(p, launch_direct_objective(rpart, radial_idft_blocks(l.nd, p->nz * p->g.n_angles), pp,
+                                      prior_blocks(l.n, p->nz), p->g.beta, obj_dev, st));
   return TOMO_OK;
 }
 

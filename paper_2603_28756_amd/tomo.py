@@ -118,6 +118,9 @@ EXPORTS = {
     "tomo_backproject": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "tomo_apply_normal": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "tomo_gradient": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_forward_project": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "tomo_gradient_direct": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                             ctypes.c_int),
     "tomo_reconstruct": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ReconOpts),
                           ctypes.POINTER(ReconStats)], ctypes.c_int),
     "tomo_psf_info": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -287,6 +290,14 @@ class Plan:
     def gradient(self, x: torch.Tensor, b: torch.Tensor, grad: torch.Tensor,
                  obj: Optional[torch.Tensor] = None):
         _check(self._lib.tomo_gradient(self._h, _ptr(x), _ptr(b), _ptr(grad), _ptr(obj)), self._h)
+
+    def forward_project(self, x: torch.Tensor, out: torch.Tensor):
+        _check(self._lib.tomo_forward_project(self._h, _ptr(x), _ptr(out)), self._h)
+
+    def gradient_direct(self, x: torch.Tensor, sino: torch.Tensor, grad: torch.Tensor,
+                        obj: Optional[torch.Tensor] = None):
+        _check(self._lib.tomo_gradient_direct(self._h, _ptr(x), _ptr(sino), _ptr(grad), _ptr(obj)),
+               self._h)
 
     def reconstruct(self, sino: torch.Tensor, x: torch.Tensor, iters: Sequence[int],
                     init: int = INIT_FBP, restart: bool = True, L_override: float = 0.0,
