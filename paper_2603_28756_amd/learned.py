@@ -176,7 +176,8 @@ def compare_starts(pr: Problem, sinos: np.ndarray, net: "tomo.UNet", scale: floa
 
     h_fbp, _ = run(tomo.INIT_FBP)
     h_net, st_net = run(tomo.INIT_LEARNED, **learned_kw)
-    fstar = float(min(h_fbp.min(), h_net.min()))
+    h_zero, _ = run(tomo.INIT_ZERO)
+    fstar = float(min(h_fbp.min(), h_net.min(), h_zero.min()))
     tail = abs(h_fbp[-1] - h_fbp[-long_iters // 4]) / abs(fstar)
     k_fbp = iterations_to_gap(h_fbp, f0, fstar, tol)
     k_net = iterations_to_gap(h_net, f0, fstar, tol)
@@ -197,14 +198,19 @@ def compare_starts(pr: Problem, sinos: np.ndarray, net: "tomo.UNet", scale: floa
     def total(init, kk):
         return init + (kk if kk is not None else np.nan) * it_ms
     t_fbp, t_net = total(fbp_ms, k_fbp), total(learned_ms, k_net)
+    k_zero = iterations_to_gap(h_zero, f0, fstar, tol)
+    zero_ms = init_ms(tomo.INIT_ZERO)
     return {
         "slices": k, "tol": tol, "F0": f0, "F_star": fstar, "F_star_tail_change": tail,
-        "gap_at_start": {"fbp": (h_fbp[0] - fstar) / (f0 - fstar), "unet": (h_net[0] - fstar) / (f0 - fstar)},
-        "iterations": {"fbp": k_fbp, "unet": k_net},
-        "iterations_rel_fstar": {"fbp": k_fbp_abs, "unet": k_net_abs},
+        "gap_at_start": {"fbp": (h_fbp[0] - fstar) / (f0 - fstar), "unet": (h_net[0] - fstar) / (f0 - fstar),
+                         "constant": (h_zero[0] - fstar) / (f0 - fstar)},
+        "iterations": {"fbp": k_fbp, "unet": k_net, "constant": k_zero},
+        "iterations_rel_fstar": {"fbp": k_fbp_abs, "unet": k_net_abs,
+                                 "constant": iterations_to_gap(h_zero, fstar + abs(fstar), fstar, tol)},
         "learned_slices": st_net["learned_slices"], "learned_state": st_net["learned_state"],
         "fallback_to_fbp": st_net["learned_slices"] < k,
-        "ms": {"fbp_start": fbp_ms, "learned_start": learned_ms, "iteration": it_ms,
+        "ms": {"fbp_start": fbp_ms, "learned_start": learned_ms, "constant_start": zero_ms,
+               "total_constant": total(zero_ms, k_zero), "iteration": it_ms,
                "total_fbp": t_fbp, "total_unet": t_net,
                "total_fbp_rel_fstar": total(fbp_ms, k_fbp_abs),
                "total_unet_rel_fstar": total(learned_ms, k_net_abs)},
