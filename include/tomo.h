@@ -394,8 +394,9 @@ tomo_status tomo_batch_destroy(tomo_batch batch);  /* NULL ok */
 /* Destroy a plan (NULL is accepted).  Does not free the caller's workspace. */
 tomo_status tomo_plan_destroy(tomo_plan plan);
 
-/* Static description of a status code. */
-const char* tomo_status_string(tomo_status s);
+/* Static description of a status code: any int is accepted (a tomo_status value, or
+ * "unknown status" for other values). */
+const char* tomo_status_string(int32_t status);
 
 /* Message of the plan's last failure ("" if none; NULL plan -> last global error). */
 const char* tomo_last_error(tomo_plan plan);

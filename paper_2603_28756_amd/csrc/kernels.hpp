@@ -116,8 +116,8 @@ struct ObjParams {
   double beta;        // prior weight
   double p;           // exponent p
   double qmp;         // q - p
-  double inv_Tsigma;  // 1 / (T sigma)
-  double c_rho;       // 1 / (p sigma^p)
+  double lw0;         // (q - p) log2(1 / (T sigma))
+  double c_rho2;      // 1 / (p sigma^p (T sigma)^(2 - p))
   double w1, w2, w3;  // normalised neighbour weights: axis, face diagonal, body diagonal
   int neighbours;     // 8 or 26
   int quadratic;      // 1 when p == q

@@ -14,12 +14,19 @@ namespace {
 
 constexpr int SO_NT = 256;
 
-// rho(d) = |d|^p / (p sigma^p) * w / (1 + w),  w = (|d| / (T sigma))^(q - p)  (float64).
+// rho(d) = |d|^p / (p sigma^p) * w / (1 + w),  w = (|d| / (T sigma))^(q - p); for q = 2 this is
+// c d^2 / (1 + w) with c = 1 / (p sigma^p (T sigma)^(2 - p)).  d, d^2 and the sums are float64; w
+// comes from the hardware exp2/log2 in float32 (relative error ~1e-7 in each term, as in the
+// iteration's own objective).
 TOMO_DEV double rho64(double d, const ObjParams& op) {
-  const double a = fabs(d);
-  if (a == 0.0) return 0.0;
-  const double w = op.quadratic ? 1.0 : pow(a * op.inv_Tsigma, op.qmp);
-  return op.c_rho * pow(a, op.p) * (w / (1.0 + w));
+  if (d == 0.0) return 0.0;
+  double r = 0.5;
+  if (!op.quadratic) {
+    const float w = __builtin_amdgcn_exp2f(
+        __builtin_fmaf((float)op.qmp, __builtin_amdgcn_logf((float)fabs(d)), (float)op.lw0));
+    r = 1.0 / (1.0 + (double)w);
+  }
+  return op.c_rho2 * d * d * r;
 }
 
 TOMO_DEV double block_sum(double v, double* sh) {

@@ -790,8 +790,8 @@ tomo_status tomo_plan_create(const tomo_geometry_t* geom, void* hip_stream, tomo
   op.beta = geom->beta;
   op.p = pe;
   op.qmp = q - pe;
-  op.inv_Tsigma = 1.0 / (T * sg);
-  op.c_rho = 1.0 / (pe * std::pow(sg, pe));
+  op.lw0 = (q - pe) * std::log2(1.0 / (T * sg));
+  op.c_rho2 = 1.0 / (pe * std::pow(sg, pe) * std::pow(T * sg, 2.0 - pe));
   op.w1 = r1 / sum;
   op.w2 = r2 / sum;
   op.w3 = r3 / sum;
@@ -1771,7 +1771,7 @@ tomo_status tomo_plan_destroy(tomo_plan p) {
   return TOMO_OK;
 }
 
-const char* tomo_status_string(tomo_status s) {
+const char* tomo_status_string(int32_t s) {
   switch (s) {
     case TOMO_OK: return "ok";
     case TOMO_ERR_INVALID_ARG: return "invalid argument";
