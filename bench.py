@@ -697,7 +697,7 @@ def main() -> int:
             "n_det": wl.n_det, "iterations": iters, "pad": P, "kb_width": wl.kb_width,
             "kb_oversamp": wl.kb_oversamp, "neighbours": wl.neighbours, "noise": wl.noise,
             "step": "PSF spectrum + step constant precompute, R*g, FBP start, iterations",
-            "tiles": ([{k: t[k] for k in ("fwd_pairs", "col_tile", "inv_pairs")} for t in tiles]
+            "tiles": ([{k: t[k] for k in ("fwd_pairs", "col_tile", "inv_pairs", "chunks")} for t in tiles]
                       if tiles else "default"),
             "prior": ("fused epilogue" if args.fused_prior else
                       "pair-shared kernel, " + ("own stream beside the row/column passes"

@@ -309,20 +309,28 @@ typedef struct {
   int32_t inv_pairs;      /* out: row pairs per workgroup of pass R'                       */
   float ms[3][3];         /* out (tomo_autotune): mean launch time [pass R, C, R'][variant]
                              in milliseconds on the plan's full volume                     */
+  int32_t chunks;         /* slices are split into this many chunks (1, 2, 4; 0 -> 1) that
+                             passes R, C, R' run through one after the other, reusing one
+                             chunk's half-spectrum buffers (which then stay in the Infinity
+                             Cache); not with the fused or concurrent prior                 */
+  float ms_chunks[3];     /* out (tomo_autotune): time of the prior kernel and the three
+                             passes with 1, 2, 4 chunks (0 where not tried)                 */
 } tomo_tiles_t;
 
 /* Time every variant of the three passes on each level at the plan's own shapes (reps
  * launches each, after one warm-up; reps <= 0 means 5) and keep the fastest per pass and
- * level (a variant replaces the default only when at least 3% faster).  Synchronises the plan's stream; overwrites the iterate and spectrum scratch of the
+ * level (a variant replaces the default only when at least 3% faster); then, with those tiles,
+ * time a whole step (prior kernel and the three passes) with 1, 2 and 4 slice chunks and keep
+ * the fastest by the same rule.  Synchronises the plan's stream; overwrites the iterate and spectrum scratch of the
  * workspace (not b, the PSF spectrum or the step constants), so call it before
  * tomo_reconstruct or between reconstructions.  Captured iteration graphs are rebuilt on the
  * next reconstruction.  chosen: nullable host [n_levels], receives the choice and timings.
  * Errors: INVALID_ARG, NO_WORKSPACE, HIP. */
 tomo_status tomo_autotune(tomo_plan plan, int32_t reps, tomo_tiles_t* chosen);
 
-/* Set (tiles != NULL: host [n_levels], only the three variant fields are read) and/or read
- * back (out != NULL: host [n_levels], variant and shape fields written, ms zero) the tile
- * schedule.  Errors: INVALID_ARG (variant outside 0..2). */
+/* Set (tiles != NULL: host [n_levels], only the three variant fields and chunks are read)
+ * and/or read back (out != NULL: host [n_levels], variant, shape and chunk fields written, ms
+ * zero) the tile schedule.  Errors: INVALID_ARG (variant outside 0..2, chunks not 0, 1, 2, 4). */
 tomo_status tomo_tiles(tomo_plan plan, const tomo_tiles_t* tiles, tomo_tiles_t* out);
 
 /* ---- batches of independent problems ------------------------------------------------- */

@@ -51,6 +51,7 @@ struct Level {
   size_t off_fk = 0, off_fkn = 0, off_b = 0;
   size_t off_rowptr = 0, off_cidx = 0, off_cw = 0, off_deapod = 0;  // gridding lists
   int v_fwd = 1, v_cc = 1, v_inv = 1;  // tile variants of passes R, C, R'
+  int chunks = 1;  // slice chunks that passes R, C, R' run through one after the other
 };
 
 }  // namespace
@@ -413,29 +414,49 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
   }
   // per-class timing covers the iteration and gradient launches, not the power iteration
   const bool timed = mode != MODE_POWER;
-  int ti = timed ? tbegin(p, TOMO_T_ROWS_FWD) : -1;
-  if (yg)
-    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, MODE_FISTA_Y, ybuf, ybuf, p->scal(), S1, p->tw32(l.P),
-                              l.n, nz, st));
-  else
-    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, mode, xk, xkm1, p->scal(), S1, p->tw32(l.P), l.n, nz,
-                              st));
-  tend(p, ti);
-  ti = timed ? tbegin(p, TOMO_T_COLS_CONV) : -1;
-  HIPCHK(p, launch_cols_conv(l.P, l.v_cc, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
-                             p->tw32(l.P), l.n, nz, st));
-  tend(p, ti);
-  if (conc) HIPCHK(p, hipStreamWaitEvent(st, p->pev_join, 0));
-  ti = timed ? tbegin(p, TOMO_T_ROWS_INV) : -1;
-  if (yg)
-    HIPCHK(p, launch_rows_inv(l.P, l.v_inv, MODE_FISTA_Y, p->g.neighbours, obj, S2, xk, ybuf,
-                              nullptr, gpv, out, p->partials(), p->scal(), p->tw32(l.P), l.n, nz,
-                              p->pp, nblocks, st));
-  else
-    HIPCHK(p, launch_rows_inv(l.P, l.v_inv, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
-                              p->partials(), p->scal(), p->tw32(l.P), l.n, nz, p->pp, nblocks,
-                              st));
-  tend(p, ti);
+  // With the prior in sequence (or computed inside pass R'), passes R, C and R' may run through
+  // the slices in chunks that reuse the same S1 and S2 buffers: a chunk's half spectra then
+  // stay in the 256 MB Infinity Cache between the passes (the autotuner picks the count).  Each
+  // chunk's pass-R' partial sums follow the previous chunk's in the partials buffer.
+  const int nch = (conc || mode == MODE_POWER || p->fused_prior) ? 1
+                                                                  : std::max(1, std::min(l.chunks, nz));
+  const size_t plane = (size_t)l.n * l.n;
+  int nbtot = 0;
+  for (int c = 0; c < nch; ++c) {
+    const int z0 = (int)((long long)c * nz / nch), zc = (int)((long long)(c + 1) * nz / nch) - z0;
+    const size_t o = (size_t)z0 * plane;
+    int ti = timed ? tbegin(p, TOMO_T_ROWS_FWD) : -1;
+    if (yg)
+      HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, MODE_FISTA_Y, ybuf + o, ybuf + o, p->scal(), S1,
+                                p->tw32(l.P), l.n, zc, st));
+    else
+      HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, mode, xk + o, xkm1 + o, p->scal(), S1, p->tw32(l.P),
+                                l.n, zc, st));
+    tend(p, ti);
+    ti = timed ? tbegin(p, TOMO_T_COLS_CONV) : -1;
+    HIPCHK(p, launch_cols_conv(l.P, l.v_cc, S1, S2, p->at<float>(l.off_fk), p->at<float>(l.off_fkn),
+                               p->tw32(l.P), l.n, zc, st));
+    tend(p, ti);
+    // the prior on its own stream (one chunk): pass R' is the only reader of its output
+    if (conc) HIPCHK(p, hipStreamWaitEvent(st, p->pev_join, 0));
+    ti = timed ? tbegin(p, TOMO_T_ROWS_INV) : -1;
+    int nbc = 0;
+    double* part = p->partials() + (size_t)nbtot * 4;
+    if (yg)
+      HIPCHK(p, launch_rows_inv(l.P, l.v_inv, MODE_FISTA_Y, p->g.neighbours, obj, S2, xk + o,
+                                ybuf + o, nullptr, gpv + o, out + o, part, p->scal(), p->tw32(l.P),
+                                l.n, zc, p->pp, &nbc, st));
+    else if (nch == 1)
+      HIPCHK(p, launch_rows_inv(l.P, l.v_inv, mode, p->g.neighbours, obj, S2, xk, xkm1, b, gpv, out,
+                                part, p->scal(), p->tw32(l.P), l.n, nz, p->pp, &nbc, st));
+    else  // separate prior (gpv set): every operand is slice-local
+      HIPCHK(p, launch_rows_inv(l.P, l.v_inv, mode, p->g.neighbours, obj, S2, xk + o, xkm1 + o,
+                                b ? b + o : nullptr, gpv + o, out + o, part, p->scal(), p->tw32(l.P),
+                                l.n, zc, p->pp, &nbc, st));
+    tend(p, ti);
+    nbtot += nbc;
+  }
+  *nblocks = nbtot;
   return TOMO_OK;
 }
 
@@ -1624,6 +1645,7 @@ tomo_status tomo_timing_read(tomo_plan p, double* total_ms, int64_t* counts) {
 
 namespace {
 void fill_tiles(const Level& l, tomo_tiles_t* o) {
+  o->chunks = l.chunks;
   o->rows_fwd = l.v_fwd;
   o->cols_conv = l.v_cc;
   o->rows_inv = l.v_inv;
@@ -1645,12 +1667,15 @@ tomo_status tomo_tiles(tomo_plan p, const tomo_tiles_t* tiles, tomo_tiles_t* out
       if (t.rows_fwd < 0 || t.rows_fwd > 2 || t.cols_conv < 0 || t.cols_conv > 2 ||
           t.rows_inv < 0 || t.rows_inv > 2)
         return fail(p, TOMO_ERR_INVALID_ARG, "tile variant of level %d outside 0..2", i);
+      if (t.chunks != 0 && t.chunks != 1 && t.chunks != 2 && t.chunks != 4)
+        return fail(p, TOMO_ERR_INVALID_ARG, "slice chunks of level %d must be 1, 2 or 4", i);
     }
     drop_graphs(p);
     for (int i = 0; i < p->n_levels; ++i) {
       p->lv[i].v_fwd = tiles[i].rows_fwd;
       p->lv[i].v_cc = tiles[i].cols_conv;
       p->lv[i].v_inv = tiles[i].rows_inv;
+      p->lv[i].chunks = tiles[i].chunks == 0 ? 1 : tiles[i].chunks;
     }
   }
   if (out)
@@ -1733,10 +1758,42 @@ tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
     l.v_fwd = best(0);
     l.v_cc = best(1);
     l.v_inv = best(2);
+    // slice chunks of passes R, C, R' (1, 2 or 4; a count replaces 1 only when at least 3%
+    // faster): the whole step of the prior kernel and the three passes, timed with the chosen
+    // tiles on the plan's own volume
+    float msc[3] = {};
+    const int counts[3] = {1, 2, 4};
+    l.chunks = 1;
+    if (!p->fused_prior && !p->concurrent_prior) {
+      const int keep_mask = p->tmask;
+      p->tmask = 0;
+      for (int ci = 0; ci < 3 && s == TOMO_OK; ++ci) {
+        if (counts[ci] > p->nz) { msc[ci] = 0.f; continue; }
+        l.chunks = counts[ci];
+        int nb = 0;
+        tomo_status ts = toeplitz_passes(p, l, MODE_FISTA, p->nz, x, x, bb, out, false, &nb);
+        hipError_t e = ts == TOMO_OK ? hipEventRecord(e0, st) : hipErrorUnknown;
+        for (int r = 0; r < reps && e == hipSuccess && ts == TOMO_OK; ++r)
+          ts = toeplitz_passes(p, l, MODE_FISTA, p->nz, x, x, bb, out, false, &nb);
+        if (e == hipSuccess && ts == TOMO_OK) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && ts == TOMO_OK) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess && ts == TOMO_OK) e = hipEventElapsedTime(&t, e0, e1);
+        if (ts != TOMO_OK) s = ts;
+        else if (e != hipSuccess) s = fail(p, TOMO_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+        msc[ci] = t / reps;
+      }
+      p->tmask = keep_mask;
+      int bc = 0;
+      for (int ci = 1; ci < 3; ++ci)
+        if (msc[ci] > 0.f && msc[ci] < 0.97f * msc[0] && msc[ci] < msc[bc]) bc = ci;
+      l.chunks = counts[bc];
+    }
     if (chosen) {
       std::memset(&chosen[li], 0, sizeof chosen[li]);
       fill_tiles(l, &chosen[li]);
       std::memcpy(chosen[li].ms, ms, sizeof ms);
+      std::memcpy(chosen[li].ms_chunks, msc, sizeof msc);
     }
   }
   (void)hipEventDestroy(e0);

@@ -102,11 +102,13 @@ class BatchSchedule(ctypes.Structure):
 class Tiles(ctypes.Structure):
     _fields_ = [("rows_fwd", ctypes.c_int32), ("cols_conv", ctypes.c_int32), ("rows_inv", ctypes.c_int32),
                 ("fwd_pairs", ctypes.c_int32), ("col_tile", ctypes.c_int32), ("inv_pairs", ctypes.c_int32),
-                ("ms", (ctypes.c_float * 3) * 3)]
+                ("ms", (ctypes.c_float * 3) * 3), ("chunks", ctypes.c_int32),
+                ("ms_chunks", ctypes.c_float * 3)]
 
     def as_dict(self) -> dict:
         return {"rows_fwd": self.rows_fwd, "cols_conv": self.cols_conv, "rows_inv": self.rows_inv,
                 "fwd_pairs": self.fwd_pairs, "col_tile": self.col_tile, "inv_pairs": self.inv_pairs,
+                "chunks": self.chunks, "ms_chunks": [float(v) for v in self.ms_chunks],
                 "ms": [[float(self.ms[i][j]) for j in range(3)] for i in range(3)]}
 
 
@@ -352,13 +354,14 @@ class Plan:
         return [t.as_dict() for t in out]
 
     def tiles(self, set_to: Optional[Sequence[dict]] = None) -> list:
-        """Set (list of {rows_fwd, cols_conv, rows_inv} per level) and return the schedule."""
+        """Set (list of {rows_fwd, cols_conv, rows_inv[, chunks]} per level) and return the schedule."""
         arg = None
         if set_to is not None:
             arg = (Tiles * self.n_levels)()
             for i, d in enumerate(set_to):
                 arg[i].rows_fwd, arg[i].cols_conv, arg[i].rows_inv = (
                     int(d["rows_fwd"]), int(d["cols_conv"]), int(d["rows_inv"]))
+                arg[i].chunks = int(d.get("chunks", 1))
         out = (Tiles * self.n_levels)()
         _check(self._lib.tomo_tiles(self._h, arg, out), self._h)
         return [t.as_dict() for t in out]

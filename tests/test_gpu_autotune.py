@@ -76,3 +76,47 @@ def test_autotune_schedule_and_reconstruction():
     (x0, r0), (x1, r1) = outs
     assert r0 == r1
     assert rel_l2(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("chunks", [2, 4])
+def test_slice_chunks_bit_identical(chunks):
+    """Passes R, C, R' run through the slices in chunks (reusing one chunk's half-spectrum
+    buffers): every row and column is transformed by the same code and the partial sums keep
+    their order, so gradients, objectives and reconstructions are bit-identical."""
+    from paper_2603_28756_amd import tomo
+    n, nz, na, nd = 128, 5, 30, 182
+    sino, ang, center, phantom = problem(n, nz, na, nd, seed=23)
+    g = to_dev(sino)
+    res = []
+    for c in (1, chunks):
+        plan = make_plan(n, nz, ang, nd, neighbours=26, kb_width=6)
+        plan.precompute_psf()
+        t = plan.tiles([{"rows_fwd": 1, "cols_conv": 1, "rows_inv": 1, "chunks": c}])[0]
+        assert t["chunks"] == c
+        rng = np.random.default_rng(4)
+        x = to_dev(phantom + 0.05 * rng.standard_normal(phantom.shape))
+        b = to_dev(0.3 * rng.standard_normal(phantom.shape))
+        grad = torch.empty_like(x)
+        obj = torch.zeros(1, dtype=torch.float64, device=dev())
+        plan.gradient(x, b, grad, obj)
+        xr = torch.empty_like(x)
+        hist = torch.zeros(15, dtype=torch.float64, device=dev())
+        plan.reconstruct(g, xr, [15], init=tomo.INIT_FBP, objective=hist)
+        torch.cuda.synchronize()
+        res.append((grad.clone(), obj.clone(), xr.clone(), hist.clone()))
+    for a, b in zip(res[0], res[1]):
+        assert torch.equal(a, b)
+
+
+def test_autotune_picks_slice_chunks_from_its_timings():
+    n, nz, na, nd = 256, 8, 45, 364
+    sino, ang, center, _ = problem(n, nz, na, nd, seed=19)
+    plan = make_plan(n, nz, ang, nd, neighbours=26, kb_width=6)
+    plan.precompute_psf()
+    s = plan.autotune(reps=3)[0]
+    msc = s["ms_chunks"]
+    assert all(m > 0 for m in msc)
+    chosen = {1: 0, 2: 1, 4: 2}[s["chunks"]]
+    if s["chunks"] != 1:
+        assert msc[chosen] < 0.97 * msc[0] and msc[chosen] == min(msc)
+    assert plan.tiles()[0]["chunks"] == s["chunks"]
