@@ -64,11 +64,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(cls: str):
-    """HBM bytes per launch of kernel class `cls` from the counter summary, or None.
+def read_traffic(cls: str, key: str = "bytes_per_launch"):
+    """HBM bytes of kernel class `cls` from the counter summary, or None.
 
-    The summary holds a `source_hash` line and `kernel <class> ... bytes_per_launch <B>`
-    lines; it is ignored when the kernel sources changed after the counters were taken.
+    The summary holds a `source_hash` line and `kernel <class> ... bytes_per_launch <B>
+    ... bytes_per_iteration <B>` lines (passes R, C, R' launch once per slice chunk); it is
+    ignored when the kernel sources changed after the counters were taken.
     """
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -78,8 +79,8 @@ def read_traffic(cls: str):
             tok = line.split()
             if len(tok) >= 2 and tok[0] == "source_hash":
                 src = tok[1]
-            elif len(tok) >= 2 and tok[0] == "kernel" and "bytes_per_launch" in tok:
-                found[tok[1]] = float(tok[tok.index("bytes_per_launch") + 1])
+            elif len(tok) >= 2 and tok[0] == "kernel" and key in tok:
+                found[tok[1]] = float(tok[tok.index(key) + 1])
     if src != kernel_source_hash():
         return None
     return found.get(cls)
@@ -88,7 +89,8 @@ def read_traffic(cls: str):
 def iteration_traffic():
     """Measured HBM bytes of one iteration (passes R, C, R', prior, finalize) from the counter
     summary, or None when it does not match the current kernel sources."""
-    vals = [read_traffic(c) for c in ("rows_fwd", "cols_conv", "rows_inv", "prior", "finalize")]
+    vals = [read_traffic(c, "bytes_per_iteration")
+            for c in ("rows_fwd", "cols_conv", "rows_inv", "prior", "finalize")]
     return None if any(v is None for v in vals) else float(sum(vals))
 
 
@@ -515,6 +517,9 @@ def main() -> int:
     ap.add_argument("--infer-batch", type=int, default=8, help="learned start: slices per inference call")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile schedule instead of the autotuned one")
+    ap.add_argument("--tiles", default="",
+                    help="finest level's schedule as rows_fwd,cols_conv,rows_inv,chunks (no autotune); "
+                         "counter runs use it to repeat the schedule a timed run chose")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--cpu-only", action="store_true",
@@ -573,7 +578,12 @@ def main() -> int:
 
     # plan-time tile choice (once per geometry, outside the timed steps)
     tiles, tune_s = None, 0.0
-    if not args.no_autotune:
+    if args.tiles:
+        f, c, i, k = (int(v) for v in args.tiles.split(","))
+        sched = plan.tiles()
+        sched[-1].update({"rows_fwd": f, "cols_conv": c, "rows_inv": i, "chunks": k})
+        tiles = plan.tiles(sched)
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         tiles = plan.autotune(reps=5)
         tune_s = time.perf_counter() - t0
@@ -625,7 +635,9 @@ def main() -> int:
         return float(np.median(ts))
     tmp = torch.empty_like(x)
     phases = {
-        "psf_spectrum_and_step_ms": ev_ms(plan.precompute_psf),
+        # the precompute runs on the plan's PSF stream; reading F K back orders the plan's
+        # stream after it (and L on the host waits for it)
+        "psf_spectrum_and_step_ms": ev_ms(lambda: (plan.precompute_psf(), plan.psf_info())),
         "backprojection_ms": ev_ms(lambda: plan.backproject(sino, tmp, ramp=False)),
         "fbp_ms": ev_ms(lambda: plan.backproject(sino, tmp, ramp=True)),
         "call_without_iterations_ms": ev_ms(

@@ -175,6 +175,14 @@ tomo_status tomo_plan_set_workspace(tomo_plan plan, void* dev, size_t bytes);
  * deapodisation, and the padded FFT all run in float64), and the step constant
  * L = 1.01 * lambda_pow + 2 beta rho''(0), lambda_pow from 30 power iterations
  * of R*R from the all-ones image with float64 norms (Sec. 2, Eq. 6).
+ * Asynchronous: the work runs on a stream of the plan's own (default priority) that
+ * starts after everything already enqueued on the plan's stream, with scratch and
+ * iterate buffers of its own, so that a following tomo_reconstruct's back-projections
+ * (R* g and the FBP start) run beside it; every call that needs F K or L (the
+ * iterations, tomo_apply_normal, tomo_gradient, tomo_autotune, batches) first orders its
+ * stream after it.  Nothing waits for the host.  A non-finite or non-positive
+ * lambda_pow is reported by the first call that reads L on the host (tomo_psf_info with
+ * L_host or lambda_host, tomo_reconstruct with stats_host) as NONFINITE.
  * Errors: NO_WORKSPACE, HIP. */
 tomo_status tomo_precompute_psf(tomo_plan plan);
 
@@ -252,7 +260,8 @@ tomo_status tomo_reconstruct(tomo_plan plan, const float* sino, float* x,
 /* Copy level `level`'s PSF spectrum F K (float32, unnormalised) into the
  * caller's device array [P_l][P_l/2 + 1] (row = vertical frequency v,
  * column = horizontal frequency u = 0..P_l/2), and its step constants into
- * host doubles (each nullable).  Errors: INVALID_ARG, NOT_READY, HIP. */
+ * host doubles (each nullable; reading them waits for the precompute).
+ * Errors: INVALID_ARG, NOT_READY, HIP, NONFINITE (lambda_pow not finite and > 0). */
 tomo_status tomo_psf_info(tomo_plan plan, int32_t level, float* fk_dev, double* L_host,
                           double* lambda_host);
 

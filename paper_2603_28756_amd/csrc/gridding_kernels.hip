@@ -78,6 +78,17 @@ __global__ void set_scalars_kernel(double* scal, int first, int count, const dou
   if (i < count) scal[first + i] = src ? src[i] : v;
 }
 
+// out = {lambda, L, 1 / L} with L = a lambda + c, lambda from the power iteration's scalars;
+// the products and sums are rounded one at a time (no contraction), as on the host.
+__global__ void lipschitz_kernel(const double* scal, double a, double c, double* out) {
+  if (threadIdx.x != 0) return;
+  const double lam = scal[SC_LAMBDA];
+  const double L = __dadd_rn(__dmul_rn(a, lam), c);
+  out[0] = lam;
+  out[1] = L;
+  out[2] = __ddiv_rn(1.0, L);
+}
+
 __global__ void angle_table_kernel(const double* ang, double* tab, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -764,6 +775,10 @@ hipError_t launch_fill(float* x, idx_t n, float v, hipStream_t st) {
 hipError_t launch_set_scalars(double* scal, int first, int count, const double* src, double v,
                               hipStream_t st) {
   hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, scal, first, count, src, v);
+  return hipGetLastError();
+}
+hipError_t launch_lipschitz(const double* scal, double a, double c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(lipschitz_kernel, dim3(1), dim3(64), 0, st, scal, a, c, out);
   return hipGetLastError();
 }
 hipError_t launch_angle_table(const double* angles_dev, double* tab, int n, hipStream_t st) {

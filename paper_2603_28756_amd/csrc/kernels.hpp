@@ -157,6 +157,8 @@ hipError_t launch_twiddles_f64(cpx<double>* tw, int P, hipStream_t st);
 hipError_t launch_fill(float* x, idx_t n, float v, hipStream_t st);
 hipError_t launch_set_scalars(double* scal, int first, int count, const double* vals_dev_or_null,
                               double v, hipStream_t st);
+// out[0..2] = {lambda, a lambda + c, 1 / (a lambda + c)}, lambda = scal[SC_LAMBDA]
+hipError_t launch_lipschitz(const double* scal, double a, double c, double* out, hipStream_t st);
 hipError_t launch_sumsq_strided(const float* g, idx_t rows, int n_out, int stride, double scale,
                                 double* partials, double* out, hipStream_t st);
 hipError_t launch_lanczos_prolong(const float* in, float* out, int n, int nz, hipStream_t st);

@@ -971,16 +971,23 @@ constexpr int kBatchLdsFused =
                          cmax(batch_lds_fused_p<1024>(), batch_lds_fused_p<2048>())));
 static_assert(PriorShape<16>::NT == BT, "a batch prior tile is one block");
 
+// Cross-XCD ordering of the tile counters.  The eight L2 caches are not coherent with one
+// another for ordinary stores, so an agent-scope release writes this XCD's dirty L2 lines back
+// and an agent-scope acquire invalidates its L2.  Polling therefore reads the counter with a
+// relaxed agent-scope load (coherent, no cache maintenance) and takes the acquire once, after
+// the wait ends; an acquire on every poll would keep invalidating the L2 under the tiles that
+// other blocks of the XCD are transforming.
 TOMO_DEV void bounded_wait(const int* ctr, int target, int* err) {
   if (threadIdx.x == 0) {
     int spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > (1 << 22)) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -1191,10 +1198,11 @@ batch_iter_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      __threadfence();  // publish this tile's results before counting it
-      const int done = atomicAdd(&cnt[ph * nprob + j], 1);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this tile's results
+      const int done = __hip_atomic_fetch_add(&cnt[ph * nprob + j], 1, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
       s_fin = (ph == 3 && done == pb.iRp - 1) ? 1 : 0;
-      if (s_fin) __threadfence();  // see every other tile's partial sums
+      if (s_fin) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every partial sum
     }
     __syncthreads();
     if (s_fin) batch_finalize(pb, reinterpret_cast<double*>(smem));

@@ -81,8 +81,13 @@ struct tomo_plan_s {
   size_t off_cnt = 0, off_scan = 0, off_rampf = 0;
   size_t off_objpart = 0, off_choice = 0;  // learned start: objective partials, choice
   size_t off_resid = 0, off_rpart = 0;      // direct gradient: residual sinogram, its partials
+  // PSF precompute: its own scratch and power-iteration buffers (it runs on fstream, beside
+  // the back-projections on the plan's stream), and per level lambda, L, 1 / L on the device
+  size_t off_psf = 0, off_pv[2] = {}, off_pS1 = 0, off_pS2 = 0, off_ppart = 0, off_pscal = 0;
+  size_t off_lvl = 0;
   bool fused_prior = false, grids_ready = false;
   bool tables_ready = false, psf_ready = false;
+  bool psf_host = false;  // lambda and L of every level copied to the host
   std::string err;
 
   // iteration graphs: replayed on an internal stream ordered against `stream` by events
@@ -92,6 +97,10 @@ struct tomo_plan_s {
   bool concurrent_prior = false;
   hipStream_t pstream = nullptr;
   hipEvent_t pev_fork = nullptr, pev_join = nullptr;
+  // PSF precompute stream: forked from the plan's stream; consumers of the PSF spectrum and
+  // of L wait for fev_done
+  hipStream_t fstream = nullptr;
+  hipEvent_t fev_fork = nullptr, fev_done = nullptr;
   // learned start: the network's stream ordered after / before the plan's stream
   hipEvent_t nev_fork = nullptr, nev_join = nullptr;
   struct GraphKey { int level, ik, nz; double* hist; int32_t* rhist; bool obj; };
@@ -212,13 +221,26 @@ void layout(tomo_plan p) {
     const size_t hot = 2 * s1;
     const size_t bp = (size_t)l.M * l.M * sizeof(cpx<float>);
     const size_t npts = (size_t)na * (l.nd - 1);
-    const size_t psf = align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>)) +
-                       align_up((size_t)l.P * l.P * sizeof(cpx<double>)) +
-                       align_up(npts * sizeof(int2)) + 2 * align_up(npts * W * sizeof(double));
-    scratch = std::max(scratch, std::max(hot, std::max(bp, psf)));
+    scratch = std::max(scratch, std::max(hot, bp));
   }
   p->scratch_bytes = scratch;
   p->off_scratch = take(scratch);
+  size_t psf = 0, pn = 0, pspec = 0;
+  for (const Level& l : p->lv) {
+    const size_t npts = (size_t)na * (l.nd - 1);
+    psf = std::max(psf, align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>)) +
+                            align_up((size_t)l.P * l.P * sizeof(cpx<double>)) +
+                            align_up(npts * sizeof(int2)) + 2 * align_up(npts * W * sizeof(double)));
+    pn = std::max(pn, (size_t)l.n * l.n);
+    pspec = std::max(pspec, (size_t)l.n * (l.P / 2));
+  }
+  p->off_psf = take(psf);
+  for (int i = 0; i < 2; ++i) p->off_pv[i] = take(pn * sizeof(float));
+  p->off_pS1 = take(pspec * sizeof(cpx<float>));
+  p->off_pS2 = take(pspec * sizeof(cpx<float>));
+  p->off_ppart = take(maxblocks * 4 * sizeof(double));
+  p->off_pscal = take(SC_COUNT * sizeof(double));
+  p->off_lvl = take(3 * (size_t)p->n_levels * sizeof(double));
   p->need = off;
 }
 
@@ -264,6 +286,7 @@ tomo_status ensure_prior_stream(tomo_plan p) {
 
 tomo_status tresolve(tomo_plan p) {
   HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (p->fstream) HIPCHK(p, hipStreamSynchronize(p->fstream));  // PSF launches are timed there
   for (auto& e : p->pending) {
     float ms = 0.f;
     HIPCHK(p, hipEventElapsedTime(&ms, e.a, e.b));
@@ -460,8 +483,12 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
   return TOMO_OK;
 }
 
-tomo_status psf_level(tomo_plan p, Level& l) {
-  hipStream_t st = p->stream;
+// PSF spectrum F K of level li (Sec. 2.1, Eq. 9) and the largest eigenvalue of T by power
+// iteration, on the PSF stream with the PSF's own scratch, iterate and spectrum buffers (so
+// that it can run beside the back-projections of the plan's stream).  lambda, L and 1 / L
+// stay on the device (off_lvl); nothing here waits for the host.
+tomo_status psf_level(tomo_plan p, Level& l, int li) {
+  hipStream_t st = p->fstream;
   GridGeom gg;
   gg.n = 2 * l.n;
   gg.n_det = l.nd;
@@ -472,7 +499,7 @@ tomo_status psf_level(tomo_plan p, Level& l) {
   gg.c = l.c;
   gg.stride = 1;
   const size_t npts = (size_t)p->g.n_angles * (l.nd - 1);
-  size_t off = p->off_scratch;
+  size_t off = p->off_psf;
   cpx<double>* grid = p->at<cpx<double>>(off);
   off += align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>));
   cpx<double>* emb = p->at<cpx<double>>(off);
@@ -487,30 +514,60 @@ tomo_status psf_level(tomo_plan p, Level& l) {
   HIPCHK(p, launch_fft2d_f64(grid, l.Mpsf, 1, +1, p->tw64(l.Mpsf), st));
   HIPCHK(p, launch_psf_embed(grid, emb, gg, l.n, l.P, st));
   HIPCHK(p, launch_fft2d_f64(emb, l.P, 1, -1, p->tw64(l.P), st));
-  HIPCHK(p, launch_fk_store(emb, p->at<float>(l.off_fk), p->at<float>(l.off_fkn), l.P, st));
+  const float* fk = p->at<float>(l.off_fk);
+  const float* fkn = p->at<float>(l.off_fkn);
+  HIPCHK(p, launch_fk_store(emb, const_cast<float*>(fk), const_cast<float*>(fkn), l.P, st));
 
-  // Power iteration on one slice: v0 = 1, lambda = ||T v|| / ||v||.
-  float* v = p->xbuf(0);
-  float* w = p->xbuf(1);
+  // Power iteration on one slice: v0 = 1, lambda = ||T v|| / ||v||; each step applies the
+  // three Toeplitz passes to the scaled iterate and normalises in the float64 finalize.
+  float* v = p->at<float>(p->off_pv[0]);
+  float* w = p->at<float>(p->off_pv[1]);
+  cpx<float>* S1 = p->at<cpx<float>>(p->off_pS1);
+  cpx<float>* S2 = p->at<cpx<float>>(p->off_pS2);
+  double* part = p->at<double>(p->off_ppart);
+  double* sc = p->at<double>(p->off_pscal);
   HIPCHK(p, launch_fill(v, (idx_t)l.n * l.n, 1.0f, st));
-  HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, st));
-  HIPCHK(p, launch_set_scalars(p->scal(), SC_VNORM, 1, nullptr, (double)l.n, st));
+  HIPCHK(p, launch_set_scalars(sc, SC_PSCALE, 1, nullptr, 1.0, st));
+  HIPCHK(p, launch_set_scalars(sc, SC_VNORM, 1, nullptr, (double)l.n, st));
   for (int it = 0; it < kPowerIters; ++it) {
     int nb = 0;
-    tomo_status s = toeplitz_passes(p, l, MODE_POWER, 1, v, v, nullptr, w, false, &nb);
-    if (s != TOMO_OK) return s;
-    HIPCHK(p, launch_finalize(MODE_POWER, p->partials(), nb, nullptr, 0, p->scal(), nullptr,
-                              nullptr, nullptr, st));
+    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, MODE_POWER, v, v, sc, S1, p->tw32(l.P), l.n, 1, st));
+    HIPCHK(p, launch_cols_conv(l.P, l.v_cc, S1, S2, fk, fkn, p->tw32(l.P), l.n, 1, st));
+    HIPCHK(p, launch_rows_inv(l.P, l.v_inv, MODE_POWER, p->g.neighbours, false, S2, v, v, nullptr,
+                              nullptr, w, part, sc, p->tw32(l.P), l.n, 1, p->pp, &nb, st));
+    HIPCHK(p, launch_finalize(MODE_POWER, part, nb, nullptr, 0, sc, nullptr, nullptr, nullptr, st));
     std::swap(v, w);
   }
-  double lam = 0.0;
-  HIPCHK(p, hipMemcpyAsync(&lam, p->scal() + SC_LAMBDA, sizeof(double), hipMemcpyDeviceToHost,
-                           st));
-  HIPCHK(p, hipStreamSynchronize(st));
-  if (!std::isfinite(lam) || lam <= 0.0)
-    return fail(p, TOMO_ERR_NONFINITE, "power iteration gave lambda = %g", lam);
-  l.lambda = lam;
-  l.L = 1.01 * lam + 2.0 * p->g.beta * p->rho2_0;
+  // L = 1.01 lambda + 2 beta rho''(0) (a bound on the Hessian of the whole objective)
+  HIPCHK(p, launch_lipschitz(sc, 1.01, 2.0 * p->g.beta * p->rho2_0,
+                             p->at<double>(p->off_lvl) + 3 * (size_t)li, st));
+  return TOMO_OK;
+}
+
+// Copy lambda and L of every level to the host (waits for the PSF stream); a non-finite or
+// non-positive lambda is reported here.
+tomo_status psf_host_values(tomo_plan p) {
+  if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
+  if (p->psf_host) return TOMO_OK;
+  std::vector<double> v(3 * (size_t)p->n_levels);
+  HIPCHK(p, hipMemcpyAsync(v.data(), p->at<double>(p->off_lvl), v.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, p->fstream));
+  HIPCHK(p, hipStreamSynchronize(p->fstream));
+  for (int li = 0; li < p->n_levels; ++li) {
+    const double lam = v[3 * li];
+    if (!std::isfinite(lam) || lam <= 0.0)
+      return fail(p, TOMO_ERR_NONFINITE, "power iteration gave lambda = %g on level %d", lam, li);
+    p->lv[li].lambda = lam;
+    p->lv[li].L = v[3 * li + 1];
+  }
+  p->psf_host = true;
+  return TOMO_OK;
+}
+
+// Order stream st after the PSF precompute (spectrum, lambda and L of every level).
+tomo_status psf_join(tomo_plan p, hipStream_t st) {
+  if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
+  HIPCHK(p, hipStreamWaitEvent(st, p->fev_done, 0));
   return TOMO_OK;
 }
 
@@ -838,6 +895,7 @@ tomo_status tomo_plan_set_workspace(tomo_plan p, void* dev, size_t bytes) {
     return fail(p, TOMO_ERR_WORKSPACE_TOO_SMALL, "workspace %zu B < required %zu B", bytes, p->need);
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);  // captured with the old pointers
   p->graphs.clear();
+  if (p->fstream) HIPCHK(p, hipStreamSynchronize(p->fstream));  // a PSF precompute may still write
   p->ws = static_cast<char*>(dev);
   p->ws_bytes = bytes;
   p->tables_ready = false;
@@ -853,12 +911,24 @@ tomo_status tomo_precompute_psf(tomo_plan p) {
   HIPCHK(p, hipSetDevice(p->device));
   if ((s = ensure_tables(p)) != TOMO_OK) return s;
   if ((s = ensure_grids(p)) != TOMO_OK) return s;
-  for (Level& l : p->lv) {
-    const int ti = tbegin(p, TOMO_T_PSF);
-    s = psf_level(p, l);
-    tend(p, ti);
+  if (!p->fstream) {
+    HIPCHK(p, hipStreamCreateWithFlags(&p->fstream, hipStreamNonBlocking));
+    HIPCHK(p, hipEventCreateWithFlags(&p->fev_fork, hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->fev_done, hipEventDisableTiming));
+  }
+  p->psf_ready = false;
+  p->psf_host = false;
+  // after everything already enqueued on the plan's stream (tables, gridding lists, and any
+  // earlier use of the spectrum this overwrites)
+  HIPCHK(p, hipEventRecord(p->fev_fork, p->stream));
+  HIPCHK(p, hipStreamWaitEvent(p->fstream, p->fev_fork, 0));
+  for (int li = 0; li < p->n_levels; ++li) {
+    const int ti = tbegin(p, TOMO_T_PSF, p->fstream);
+    s = psf_level(p, p->lv[li], li);
+    tend(p, ti, p->fstream);
     if (s != TOMO_OK) return s;
   }
+  HIPCHK(p, hipEventRecord(p->fev_done, p->fstream));
   p->psf_ready = true;
   return TOMO_OK;
 }
@@ -881,6 +951,7 @@ tomo_status tomo_apply_normal(tomo_plan p, const float* x, float* out) {
   if (s != TOMO_OK) return s;
   if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
   HIPCHK(p, hipSetDevice(p->device));
+  if ((s = psf_join(p, p->stream)) != TOMO_OK) return s;
   HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, p->stream));
   int nb = 0;
   return toeplitz_passes(p, p->lv.back(), MODE_POWER, p->nz, x, x, nullptr, out, false, &nb);
@@ -896,6 +967,7 @@ tomo_status tomo_gradient(tomo_plan p, const float* x, const float* b, float* gr
   if (s != TOMO_OK) return s;
   if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
   HIPCHK(p, hipSetDevice(p->device));
+  if ((s = psf_join(p, p->stream)) != TOMO_OK) return s;
   int nb = 0, npr = 0;
   if ((s = toeplitz_passes(p, p->lv.back(), MODE_GRAD, p->nz, x, x, b, grad, obj_dev != nullptr,
                            &nb, &npr)) != TOMO_OK)
@@ -985,7 +1057,7 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
         if (opts->init == TOMO_INIT_LEARNED) {
           learned_state = in_domain(p, l, net) ? TOMO_LEARNED_TESTED : TOMO_LEARNED_OUT_OF_DOMAIN;
           if (learned_state == TOMO_LEARNED_TESTED &&
-              (s = learned_start(p, l, b, cur, net, opts)) != TOMO_OK)
+              ((s = psf_join(p, st)) != TOMO_OK || (s = learned_start(p, l, b, cur, net, opts)) != TOMO_OK))
             return s;
         }
       } else if (opts->init == TOMO_INIT_ZERO) {
@@ -998,10 +1070,16 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
       HIPCHK(p, launch_lanczos_prolong(p->xbuf(cur), p->xbuf(nxt), p->lv[li - 1].n, p->nz, st));
       cur = nxt;
     }
-    const double L = opts->L_override > 0.0 ? opts->L_override : l.L;
+    // the iterations need the level's PSF spectrum and 1 / L: wait for the PSF stream here, so
+    // that the back-projections above overlap the precompute
+    if ((s = psf_join(p, st)) != TOMO_OK) return s;
     HIPCHK(p, launch_set_scalars(sc, SC_MU, 1, nullptr, 0.0, st));
     HIPCHK(p, launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st));
-    HIPCHK(p, launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / L, st));
+    if (opts->L_override > 0.0)
+      HIPCHK(p, launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / opts->L_override, st));
+    else
+      HIPCHK(p, launch_set_scalars(sc, SC_INVL, 1, p->at<double>(p->off_lvl) + 3 * (size_t)li + 2,
+                                   0.0, st));
     int ik = cur, ikm1 = cur, inext = (cur + 1) % 3;
     const int n_it = opts->iters[li];
     // Graph replay of 3-iteration blocks once the buffer rotation is periodic; the events
@@ -1041,6 +1119,7 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
     double sv[SC_COUNT];
     HIPCHK(p, hipMemcpyAsync(sv, sc, sizeof sv, hipMemcpyDeviceToHost, st));
     HIPCHK(p, hipStreamSynchronize(st));
+    if ((s = psf_host_values(p)) != TOMO_OK) return s;
     std::memset(stats, 0, sizeof *stats);
     for (int l = 0; l < p->n_levels && l < 6; ++l) {
       stats->L[l] = opts->L_override > 0.0 ? opts->L_override : p->lv[l].L;
@@ -1067,11 +1146,14 @@ tomo_status tomo_psf_info(tomo_plan p, int32_t level, float* fk_dev, double* L_h
   if (!p || level < 0 || level >= p->n_levels) return fail(p, TOMO_ERR_INVALID_ARG, "bad level");
   if (!p->psf_ready) return fail(p, TOMO_ERR_NOT_READY, "PSF not precomputed");
   const Level& l = p->lv[level];
+  tomo_status s = TOMO_OK;
   if (fk_dev) {
     HIPCHK(p, hipSetDevice(p->device));
+    if ((s = psf_join(p, p->stream)) != TOMO_OK) return s;
     HIPCHK(p, launch_fk_export(p->at<float>(l.off_fk), p->at<float>(l.off_fkn), fk_dev, l.P,
                                p->stream));
   }
+  if ((L_host || lambda_host) && (s = psf_host_values(p)) != TOMO_OK) return s;
   if (L_host) *L_host = l.L;
   if (lambda_host) *lambda_host = l.lambda;
   return TOMO_OK;
@@ -1149,6 +1231,7 @@ tomo_status batch_prepare(tomo_batch bt, int j, const float* sino, int restart) 
   if (s == TOMO_OK) s = backproject_level(p, l, sino, p->at<float>(l.off_b), 0);
   if (s == TOMO_OK) s = backproject_level(p, l, sino, p->xbuf(0), 1, true);
   hipStream_t st = bt->stream;
+  if (s == TOMO_OK) s = psf_join(p, st);
   double* sc = p->scal();
   hipError_t e = hipSuccess;
   if (s == TOMO_OK) {
@@ -1156,7 +1239,8 @@ tomo_status batch_prepare(tomo_batch bt, int j, const float* sino, int restart) 
                              sc + SC_GG, st);
     if (e == hipSuccess) e = launch_set_scalars(sc, SC_MU, 1, nullptr, 0.0, st);
     if (e == hipSuccess) e = launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st);
-    if (e == hipSuccess) e = launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / l.L, st);
+    if (e == hipSuccess)
+      e = launch_set_scalars(sc, SC_INVL, 1, p->at<double>(p->off_lvl) + 2, 0.0, st);
     if (e == hipSuccess) e = launch_set_scalars(sc, SC_RESTART_ON, 1, nullptr, restart ? 1.0 : 0.0, st);
     if (e == hipSuccess) e = launch_set_scalars(sc, SC_ITER, 1, nullptr, 0.0, st);
     if (e == hipSuccess) e = launch_set_scalars(sc, SC_NRESTART, 1, nullptr, 0.0, st);
@@ -1514,6 +1598,7 @@ tomo_status tomo_batch_autotune(tomo_batch b, int32_t reps, tomo_batch_schedule_
     tomo_status s = ensure_tables(p);
     if (s == TOMO_OK && !p->psf_ready) s = tomo_precompute_psf(p);
     p->stream = keep;
+    if (s == TOMO_OK) s = psf_join(p, st);
     if (s != TOMO_OK) return bfail(b, s, "autotune setup: %s", p->err.c_str());
     const Level& l = p->lv[0];
     const idx_t vol = (idx_t)p->nz * l.n * l.n;
@@ -1523,7 +1608,7 @@ tomo_status tomo_batch_autotune(tomo_batch b, int32_t reps, tomo_batch_schedule_
     double* sc = p->scal();
     BHIPCHK(b, launch_set_scalars(sc, 0, SC_COUNT, nullptr, 0.0, st));
     BHIPCHK(b, launch_set_scalars(sc, SC_T, 1, nullptr, 1.0, st));
-    BHIPCHK(b, launch_set_scalars(sc, SC_INVL, 1, nullptr, 1.0 / l.L, st));
+    BHIPCHK(b, launch_set_scalars(sc, SC_INVL, 1, p->at<double>(p->off_lvl) + 2, 0.0, st));
     BHIPCHK(b, launch_set_scalars(sc, SC_NONFINITE, 1, nullptr, -1.0, st));
   }
   batch_fill_descriptors(b);
@@ -1693,6 +1778,8 @@ tomo_status tomo_autotune(tomo_plan p, int32_t reps, tomo_tiles_t* chosen) {
   if (tomo_status s = check_ws(p); s != TOMO_OK) return s;
   hipStream_t st = p->stream;
   drop_graphs(p);
+  // the timings must not overlap a PSF precompute still running beside the plan's stream
+  if (p->fstream) HIPCHK(p, hipStreamSynchronize(p->fstream));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(p, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1820,6 +1907,12 @@ tomo_status tomo_plan_destroy(tomo_plan p) {
   }
   if (p->pev_fork) (void)hipEventDestroy(p->pev_fork);
   if (p->pev_join) (void)hipEventDestroy(p->pev_join);
+  if (p->fstream) {
+    (void)hipStreamSynchronize(p->fstream);
+    (void)hipStreamDestroy(p->fstream);
+  }
+  if (p->fev_fork) (void)hipEventDestroy(p->fev_fork);
+  if (p->fev_done) (void)hipEventDestroy(p->fev_done);
   if (p->gev_in) (void)hipEventDestroy(p->gev_in);
   if (p->gev_out) (void)hipEventDestroy(p->gev_out);
   if (p->nev_fork) (void)hipEventDestroy(p->nev_fork);
