@@ -257,6 +257,12 @@ tomo_status tomo_gradient_direct(tomo_plan plan, const float* x, const float* si
 tomo_status tomo_reconstruct(tomo_plan plan, const float* sino, float* x,
                              const tomo_recon_opts_t* opts, tomo_recon_stats_t* stats_host);
 
+/* The plan's geometry as validated at creation (n_slices, n, n_angles, n_det, ...; the
+ * centre and KB shape as given), its HIP stream and device (each nullable).
+ * Errors: INVALID_ARG (NULL plan). */
+tomo_status tomo_plan_geometry(tomo_plan plan, tomo_geometry_t* geom, void** hip_stream,
+                               int32_t* device);
+
 /* Copy level `level`'s PSF spectrum F K (float32, unnormalised) into the
  * caller's device array [P_l][P_l/2 + 1] (row = vertical frequency v,
  * column = horizontal frequency u = 0..P_l/2), and its step constants into

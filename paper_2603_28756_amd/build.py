@@ -15,7 +15,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libtomo.so")
 SOURCES = ["toeplitz_kernels.hip", "gridding_kernels.hip", "unet_kernels.hip", "start_kernels.hip",
            "direct_kernels.hip",
-           "tomo_api.cpp", "unet_api.cpp"]
+           "tomo_api.cpp", "unet_api.cpp", "pipeline.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

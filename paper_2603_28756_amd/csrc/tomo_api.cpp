@@ -1159,6 +1159,15 @@ tomo_status tomo_psf_info(tomo_plan p, int32_t level, float* fk_dev, double* L_h
   return TOMO_OK;
 }
 
+tomo_status tomo_plan_geometry(tomo_plan p, tomo_geometry_t* geom, void** hip_stream,
+                               int32_t* device) {
+  if (!p) return fail(nullptr, TOMO_ERR_INVALID_ARG, "plan is NULL");
+  if (geom) *geom = p->g;
+  if (hip_stream) *hip_stream = p->stream;
+  if (device) *device = p->device;
+  return TOMO_OK;
+}
+
 tomo_status tomo_level_dims(tomo_plan p, int32_t level, int32_t* n, int32_t* n_det, int32_t* pad) {
   if (!p || level < 0 || level >= p->n_levels) return fail(p, TOMO_ERR_INVALID_ARG, "bad level");
   const Level& l = p->lv[level];

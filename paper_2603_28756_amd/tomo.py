@@ -77,6 +77,15 @@ class UnetDomain(ctypes.Structure):
     ]
 
 
+class PipelineStats(ctypes.Structure):
+    _fields_ = [
+        ("n_windows", ctypes.c_int32), ("nonfinite_window", ctypes.c_int32),
+        ("n_restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("wall_ms", ctypes.c_double), ("upload_ms", ctypes.c_double),
+        ("compute_ms", ctypes.c_double), ("download_ms", ctypes.c_double),
+    ]
+
+
 class BatchStats(ctypes.Structure):
     _fields_ = [("n_nonfinite", ctypes.c_int32), ("n_restarts", ctypes.c_int32),
                 ("wait_timeouts", ctypes.c_int32)]
@@ -147,6 +156,19 @@ EXPORTS = {
     "tomo_batch_schedule": ([ctypes.c_void_p, ctypes.POINTER(BatchSchedule), ctypes.POINTER(BatchSchedule)],
                             ctypes.c_int),
     "tomo_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "tomo_plan_geometry": ([ctypes.c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(ctypes.c_void_p),
+                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "tomo_pipeline_window": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "tomo_pipeline_create": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "tomo_pipeline_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tomo_pipeline_set_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "tomo_pipeline_run": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ReconOpts),
+                           ctypes.POINTER(PipelineStats)], ctypes.c_int),
+    "tomo_pipeline_last_error": ([ctypes.c_void_p], ctypes.c_char_p),
+    "tomo_pipeline_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "tomo_unet_create": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "tomo_unet_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -382,6 +404,83 @@ def lanczos_prolong(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=
         out = torch.empty((nz, 2 * n, 2 * n), dtype=torch.float32, device=x.device)
     _check(lib.tomo_lanczos_prolong(_ptr(x), _ptr(out), n, nz, _stream_ptr(stream)))
     return out
+
+
+def pipeline_window(n_total: int, n_slices: int, halo: int, k: int):
+    """(first, keep0, keep1, n_windows) of window k (host arithmetic of include/tomo_pipeline.h)."""
+    lib = load_library()
+    f, a, b, w = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32())
+    st = lib.tomo_pipeline_window(int(n_total), int(n_slices), int(halo), int(k), ctypes.byref(f),
+                                  ctypes.byref(a), ctypes.byref(b), ctypes.byref(w))
+    if st != TOMO_OK:
+        raise TomoError(st, lib.tomo_pipeline_last_error(None).decode())
+    return f.value, a.value, b.value, w.value
+
+
+class Pipeline:
+    """A volume of n_total slices in host memory streamed through `plan` (window = the plan's
+    n_slices, `halo` context slices per side, `depth` windows in flight): include/tomo_pipeline.h.
+    The device workspace of the window slots is a torch tensor owned by this object."""
+
+    def __init__(self, plan: "Plan", n_total: int, halo: int = 0, depth: int = 2):
+        lib = load_library()
+        self._lib = lib
+        self.plan = plan
+        self.n_total, self.halo, self.depth = int(n_total), int(halo), int(depth)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(plan.device):
+            st = lib.tomo_pipeline_create(plan._h, self.n_total, self.halo, self.depth, ctypes.byref(h))
+        if st != TOMO_OK:
+            raise TomoError(st, lib.tomo_pipeline_last_error(None).decode())
+        self._h = h
+        sz = ctypes.c_size_t()
+        self._pcheck(lib.tomo_pipeline_workspace_size(self._h, ctypes.byref(sz)))
+        self._ws = torch.empty(sz.value + 256, dtype=torch.uint8, device=plan.device)
+        base = self._ws.data_ptr()
+        self._pcheck(lib.tomo_pipeline_set_workspace(self._h, ctypes.c_void_p(base + (-base) % 256), sz.value))
+
+    def _pcheck(self, status: int):
+        if status != TOMO_OK:
+            raise TomoError(status, self._lib.tomo_pipeline_last_error(self._h).decode())
+
+    def run(self, sino: "np.ndarray", x: "np.ndarray", iters: Sequence[int], init: int = INIT_FBP,
+            restart: bool = True, L_override: float = 0.0, stats: bool = True,
+            unet: Optional["UNet"] = None, unet_scale: float = 0.0):
+        """sino [n_total][n_angles][n_det] and x [n_total][N][N]: C-contiguous float32 host arrays."""
+        import numpy as np
+        for a in (sino, x):
+            if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]):
+                raise TypeError("expected C-contiguous float32 numpy arrays")
+        g = self.plan
+        if sino.shape != (self.n_total, g.n_angles, g.n_det) or x.shape != (self.n_total, g.n, g.n):
+            raise ValueError("array shapes do not match the pipeline's volume")
+        if not x.flags["WRITEABLE"]:
+            raise ValueError("x must be writeable")
+        it = (ctypes.c_int32 * len(iters))(*[int(i) for i in iters])
+        o = ReconOpts()
+        o.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+        o.init, o.restart, o.L_override = init, int(restart), float(L_override)
+        o.unet = unet._h.value if unet is not None else None
+        o.unet_scale = float(unet_scale)
+        st = PipelineStats() if stats else None
+        torch.cuda.current_stream(g.device).synchronize()  # device work queued before the call
+        self._pcheck(self._lib.tomo_pipeline_run(self._h, ctypes.c_void_p(sino.ctypes.data),
+                                                 ctypes.c_void_p(x.ctypes.data), ctypes.byref(o),
+                                                 ctypes.byref(st) if st is not None else None))
+        if st is None:
+            return None
+        return {k: getattr(st, k) for k, _ in PipelineStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tomo_pipeline_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

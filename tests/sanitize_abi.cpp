@@ -9,6 +9,7 @@
 
 #include "tomo.h"
 #include "tomo_nn.h"
+#include "tomo_pipeline.h"
 
 static int failures = 0;
 #define CHECK(cond)                                                         \
@@ -99,6 +100,26 @@ int main() {
   tomo_batch batch = nullptr;
   CHECK(tomo_batch_create(nullptr, 0, nullptr, &batch) == TOMO_ERR_INVALID_ARG);
   CHECK(tomo_batch_destroy(nullptr) == TOMO_OK);
+
+  CHECK(tomo_plan_geometry(nullptr, nullptr, nullptr, nullptr) == TOMO_ERR_INVALID_ARG);
+  {
+    int32_t f = -1, a = -1, b = -1, w = -1;
+    CHECK(tomo_pipeline_window(11, 4, 0, 2, &f, &a, &b, &w) == TOMO_OK);
+    CHECK(f == 7 && a == 8 && b == 11 && w == 3);
+    CHECK(tomo_pipeline_window(13, 6, 2, 0, &f, &a, &b, nullptr) == TOMO_OK && f == 0 && a == 0 && b == 2);
+    CHECK(tomo_pipeline_window(3, 4, 0, 0, &f, &a, &b, &w) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_window(10, 4, 2, 0, &f, &a, &b, &w) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_window(10, 4, 0, 3, &f, &a, &b, &w) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_window(10, 4, 0, 0, nullptr, &a, &b, &w) == TOMO_ERR_INVALID_ARG);
+    CHECK(std::strlen(tomo_pipeline_last_error(nullptr)) > 0);
+    tomo_pipeline pipe = reinterpret_cast<tomo_pipeline>(0x1);
+    CHECK(tomo_pipeline_create(nullptr, 16, 0, 2, &pipe) == TOMO_ERR_INVALID_ARG && pipe == nullptr);
+    CHECK(tomo_pipeline_create(nullptr, 16, 0, 2, nullptr) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_workspace_size(nullptr, &bytes) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_set_workspace(nullptr, nullptr, 0) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_run(nullptr, nullptr, nullptr, nullptr, nullptr) == TOMO_ERR_INVALID_ARG);
+    CHECK(tomo_pipeline_destroy(nullptr) == TOMO_OK);
+  }
 
   tomo_unet net = reinterpret_cast<tomo_unet>(0x1);
   CHECK(tomo_unet_create(0, 32, 1, 64, 64, nullptr, &net) == TOMO_ERR_INVALID_ARG);

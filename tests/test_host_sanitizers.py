@@ -1,4 +1,4 @@
-"""Host code of libtomo (tomo_api.cpp, unet_api.cpp) built with AddressSanitizer and
+"""Host code of libtomo (tomo_api.cpp, unet_api.cpp, pipeline.cpp) built with AddressSanitizer and
 UndefinedBehaviorSanitizer instrumentation on its host side only (the device code is as in
 the library), linked with the library's kernel objects, and run through every ABI validation
 path that needs no GPU (tests/sanitize_abi.cpp)."""
@@ -30,7 +30,7 @@ def test_abi_host_paths_under_asan_and_ubsan(tmp_path):
         pytest.skip("needs hipcc, clang++ and the library's kernel objects (run the build first)")
     inc = os.path.join(ROOT, "include")
     objs = []
-    for src in ("tomo_api.cpp", "unet_api.cpp"):
+    for src in ("tomo_api.cpp", "unet_api.cpp", "pipeline.cpp"):
         o = str(tmp_path / (src + ".o"))
         _run([HIPCC, "--offload-arch=gfx950", "-O1", "-std=c++17", "-fPIC", "-Xclang", "-target-feature",
               "-Xclang", "-packed-fp32-ops", "-I", inc, *HOST_SAN, "-x", "hip", "-c",
