@@ -367,30 +367,36 @@ gather_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid
 }
 
 // Same sums with lanes over slices: a wave walks the lists of 64/ZL cells at a time, each
-// group of ZL lanes reading ZL consecutive slices of a sample (one contiguous line); results
-// are transposed through LDS so that each slice's row of 64 cells is written contiguously.
-template <int ZL>
+// group of ZL lanes reading ZL x SPL consecutive slices of a sample (one contiguous line; SPL
+// slices per lane in one 8- or 16-byte load); results are transposed through LDS so that each
+// slice's row of 64 cells is written contiguously.  The walk is bound by the latency of its
+// dependent loads (list bounds, then entries, then values), so more cells per wave step (two
+// slices per lane) means fewer rounds for the same sums.  Every sum runs in list order.
+template <int ZL, int SPL>
 __global__ void __launch_bounds__(256)
 gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid,
                 const int* __restrict__ row_ptr, const int* __restrict__ idx,
                 const float* __restrict__ wts, const float* __restrict__ lscale, int M, int nl,
                 int nz, int z0, int nzb) {
+  static_assert(SPL == 1 || SPL == 2 || SPL == 4, "slices per lane");
   constexpr int G = 64 / ZL;   // cells per wave step
   constexpr int CB = 64;       // cells per block
-  __shared__ cpx<float> tile[ZL][CB + 1];
+  constexpr int ZS = ZL * SPL; // slices per block row
+  __shared__ cpx<float> tile[ZS][CB + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / ZL, zl = lane - g * ZL;
   const idx_t cells = (idx_t)M * M;
   const idx_t cell0 = (idx_t)blockIdx.x * CB;
-  const int zi = blockIdx.y * ZL + zl;
+  const int zi = blockIdx.y * ZS + zl * SPL;  // first slice of this lane
   for (int cs = wave * G + g; cs < CB; cs += 4 * G) {
     const idx_t cell = cell0 + cs;
-    float ar = 0.f, ai = 0.f;
+    float ar[SPL], ai[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) ar[s] = ai[s] = 0.f;
     if (cell < cells && zi < nzb) {
       const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
       // eight entries per step: their indices and weights first, then eight independent
-      // value loads in flight (cells near the origin have lists of ~n_angles * W entries);
-      // the sum still runs in list order
+      // value loads in flight (cells near the origin have lists of ~n_angles * W entries)
       constexpr int U = 8;
       for (int k = k0; k < k1; k += U) {
         int pp[U];
@@ -405,25 +411,49 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
 #pragma unroll
           for (int u = 0; u < U; ++u) w[u] *= lscale[pp[u] % nl];
         }
-        cpx<float> v[U];
+        if constexpr (SPL == 1) {
+          cpx<float> v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = vals[(idx_t)pp[u] * nz + z0 + zi];
+          for (int u = 0; u < U; ++u) v[u] = vals[(idx_t)pp[u] * nz + z0 + zi];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (k + u < k1) {
-            ar += w[u] * v[u].re;
-            ai += w[u] * v[u].im;
+          for (int u = 0; u < U; ++u) {
+            if (k + u < k1) {
+              ar[0] += w[u] * v[u].re;
+              ai[0] += w[u] * v[u].im;
+            }
+          }
+        } else {
+          // slices zi .. zi + SPL - 1 of a sample: SPL / 2 16-byte loads (nz, z0, zi even)
+          constexpr int H = SPL / 2;
+          float4 v[U][H];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+              v[u][h] = *reinterpret_cast<const float4*>(vals + (idx_t)pp[u] * nz + z0 + zi + 2 * h);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (k + u < k1) {
+#pragma unroll
+              for (int h = 0; h < H; ++h) {
+                ar[2 * h] += w[u] * v[u][h].x;
+                ai[2 * h] += w[u] * v[u][h].y;
+                ar[2 * h + 1] += w[u] * v[u][h].z;
+                ai[2 * h + 1] += w[u] * v[u][h].w;
+              }
+            }
           }
         }
       }
     }
-    tile[zl][cs] = mk(ar, ai);
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) tile[zl * SPL + s][cs] = mk(ar[s], ai[s]);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ZL * CB; e += 256) {
+  for (int e = threadIdx.x; e < ZS * CB; e += 256) {
     const int z = e / CB, c = e - z * CB;
     const idx_t cell = cell0 + c;
-    const int zo = blockIdx.y * ZL + z;
+    const int zo = blockIdx.y * ZS + z;
     if (cell < cells && zo < nzb) grid[(idx_t)zo * cells + cell] = tile[z][c];
   }
 }
@@ -525,9 +555,12 @@ spread_kernel(const cpx<T>* __restrict__ vals, cpx<T>* __restrict__ grid,
 template <typename T>
 constexpr int fftE() { return sizeof(T) == 8 ? 8 : 16; }
 
+// keep > 0: only the outputs at positions [0, keep) and [P - keep, P) are stored (the columns
+// that a following cropped column pass reads); keep = 0 stores every position.
 template <typename T, int P, int ROWS, int DIR>
 __global__ void __launch_bounds__(ROWS * (P / fftE<T>()))
-fft_rows_kernel(cpx<T>* __restrict__ data, idx_t n_rows, const cpx<T>* __restrict__ tw) {
+fft_rows_kernel(cpx<T>* __restrict__ data, idx_t n_rows, const cpx<T>* __restrict__ tw,
+                int keep = 0) {
   using PL = fft::Plan<P, fftE<T>()>;
   constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
   constexpr int REG = fft::row_region<P>();
@@ -548,7 +581,10 @@ fft_rows_kernel(cpx<T>* __restrict__ data, idx_t n_rows, const cpx<T>* __restric
 #pragma unroll
     for (int m = 0; m < E / RL; ++m)
 #pragma unroll
-      for (int r = 0; r < RL; ++r) d[fft::reg_pos<P, TPF, RL>(q, m, r)] = v[m * RL + r];
+      for (int r = 0; r < RL; ++r) {
+        const int pos = fft::reg_pos<P, TPF, RL>(q, m, r);
+        if (keep == 0 || pos < keep || pos >= P - keep) d[pos] = v[m * RL + r];
+      }
 }
 
 template <typename T, int P, int TC, int DIR>
@@ -570,6 +606,43 @@ fft_cols_kernel(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ tw) {
   for (int m = 0; m < E / RL; ++m)
 #pragma unroll
     for (int r = 0; r < RL; ++r) d[(idx_t)fft::reg_pos<P, TPF, RL>(q, m, r) * P] = v[m * RL + r];
+}
+
+// Inverse-direction column transforms of the N columns that survive the crop of a
+// back-projection grid, with the crop and deapodisation as the epilogue:
+//   out[z][my][mx] = Re H[z][(my - N/2) mod P][(mx - N/2) mod P] inv[my] inv[mx],
+// H the 2D transform of the rows already transformed by fft_rows_kernel (keep = N/2).
+// Block (bx, z) takes kept columns mx = bx TC .. bx TC + TC - 1 (those >= N idle).
+template <int P, int TC>
+__global__ void __launch_bounds__(TC * (P / fftE<float>()))
+fft_cols_crop_kernel(const cpx<float>* __restrict__ data, const cpx<float>* __restrict__ tw,
+                     float* __restrict__ out, const float* __restrict__ inv, int N) {
+  using PL = fft::Plan<P, fftE<float>()>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  __shared__ cpx<float> lds[P * TC];
+  const int t = threadIdx.x, c = t % TC, q = t / TC;
+  const int mx = blockIdx.x * TC + c;
+  const bool active = mx < N;
+  const int gx = (mx - N / 2 + P) % P;
+  const cpx<float>* d = data + (idx_t)blockIdx.y * P * P + (active ? gx : 0);
+  cpx<float> v[E];
+#pragma unroll
+  for (int m = 0; m < E / R0; ++m)
+#pragma unroll
+    for (int r = 0; r < R0; ++r)
+      v[m * R0 + r] = active ? d[(idx_t)fft::reg_pos<P, TPF, R0>(q, m, r) * P] : mk(0.f, 0.f);
+  fft::LdsCols<float, TC> L{lds, c};
+  fft::run_stages<PL, 0, +1>(v, q, tw, L);
+  if (!active) return;
+  float* o = out + (idx_t)blockIdx.y * N * N + mx;
+  const float sx = inv[mx];
+#pragma unroll
+  for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int my = (fft::reg_pos<P, TPF, RL>(q, m, r) + N / 2) % P;
+      if (my < N) o[(idx_t)my * N] = v[m * RL + r].re * inv[my] * sx;
+    }
 }
 
 template <typename T>
@@ -823,15 +896,23 @@ hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* ro
   const idx_t cells = (idx_t)gg.M * gg.M;
   const int nl = gg.n_det - 1;
   if (nzb >= 3) {
-    const int zl = nzb > 32 ? 64 : nzb > 16 ? 32 : nzb > 4 ? 16 : 4;
-    const dim3 blocks(nblk(cells, 64), (nzb + zl - 1) / zl);
-#define TOMO_GZ(ZLV)                                                                          \
-  hipLaunchKernelGGL((gather_z_kernel<ZLV>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx, \
-                     wts, lscale, gg.M, nl, nz, z0, nzb)
-    if (zl == 64) TOMO_GZ(64);
-    else if (zl == 32) TOMO_GZ(32);
-    else if (zl == 16) TOMO_GZ(16);
-    else TOMO_GZ(4);
+    // two slices per lane where every 16-byte value load is aligned: nz, z0 and nzb even
+    const bool two = nzb >= 8 && (nz % 2) == 0 && (z0 % 2) == 0 && (nzb % 2) == 0;
+    const int zs = nzb > 32 ? 64 : nzb > 16 ? 32 : nzb > 4 ? 16 : 4;  // slices per block row
+    const dim3 blocks(nblk(cells, 64), (nzb + zs - 1) / zs);
+#define TOMO_GZ(ZLV, SPLV)                                                                     \
+  hipLaunchKernelGGL((gather_z_kernel<ZLV, SPLV>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, \
+                     idx, wts, lscale, gg.M, nl, nz, z0, nzb)
+    if (two) {
+      if (zs == 64) TOMO_GZ(32, 2);
+      else if (zs == 32) TOMO_GZ(16, 2);
+      else TOMO_GZ(8, 2);
+    } else {
+      if (zs == 64) TOMO_GZ(64, 1);
+      else if (zs == 32) TOMO_GZ(32, 1);
+      else if (zs == 16) TOMO_GZ(16, 1);
+      else TOMO_GZ(4, 1);
+    }
 #undef TOMO_GZ
     return hipGetLastError();
   }
@@ -896,6 +977,28 @@ hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* atab, const in
 hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir, const cpx<float>* tw,
                             hipStream_t st) {
 #define CALL(T, PP) fft2d_p<T, PP>(data, batch, dir, tw, st)
+  TOMO_MSWITCH(float, CALL)
+#undef CALL
+}
+template <int P>
+hipError_t fft2d_crop_p(cpx<float>* data, int batch, const cpx<float>* tw, float* out,
+                        const float* inv, int N, hipStream_t st) {
+  constexpr int ROWS = rows_per_block<float>(P);
+  constexpr int TC = cols_per_block<float>(P);
+  constexpr int TPF = fft::Plan<P, fftE<float>()>::TPF;
+  const idx_t n_rows = (idx_t)batch * P;
+  const dim3 gr((unsigned)((n_rows + ROWS - 1) / ROWS));
+  const dim3 gc((unsigned)((N + TC - 1) / TC), batch);
+  hipLaunchKernelGGL((fft_rows_kernel<float, P, ROWS, +1>), gr, dim3(ROWS * TPF), 0, st, data,
+                     n_rows, tw, N / 2);
+  hipLaunchKernelGGL((fft_cols_crop_kernel<P, TC>), gc, dim3(TC * TPF), 0, st, data, tw, out, inv,
+                     N);
+  return hipGetLastError();
+}
+hipError_t launch_fft2d_crop_f32(cpx<float>* data, int M, int batch, const cpx<float>* tw,
+                                 float* out, const float* inv, int N, hipStream_t st) {
+  if (N < 2 || N > M || (N & 1)) return hipErrorInvalidValue;
+#define CALL(T, PP) fft2d_crop_p<PP>(data, batch, tw, out, inv, N, st)
   TOMO_MSWITCH(float, CALL)
 #undef CALL
 }

@@ -201,6 +201,13 @@ hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir,
                             const cpx<float>* tw, hipStream_t st);
 hipError_t launch_fft2d_f64(cpx<double>* data, int M, int batch, int dir,
                             const cpx<double>* tw, hipStream_t st);
+// The 2D inverse-direction transform of a back-projection grid [batch][M][M] followed by the
+// crop to N x N and the deapodisation into out [batch][N][N]: the row pass stores only the
+// columns the crop keeps, the column pass transforms only those and writes the cropped rows.
+// Overwrites the kept columns of data.  Same values as launch_fft2d_f32 (+1) then
+// launch_crop_deapod.
+hipError_t launch_fft2d_crop_f32(cpx<float>* data, int M, int batch, const cpx<float>* tw,
+                                 float* out, const float* inv, int N, hipStream_t st);
 hipError_t launch_crop_deapod(const cpx<float>* grid, float* out, const float* inv,
                               const GridGeom& gg, int nzb, hipStream_t st);
 hipError_t launch_psf_embed(const cpx<double>* grid, cpx<double>* emb, const GridGeom& gg,

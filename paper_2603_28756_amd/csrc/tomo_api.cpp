@@ -388,9 +388,8 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
                               p->at<int>(l.off_cidx), p->at<float>(l.off_cw),
                               ramp ? rampf : nullptr, gg, p->nz, z0 + zb, nzb, st));
     }
-    HIPCHK(p, launch_fft2d_f32(grid, l.M, zc, +1, p->tw32(l.M), st));
-    HIPCHK(p, launch_crop_deapod(grid, out + (size_t)z0 * l.n * l.n, p->at<float>(l.off_deapod),
-                                 gg, zc, st));
+    HIPCHK(p, launch_fft2d_crop_f32(grid, l.M, zc, p->tw32(l.M), out + (size_t)z0 * l.n * l.n,
+                                    p->at<float>(l.off_deapod), l.n, st));
   }
   return TOMO_OK;
 }
