@@ -244,16 +244,44 @@ TOMO_DEV void visit_cell(int ix, int iy, const double* __restrict__ atab,
 }
 
 // Cell-sorted contribution lists (CSR over grid cells): count, then fill at scanned offsets.
+template <typename T>
 __global__ void __launch_bounds__(256)
 csr_count_kernel(int* __restrict__ cnt, const double* __restrict__ atab,
-                 const int2* __restrict__ g0, const float* __restrict__ wx,
-                 const float* __restrict__ wy, int M, int nd, int n_angles, int W) {
+                 const int2* __restrict__ g0, const T* __restrict__ wx,
+                 const T* __restrict__ wy, int M, int nd, int n_angles, int W) {
   const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
   if (cell >= (idx_t)M * M) return;
   const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
   int c = 0;
-  visit_cell<float>(ix, iy, atab, g0, wx, wy, M, nd, n_angles, W, [&](int, float) { ++c; });
+  visit_cell<T>(ix, iy, atab, g0, wx, wy, M, nd, n_angles, W, [&](int, T) { ++c; });
   cnt[cell] = c;
+}
+
+// Weights only (float64), in the same visit order: the lists of the point-spread grid, whose
+// samples all carry the same value.
+__global__ void __launch_bounds__(256)
+csr_fill_w64_kernel(const int* __restrict__ row_ptr, double* __restrict__ wts,
+                    const double* __restrict__ atab, const int2* __restrict__ g0,
+                    const double* __restrict__ wx, const double* __restrict__ wy, int M, int nd,
+                    int n_angles, int W) {
+  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (idx_t)M * M) return;
+  const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
+  int k = row_ptr[cell];
+  visit_cell<double>(ix, iy, atab, g0, wx, wy, M, nd, n_angles, W, [&](int, double w) { wts[k++] = w; });
+}
+
+// Point-spread grid (Sec. 2.1, Eq. 8: the adjoint NUFFT of the all-ones function, every sample
+// weighted 1 / n_det): grid[cell] = sum over the cell's list, in list order, of w c (the
+// cell's samples angle by angle, then along each ray).
+__global__ void __launch_bounds__(256)
+psf_grid_kernel(const int* __restrict__ row_ptr, const double* __restrict__ wts,
+                cpx<double>* __restrict__ grid, idx_t cells, double c) {
+  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= cells) return;
+  double a = 0.0;
+  for (int k = row_ptr[cell], k1 = row_ptr[cell + 1]; k < k1; ++k) a += wts[k] * c;
+  grid[cell] = mk(a, 0.0);
 }
 
 __global__ void __launch_bounds__(256)
@@ -456,99 +484,6 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
     const int zo = blockIdx.y * ZS + z;
     if (cell < cells && zo < nzb) grid[(idx_t)zo * cells + cell] = tile[z][c];
   }
-}
-
-constexpr int SPREAD_ANG_LDS = 2048;
-
-// Gather-spread: H[z][iy][ix] = sum over samples p whose footprint covers cell (ix, iy)
-// of wx[p][ix - g0x] wy[p][iy - g0y] c[z][p], grid index = frequency mod M.
-template <typename T, int ZB, bool CONST>
-__global__ void __launch_bounds__(256)
-spread_kernel(const cpx<T>* __restrict__ vals, cpx<T>* __restrict__ grid,
-              const double* __restrict__ atab, const int2* __restrict__ g0,
-              const T* __restrict__ wx, const T* __restrict__ wy, int M, int nd, int n_angles,
-              int W, int z0, int nzb, idx_t slice_pts, T const_val) {
-  // per-angle grid steps and their reciprocals, once per block (bounds by multiplication)
-  __shared__ float4 ang[SPREAD_ANG_LDS];
-  const float step = (float)M / (float)nd;
-  const bool tab = n_angles <= SPREAD_ANG_LDS;
-  if (tab) {
-    for (int i = threadIdx.x; i < n_angles; i += 256) {
-      const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
-      ang[i] = make_float4(cx, cy, fabsf(cx) > 1e-6f ? 1.f / cx : 0.f, fabsf(cy) > 1e-6f ? 1.f / cy : 0.f);
-    }
-    __syncthreads();
-  }
-  const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
-  if (cell >= (idx_t)M * M) return;
-  const int iy = (int)(cell / M), ix = (int)(cell - (idx_t)iy * M);
-  const int half = M / 2;
-  const int gx = ix < half ? ix : ix - M;
-  const int gy = iy < half ? iy : iy - M;
-  const int nl = nd - 1, lmax = nd / 2 - 1;
-  const float hw = 0.5f * (float)W + 1.5f;  // 1.5 cells of slack over the footprint half-width
-  const float reach = (float)half + hw;
-
-  T ar[ZB], ai[ZB];
-#pragma unroll
-  for (int z = 0; z < ZB; ++z) ar[z] = ai[z] = (T)0;
-
-  for (int sx = -1; sx <= 1; ++sx) {
-    const int gxp = gx + sx * M;
-    if (fabsf((float)gxp) > reach) continue;
-    for (int sy = -1; sy <= 1; ++sy) {
-      const int gyp = gy + sy * M;
-      if (fabsf((float)gyp) > reach) continue;
-      for (int i = 0; i < n_angles; ++i) {
-        float4 a4;
-        if (tab) {
-          a4 = ang[i];
-        } else {
-          const float cx = (float)atab[2 * i] * step, cy = (float)atab[2 * i + 1] * step;
-          a4 = make_float4(cx, cy, fabsf(cx) > 1e-6f ? 1.f / cx : 0.f, fabsf(cy) > 1e-6f ? 1.f / cy : 0.f);
-        }
-        float lo = (float)(-lmax), hi = (float)lmax;
-        if (fabsf(a4.x) > 1e-6f) {
-          const float a = ((float)gxp - hw) * a4.z, b = ((float)gxp + hw) * a4.z;
-          lo = fmaxf(lo, fminf(a, b));
-          hi = fminf(hi, fmaxf(a, b));
-        } else if (fabsf((float)gxp) > hw) {
-          continue;
-        }
-        if (fabsf(a4.y) > 1e-6f) {
-          const float a = ((float)gyp - hw) * a4.w, b = ((float)gyp + hw) * a4.w;
-          lo = fmaxf(lo, fminf(a, b));
-          hi = fminf(hi, fmaxf(a, b));
-        } else if (fabsf((float)gyp) > hw) {
-          continue;
-        }
-        const int l0 = (int)ceilf(lo), l1 = (int)floorf(hi);
-        for (int l = l0; l <= l1; ++l) {
-          const int p = i * nl + (l + lmax);
-          const int2 o = g0[p];
-          const int ox = gxp - o.x, oy = gyp - o.y;
-          if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W) {
-            const T w = wx[(idx_t)p * W + ox] * wy[(idx_t)p * W + oy];
-            if constexpr (CONST) {
-              ar[0] += w * const_val;
-            } else {
-#pragma unroll
-              for (int z = 0; z < ZB; ++z) {
-                if (z < nzb) {
-                  const cpx<T> c = vals[(idx_t)(z0 + z) * slice_pts + p];
-                  ar[z] += w * c.re;
-                  ai[z] += w * c.im;
-                }
-              }
-            }
-          }
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int z = 0; z < ZB; ++z)
-    if (z < nzb) grid[(idx_t)z * M * M + cell] = mk(ar[z], ai[z]);
 }
 
 // ------------------------------------------------------------------- generic 2D C2C FFT
@@ -878,8 +813,8 @@ hipError_t launch_csr_build(const double* atab, const int2* g0, const float* wx,
                             int* scan_sums, hipStream_t st) {
   const idx_t cells = (idx_t)gg.M * gg.M;
   const unsigned nb = nblk(cells, 256);
-  hipLaunchKernelGGL(csr_count_kernel, dim3(nb), dim3(256), 0, st, cnt, atab, g0, wx, wy, gg.M,
-                     gg.n_det, gg.n_angles, gg.W);
+  hipLaunchKernelGGL(csr_count_kernel<float>, dim3(nb), dim3(256), 0, st, cnt, atab, g0, wx, wy,
+                     gg.M, gg.n_det, gg.n_angles, gg.W);
   const int nsb = (int)((cells + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(nsb), dim3(1024), 0, st, cnt, row_ptr, scan_sums,
                      cells);
@@ -888,6 +823,30 @@ hipError_t launch_csr_build(const double* atab, const int2* g0, const float* wx,
   hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, st, row_ptr, scan_sums, cells);
   hipLaunchKernelGGL(csr_fill_kernel, dim3(nb), dim3(256), 0, st, row_ptr, idx, wts, atab, g0,
                      wx, wy, gg.M, gg.n_det, gg.n_angles, gg.W);
+  return hipGetLastError();
+}
+hipError_t launch_psf_lists(const double* atab, const int2* g0, const double* wx,
+                            const double* wy, const GridGeom& gg, int* cnt, int* row_ptr,
+                            double* wts, int* scan_sums, hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  const unsigned nb = nblk(cells, 256);
+  hipLaunchKernelGGL(csr_count_kernel<double>, dim3(nb), dim3(256), 0, st, cnt, atab, g0, wx, wy,
+                     gg.M, gg.n_det, gg.n_angles, gg.W);
+  const int nsb = (int)((cells + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nsb), dim3(1024), 0, st, cnt, row_ptr, scan_sums,
+                     cells);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, scan_sums, nsb,
+                     row_ptr + cells);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, st, row_ptr, scan_sums, cells);
+  hipLaunchKernelGGL(csr_fill_w64_kernel, dim3(nb), dim3(256), 0, st, row_ptr, wts, atab, g0, wx,
+                     wy, gg.M, gg.n_det, gg.n_angles, gg.W);
+  return hipGetLastError();
+}
+hipError_t launch_psf_grid(const int* row_ptr, const double* wts, cpx<double>* grid,
+                           const GridGeom& gg, hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  hipLaunchKernelGGL(psf_grid_kernel, dim3(nblk(cells, 256)), dim3(256), 0, st, row_ptr, wts, grid,
+                     cells, 1.0 / (double)gg.n_det);
   return hipGetLastError();
 }
 hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
@@ -947,18 +906,6 @@ template hipError_t launch_point_table<float>(const double*, int2*, float*, floa
                                               const GridGeom&, hipStream_t);
 template hipError_t launch_point_table<double>(const double*, int2*, double*, double*,
                                                const GridGeom&, hipStream_t);
-
-hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* atab, const int2* g0,
-                                 const double* wx, const double* wy, const GridGeom& gg,
-                                 hipStream_t st) {
-  const idx_t cells = (idx_t)gg.M * gg.M;
-  const idx_t spts = (idx_t)gg.n_angles * (gg.n_det - 1);
-  const double cval = 1.0 / (double)gg.n_det;
-  hipLaunchKernelGGL((spread_kernel<double, 1, true>), dim3(nblk(cells, 256)), dim3(256), 0, st,
-                     (const cpx<double>*)nullptr, grid, atab, g0, wx, wy, gg.M, gg.n_det,
-                     gg.n_angles, gg.W, 0, 1, spts, cval);
-  return hipGetLastError();
-}
 
 #define TOMO_MSWITCH(T, CALL)         \
   switch (M) {                        \

@@ -189,14 +189,19 @@ hipError_t launch_angle_table(const double* angles_dev, double* tab, int n_angle
 hipError_t launch_csr_build(const double* atab, const int2* g0, const float* wx, const float* wy,
                             const GridGeom& gg, int* cnt, int* row_ptr, int* idx, float* wts,
                             int* scan_sums, hipStream_t st);
+// Lists of the point-spread grid (float64 weights, no sample indices: every sample carries
+// the value 1 / n_det): cnt [M*M] scratch, row_ptr [M*M+1], wts [n_samples * W^2].
+hipError_t launch_psf_lists(const double* atab, const int2* g0, const double* wx,
+                            const double* wy, const GridGeom& gg, int* cnt, int* row_ptr,
+                            double* wts, int* scan_sums, hipStream_t st);
+// grid [M*M] complex128 = the point-spread grid summed over those lists (imaginary part 0).
+hipError_t launch_psf_grid(const int* row_ptr, const double* wts, cpx<double>* grid,
+                           const GridGeom& gg, hipStream_t st);
 // grid[z][cell] for slices z0 .. z0+nzb-1 (nzb <= 64) from samples [p][nz] complex64.
 hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
                          const int* idx, const float* wts, const float* lscale,
                          const GridGeom& gg, int nz, int z0, int nzb, hipStream_t st);
 hipError_t launch_deapod_table(float* inv, const GridGeom& gg, hipStream_t st);
-hipError_t launch_spread_psf_f64(cpx<double>* grid, const double* angle_tab, const int2* g0,
-                                 const double* wx, const double* wy, const GridGeom& gg,
-                                 hipStream_t st);
 hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir,
                             const cpx<float>* tw, hipStream_t st);
 hipError_t launch_fft2d_f64(cpx<double>* data, int M, int batch, int dir,

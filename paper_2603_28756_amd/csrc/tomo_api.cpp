@@ -50,6 +50,7 @@ struct Level {
   double L = 0.0, lambda = 0.0;
   size_t off_fk = 0, off_fkn = 0, off_b = 0;
   size_t off_rowptr = 0, off_cidx = 0, off_cw = 0, off_deapod = 0;  // gridding lists
+  size_t off_prow = 0, off_pw = 0;  // point-spread grid lists (row pointers, float64 weights)
   int v_fwd = 1, v_cc = 1, v_inv = 1;  // tile variants of passes R, C, R'
   int chunks = 1;  // slice chunks that passes R, C, R' run through one after the other
 };
@@ -192,7 +193,10 @@ void layout(tomo_plan p) {
     l.off_cidx = take(nnz * sizeof(int));
     l.off_cw = take(nnz * sizeof(float));
     l.off_deapod = take((size_t)l.n * sizeof(float));
-    maxcells = std::max(maxcells, cells);
+    const size_t pcells = (size_t)l.Mpsf * l.Mpsf;
+    l.off_prow = take((pcells + 1) * sizeof(int));
+    l.off_pw = take(nnz * sizeof(double));
+    maxcells = std::max(maxcells, std::max(cells, pcells));
   }
   p->off_cnt = take(maxcells * sizeof(int));
   p->off_scan = take((maxcells / 4096 + 2) * sizeof(int));
@@ -332,6 +336,48 @@ GridGeom bp_geom(tomo_plan p, const Level& l) {
 
 // Geometry-only gridding data of every level: the cell-sorted contribution lists of the
 // back-projection grid and the deapodisation factors (built once per attached workspace).
+// Geometry of level l's point-spread grid: the image doubled (2N, so that every lag of an
+// N x N image is on it), oversampled grid M_psf, the PSF's own Kaiser-Bessel shape.
+GridGeom psf_geom(tomo_plan p, const Level& l) {
+  GridGeom gg;
+  gg.n = 2 * l.n;
+  gg.n_det = l.nd;
+  gg.n_angles = p->g.n_angles;
+  gg.M = l.Mpsf;
+  gg.W = p->g.kb_width;
+  gg.beta = l.beta_psf;
+  gg.c = l.c;
+  gg.stride = 1;
+  return gg;
+}
+
+// The PSF precompute's scratch: grid [M_psf^2] and embedding [P^2] (complex128), and the
+// sample table of the PSF geometry (footprint origins, float64 1D weights).
+struct PsfScratch {
+  cpx<double>* grid;
+  cpx<double>* emb;
+  int2* g0;
+  double *wx, *wy;
+};
+PsfScratch psf_scratch(tomo_plan p, const Level& l) {
+  const size_t npts = (size_t)p->g.n_angles * (l.nd - 1);
+  size_t off = p->off_psf;
+  PsfScratch s;
+  s.grid = p->at<cpx<double>>(off);
+  off += align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>));
+  s.emb = p->at<cpx<double>>(off);
+  off += align_up((size_t)l.P * l.P * sizeof(cpx<double>));
+  s.g0 = p->at<int2>(off);
+  off += align_up(npts * sizeof(int2));
+  s.wx = p->at<double>(off);
+  off += align_up(npts * p->g.kb_width * sizeof(double));
+  s.wy = p->at<double>(off);
+  return s;
+}
+
+// Cell-sorted lists of every level, once per geometry: the back-projection grid's (sample
+// indices and float32 weights) and the point-spread grid's (float64 weights).  Runs on the
+// plan's stream before any PSF precompute of this workspace.
 tomo_status ensure_grids(tomo_plan p) {
   if (p->grids_ready) return TOMO_OK;
   hipStream_t st = p->stream;
@@ -345,6 +391,12 @@ tomo_status ensure_grids(tomo_plan p) {
                                p->at<int>(l.off_rowptr), p->at<int>(l.off_cidx),
                                p->at<float>(l.off_cw), p->at<int>(p->off_scan), st));
     HIPCHK(p, launch_deapod_table(p->at<float>(l.off_deapod), gg, st));
+    const GridGeom pg = psf_geom(p, l);
+    const PsfScratch ps = psf_scratch(p, l);
+    HIPCHK(p, launch_point_table<double>(p->at<double>(p->off_atab), ps.g0, ps.wx, ps.wy, pg, st));
+    HIPCHK(p, launch_psf_lists(p->at<double>(p->off_atab), ps.g0, ps.wx, ps.wy, pg,
+                               p->at<int>(p->off_cnt), p->at<int>(l.off_prow),
+                               p->at<double>(l.off_pw), p->at<int>(p->off_scan), st));
   }
   p->grids_ready = true;
   return TOMO_OK;
@@ -488,28 +540,12 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
 // stay on the device (off_lvl); nothing here waits for the host.
 tomo_status psf_level(tomo_plan p, Level& l, int li) {
   hipStream_t st = p->fstream;
-  GridGeom gg;
-  gg.n = 2 * l.n;
-  gg.n_det = l.nd;
-  gg.n_angles = p->g.n_angles;
-  gg.M = l.Mpsf;
-  gg.W = p->g.kb_width;
-  gg.beta = l.beta_psf;
-  gg.c = l.c;
-  gg.stride = 1;
-  const size_t npts = (size_t)p->g.n_angles * (l.nd - 1);
-  size_t off = p->off_psf;
-  cpx<double>* grid = p->at<cpx<double>>(off);
-  off += align_up((size_t)l.Mpsf * l.Mpsf * sizeof(cpx<double>));
-  cpx<double>* emb = p->at<cpx<double>>(off);
-  off += align_up((size_t)l.P * l.P * sizeof(cpx<double>));
-  int2* g0 = p->at<int2>(off);
-  off += align_up(npts * sizeof(int2));
-  double* wx = p->at<double>(off);
-  off += align_up(npts * gg.W * sizeof(double));
-  double* wy = p->at<double>(off);
-  HIPCHK(p, launch_point_table<double>(p->at<double>(p->off_atab), g0, wx, wy, gg, st));
-  HIPCHK(p, launch_spread_psf_f64(grid, p->at<double>(p->off_atab), g0, wx, wy, gg, st));
+  const GridGeom gg = psf_geom(p, l);
+  const PsfScratch ps = psf_scratch(p, l);
+  cpx<double>* grid = ps.grid;
+  cpx<double>* emb = ps.emb;
+  // spreading of the all-ones function over the level's cell-sorted lists
+  HIPCHK(p, launch_psf_grid(p->at<int>(l.off_prow), p->at<double>(l.off_pw), grid, gg, st));
   HIPCHK(p, launch_fft2d_f64(grid, l.Mpsf, 1, +1, p->tw64(l.Mpsf), st));
   HIPCHK(p, launch_psf_embed(grid, emb, gg, l.n, l.P, st));
   HIPCHK(p, launch_fft2d_f64(emb, l.P, 1, -1, p->tw64(l.P), st));
