@@ -24,6 +24,15 @@
 namespace tomo {
 namespace {
 
+// Hardware workgroup id -> logical block id such that each of the 8 XCDs (own L2 each) gets
+// one contiguous range of logical blocks (a bijection on [0, total)).
+TOMO_DEV int xcd_band_index(int hw, int total) {
+  constexpr int X = 8;
+  const int q = total / X, r = total % X;
+  const int xcd = hw % X, local = hw / X;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 // Modified Bessel function I0 from its power series sum_k ((x/2)^k / k!)^2 (float64).
 __device__ double bessel_i0(double x) {
   const double q = 0.25 * x * x;
@@ -169,6 +178,109 @@ radial_dft_kernel(const float* __restrict__ sino, int nd_full, int nd, int strid
         ghat[((idx_t)i * nl + lidx) * nz + z] = cmul(mk(ar[r], ai[r]), f);
       }
     }
+  }
+}
+
+// ------------------------------------------------------ radial DFT by chirp-z (Bluestein)
+// The same G[row][l] as radial_dft_kernel in O(L log L) per row: with c_j = exp(-pi i j^2 / n)
+// and b_m = exp(+pi i m^2 / n) (n = n_det of the level), 2 kj = k^2 + j^2 - (k - j)^2 gives
+//   X[k] = sum_j x_j exp(-2 pi i k j / n) = c_k sum_j (x_j c_j) b_(k-j),
+// a linear convolution evaluated as a length-L cyclic one (L >= 2n - 1, a power of two):
+// forward FFT of x c (zero beyond n), times B = FFT(b wrapped to [0, L)), inverse FFT.
+// Tables, float64-evaluated once per level (exponents reduced modulo 2n exactly):
+//   chirp[j] = c_j,  fac[l_idx] = c_k post[l_idx] / L (k = l mod n),  bspec = B.
+__global__ void czt_tables_kernel(cpx<float>* __restrict__ chirp, cpx<float>* __restrict__ fac,
+                                  int nd, double c, int stride, int L) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long twon = 2LL * nd;
+  if (m < nd) {
+    double s, co;
+    sincospi(-(double)(((long long)m * m) % twon) / (double)nd, &s, &co);
+    chirp[m] = mk((float)co, (float)s);
+  }
+  if (m < nd - 1) {
+    const int l = m - (nd / 2 - 1);
+    const int k = ((l % nd) + nd) % nd;
+    double s1, c1, s2, c2;
+    sincospi(-(double)(((long long)k * k) % twon) / (double)nd, &s1, &c1);
+    sincospi(2.0 * (double)l * c / (double)nd, &s2, &c2);
+    const double f = 1.0 / ((double)nd * (double)stride * (double)L);
+    fac[m] = mk((float)((c1 * c2 - s1 * s2) * f), (float)((c1 * s2 + s1 * c2) * f));
+  }
+}
+
+// bspec[k] = sum over m in [0, n) and L - m for m in [1, n) of b_m exp(-2 pi i m k / L)
+// (float64, the phase m k reduced modulo L exactly).
+__global__ void czt_bspec_kernel(cpx<float>* __restrict__ bspec, int nd, int L) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  const long long twon = 2LL * nd;
+  double ar = 0.0, ai = 0.0;
+  for (int m = 0; m < nd; ++m) {
+    double sb, cb;
+    sincospi((double)(((long long)m * m) % twon) / (double)nd, &sb, &cb);
+    for (int side = 0; side < (m == 0 ? 1 : 2); ++side) {
+      const long long pos = side == 0 ? m : L - m;
+      double sw, cw;
+      sincospi(-2.0 * (double)((pos * k) % L) / (double)L, &sw, &cw);
+      ar += cb * cw - sb * sw;
+      ai += cb * sw + sb * cw;
+    }
+  }
+  bspec[k] = mk((float)ar, (float)ai);
+}
+
+// Block: R rows of one angle and consecutive slices (so that the slice-innermost output of a
+// frequency is written R values at a time); one row = TPF = L/16 threads.  Rows are taken
+// angle-major (row = angle * nz + slice) in XCD-contiguous block order.
+template <int L>
+constexpr int czt_rows() { return (L / 16) >= 256 ? 1 : 256 / (L / 16); }
+
+template <int L>
+__global__ void __launch_bounds__(czt_rows<L>() * (L / 16))
+radial_czt_kernel(const float* __restrict__ sino, int nd_full, int nd, int stride, int n_angles,
+                  int nz, cpx<float>* __restrict__ ghat, const cpx<float>* __restrict__ chirp,
+                  const cpx<float>* __restrict__ bspec, const cpx<float>* __restrict__ fac,
+                  const cpx<float>* __restrict__ tw) {
+  using PL = fft::Plan<L, 16>;
+  using IPL = fft::RevPlan<PL>;
+  constexpr int TPF = PL::TPF, E = PL::E, R0 = PL::radix(0), RL = PL::radix(PL::NS - 1);
+  constexpr int R = czt_rows<L>(), REG = fft::row_region<L>();
+  static_assert(E == R0, "one first-stage butterfly per thread");
+  __shared__ cpx<float> lds[R * REG];
+  const int t = threadIdx.x, rr = t / TPF, q = t - rr * TPF;
+  const int rows = nz * n_angles;
+  const int nblk_ = (rows + R - 1) / R;
+  const int blk = xcd_band_index(blockIdx.x, nblk_);
+  const int row = blk * R + rr;  // angle-major
+  const bool active = row < rows;
+  const int ang = active ? row / nz : 0, z = active ? row - ang * nz : 0;
+  const float* g = sino + ((idx_t)z * n_angles + ang) * nd_full;
+  cpx<float> v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int j = q + r * TPF;  // positions >= L/2 >= n are the zero padding
+    cpx<float> a = mk(0.f, 0.f);
+    if (2 * r < E && active && j < nd) a = scale(chirp[j], g[(idx_t)j * stride]);
+    v[r] = a;
+  }
+  fft::LdsRow<float> Ls{lds + rr * REG};
+  fft::run_stages<PL, 0, -1, true>(v, q, tw, Ls);
+#pragma unroll
+  for (int m = 0; m < E / RL; ++m)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) v[m * RL + r] = cmul(v[m * RL + r], bspec[fft::reg_pos<L, TPF, RL>(q, m, r)]);
+  fft::run_stages<IPL, 0, +1>(v, q, tw, Ls);
+  if (!active) return;
+  const int nl = nd - 1, lmax = nd / 2 - 1;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = q + r * TPF;  // y_k in the first-stage layout
+    int lidx = -1;
+    if (k <= lmax) lidx = k + lmax;
+    else if (k < nd && k >= nd - lmax) lidx = k - nd + lmax;
+    if (lidx >= 0 && k < nd)
+      ghat[((idx_t)ang * nl + lidx) * nz + z] = cmul(v[r], fac[lidx]);
   }
 }
 
@@ -807,6 +919,39 @@ hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat
   hipLaunchKernelGGL(radial_dft_kernel, grid, dim3(256), 0, st, sino, n_det_full, gg.n_det,
                      gg.stride, rows, gg.n_angles, nz, ghat, dft_tab, post);
   return hipGetLastError();
+}
+int czt_length(int nd) {
+  int L = 256;
+  while (L < 2 * nd - 1) L <<= 1;
+  return L;
+}
+hipError_t launch_czt_tables(cpx<float>* chirp, cpx<float>* fac, cpx<float>* bspec,
+                             const GridGeom& gg, hipStream_t st) {
+  const int L = czt_length(gg.n_det);
+  hipLaunchKernelGGL(czt_tables_kernel, dim3(nblk(gg.n_det, 256)), dim3(256), 0, st, chirp, fac,
+                     gg.n_det, gg.c, gg.stride, L);
+  hipLaunchKernelGGL(czt_bspec_kernel, dim3(nblk(L, 128)), dim3(128), 0, st, bspec, gg.n_det, L);
+  return hipGetLastError();
+}
+hipError_t launch_radial_czt(const float* sino, int n_det_full, cpx<float>* ghat,
+                             const cpx<float>* chirp, const cpx<float>* bspec,
+                             const cpx<float>* fac, const cpx<float>* tw, const GridGeom& gg,
+                             int nz, hipStream_t st) {
+  const int L = czt_length(gg.n_det);
+  const int rows = nz * gg.n_angles;
+#define TOMO_CZT(LL)                                                                              \
+  case LL: {                                                                                      \
+    constexpr int R = czt_rows<LL>();                                                             \
+    hipLaunchKernelGGL((radial_czt_kernel<LL>), dim3((unsigned)((rows + R - 1) / R)),               \
+                       dim3(R * (LL / 16)), 0, st, sino, n_det_full, gg.n_det, gg.stride,         \
+                       gg.n_angles, nz, ghat, chirp, bspec, fac, tw);                              \
+    return hipGetLastError();                                                                     \
+  }
+  switch (L) {
+    TOMO_CZT(256) TOMO_CZT(512) TOMO_CZT(1024) TOMO_CZT(2048) TOMO_CZT(4096) TOMO_CZT(8192)
+  }
+#undef TOMO_CZT
+  return hipErrorInvalidValue;
 }
 hipError_t launch_csr_build(const double* atab, const int2* g0, const float* wx, const float* wy,
                             const GridGeom& gg, int* cnt, int* row_ptr, int* idx, float* wts,

@@ -177,6 +177,17 @@ struct GridGeom {
 
 hipError_t launch_radial_tables(cpx<float>* dft_tab, cpx<float>* post, float* rampf,
                                 const GridGeom& gg, int ramp, hipStream_t st);
+// Radial DFT by chirp-z: L = czt_length(n_det) (the smallest power of two >= max(256,
+// 2 n_det - 1)); tables chirp [n_det], fac [n_det - 1], bspec [L] per level (float64-evaluated,
+// launch_czt_tables); tw = the float32 twiddle table of length L.  Same output as
+// launch_radial_dft (post without the ramp).
+int czt_length(int nd);
+hipError_t launch_czt_tables(cpx<float>* chirp, cpx<float>* fac, cpx<float>* bspec,
+                             const GridGeom& gg, hipStream_t st);
+hipError_t launch_radial_czt(const float* sino, int n_det_full, cpx<float>* ghat,
+                             const cpx<float>* chirp, const cpx<float>* bspec,
+                             const cpx<float>* fac, const cpx<float>* tw, const GridGeom& gg,
+                             int nz, hipStream_t st);
 hipError_t launch_radial_dft(const float* sino, int n_det_full, cpx<float>* ghat,
                              const cpx<float>* dft_tab, const cpx<float>* post,
                              const GridGeom& gg, int nz, hipStream_t st);

@@ -51,6 +51,7 @@ struct Level {
   size_t off_fk = 0, off_fkn = 0, off_b = 0;
   size_t off_rowptr = 0, off_cidx = 0, off_cw = 0, off_deapod = 0;  // gridding lists
   size_t off_prow = 0, off_pw = 0;  // point-spread grid lists (row pointers, float64 weights)
+  size_t off_czc = 0, off_czf = 0, off_czb = 0;  // radial chirp-z tables (chirp, factor, B)
   int v_fwd = 1, v_cc = 1, v_inv = 1;  // tile variants of passes R, C, R'
   int chunks = 1;  // slice chunks that passes R, C, R' run through one after the other
 };
@@ -193,6 +194,9 @@ void layout(tomo_plan p) {
     l.off_cidx = take(nnz * sizeof(int));
     l.off_cw = take(nnz * sizeof(float));
     l.off_deapod = take((size_t)l.n * sizeof(float));
+    l.off_czc = take((size_t)l.nd * sizeof(cpx<float>));
+    l.off_czf = take((size_t)l.nd * sizeof(cpx<float>));
+    l.off_czb = take((size_t)czt_length(l.nd) * sizeof(cpx<float>));
     const size_t pcells = (size_t)l.Mpsf * l.Mpsf;
     l.off_prow = take((pcells + 1) * sizeof(int));
     l.off_pw = take(nnz * sizeof(double));
@@ -391,6 +395,9 @@ tomo_status ensure_grids(tomo_plan p) {
                                p->at<int>(l.off_rowptr), p->at<int>(l.off_cidx),
                                p->at<float>(l.off_cw), p->at<int>(p->off_scan), st));
     HIPCHK(p, launch_deapod_table(p->at<float>(l.off_deapod), gg, st));
+    if (czt_length(l.nd) <= kMaxGrid)
+      HIPCHK(p, launch_czt_tables(p->at<cpx<float>>(l.off_czc), p->at<cpx<float>>(l.off_czf),
+                                  p->at<cpx<float>>(l.off_czb), gg, st));
     const GridGeom pg = psf_geom(p, l);
     const PsfScratch ps = psf_scratch(p, l);
     HIPCHK(p, launch_point_table<double>(p->at<double>(p->off_atab), ps.g0, ps.wx, ps.wy, pg, st));
@@ -426,7 +433,15 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
     cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
     cpx<float>* post = p->at<cpx<float>>(p->off_post);
     HIPCHK(p, launch_radial_tables(tab, post, rampf, gg, 0, st));
-    HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
+    // the radial DFT by chirp-z (two FFTs of length L per row); the direct sum where L would
+    // exceed the largest transform
+    const int L = czt_length(l.nd);
+    if (L <= kMaxGrid)
+      HIPCHK(p, launch_radial_czt(sino, p->g.n_det, ghat, p->at<cpx<float>>(l.off_czc),
+                                  p->at<cpx<float>>(l.off_czb), p->at<cpx<float>>(l.off_czf),
+                                  p->tw32(L), gg, p->nz, st));
+    else
+      HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
   }
   const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
   int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / slice_grid);
