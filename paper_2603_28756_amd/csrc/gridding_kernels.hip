@@ -508,21 +508,24 @@ gather_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid
 
 // Same sums with lanes over slices: a wave walks the lists of 64/ZL cells at a time, each
 // group of ZL lanes reading ZL x SPL consecutive slices of a sample (one contiguous line; SPL
-// slices per lane in one 8- or 16-byte load); results are transposed through LDS so that each
+// slices per lane in 8- or 16-byte loads); results are transposed through LDS so that each
 // slice's row of 64 cells is written contiguously.  The walk is bound by the latency of its
 // dependent loads (list bounds, then entries, then values), so more cells per wave step (two
 // slices per lane) means fewer rounds for the same sums.  Every sum runs in list order.
-template <int ZL, int SPL>
+// DUAL: one walk gives both the plain sums (grid, lscale unused) and the sums with each
+// sample weighted by lscale[l] (grid2): R* g and the ramp-filtered back-projection.
+template <int ZL, int SPL, bool DUAL>
 __global__ void __launch_bounds__(256)
 gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid,
-                const int* __restrict__ row_ptr, const int* __restrict__ idx,
-                const float* __restrict__ wts, const float* __restrict__ lscale, int M, int nl,
-                int nz, int z0, int nzb) {
+                cpx<float>* __restrict__ grid2, const int* __restrict__ row_ptr,
+                const int* __restrict__ idx, const float* __restrict__ wts,
+                const float* __restrict__ lscale, int M, int nl, int nz, int z0, int nzb) {
   static_assert(SPL == 1 || SPL == 2 || SPL == 4, "slices per lane");
   constexpr int G = 64 / ZL;   // cells per wave step
   constexpr int CB = 64;       // cells per block
   constexpr int ZS = ZL * SPL; // slices per block row
-  __shared__ cpx<float> tile[ZS][CB + 1];
+  constexpr int NO = DUAL ? 2 : 1;
+  __shared__ cpx<float> tile[NO][ZS][CB + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane / ZL, zl = lane - g * ZL;
   const idx_t cells = (idx_t)M * M;
@@ -530,9 +533,11 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
   const int zi = blockIdx.y * ZS + zl * SPL;  // first slice of this lane
   for (int cs = wave * G + g; cs < CB; cs += 4 * G) {
     const idx_t cell = cell0 + cs;
-    float ar[SPL], ai[SPL];
+    float ar[NO][SPL], ai[NO][SPL];
 #pragma unroll
-    for (int s = 0; s < SPL; ++s) ar[s] = ai[s] = 0.f;
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) ar[o][s] = ai[o][s] = 0.f;
     if (cell < cells && zi < nzb) {
       const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
       // eight entries per step: their indices and weights first, then eight independent
@@ -540,46 +545,48 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
       constexpr int U = 8;
       for (int k = k0; k < k1; k += U) {
         int pp[U];
-        float w[U];
+        float w[NO][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool in = k + u < k1;
           pp[u] = in ? idx[k + u] : 0;
-          w[u] = in ? wts[k + u] : 0.f;
+          w[0][u] = in ? wts[k + u] : 0.f;
         }
-        if (lscale) {
+        if (DUAL || lscale) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) w[u] *= lscale[pp[u] % nl];
+          for (int u = 0; u < U; ++u) w[NO - 1][u] = w[0][u] * lscale[pp[u] % nl];
         }
-        if constexpr (SPL == 1) {
-          cpx<float> v[U];
+        constexpr int H = SPL == 1 ? 1 : SPL / 2;
+        float4 v[U][H];
+        cpx<float> v1[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) v[u] = vals[(idx_t)pp[u] * nz + z0 + zi];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (k + u < k1) {
-              ar[0] += w[u] * v[u].re;
-              ai[0] += w[u] * v[u].im;
-            }
-          }
-        } else {
-          // slices zi .. zi + SPL - 1 of a sample: SPL / 2 16-byte loads (nz, z0, zi even)
-          constexpr int H = SPL / 2;
-          float4 v[U][H];
-#pragma unroll
-          for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+          if constexpr (SPL == 1) {
+            v1[u] = vals[(idx_t)pp[u] * nz + z0 + zi];
+          } else {
+            // slices zi .. zi + SPL - 1 of a sample: 16-byte loads (nz, z0 and zi are even)
 #pragma unroll
             for (int h = 0; h < H; ++h)
               v[u][h] = *reinterpret_cast<const float4*>(vals + (idx_t)pp[u] * nz + z0 + zi + 2 * h);
+          }
+        }
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (k + u < k1) {
+        for (int u = 0; u < U; ++u) {
+          if (k + u < k1) {
 #pragma unroll
-              for (int h = 0; h < H; ++h) {
-                ar[2 * h] += w[u] * v[u][h].x;
-                ai[2 * h] += w[u] * v[u][h].y;
-                ar[2 * h + 1] += w[u] * v[u][h].z;
-                ai[2 * h + 1] += w[u] * v[u][h].w;
+            for (int o = 0; o < NO; ++o) {
+              const float wo = w[o][u];
+              if constexpr (SPL == 1) {
+                ar[o][0] += wo * v1[u].re;
+                ai[o][0] += wo * v1[u].im;
+              } else {
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                  ar[o][2 * h] += wo * v[u][h].x;
+                  ai[o][2 * h] += wo * v[u][h].y;
+                  ar[o][2 * h + 1] += wo * v[u][h].z;
+                  ai[o][2 * h + 1] += wo * v[u][h].w;
+                }
               }
             }
           }
@@ -587,14 +594,19 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
       }
     }
 #pragma unroll
-    for (int s = 0; s < SPL; ++s) tile[zl * SPL + s][cs] = mk(ar[s], ai[s]);
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) tile[o][zl * SPL + s][cs] = mk(ar[o][s], ai[o][s]);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < ZS * CB; e += 256) {
     const int z = e / CB, c = e - z * CB;
     const idx_t cell = cell0 + c;
     const int zo = blockIdx.y * ZS + z;
-    if (cell < cells && zo < nzb) grid[(idx_t)zo * cells + cell] = tile[z][c];
+    if (cell < cells && zo < nzb) {
+      grid[(idx_t)zo * cells + cell] = tile[0][z][c];
+      if constexpr (DUAL) grid2[(idx_t)zo * cells + cell] = tile[NO - 1][z][c];
+    }
   }
 }
 
@@ -1004,9 +1016,9 @@ hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* ro
     const bool two = nzb >= 8 && (nz % 2) == 0 && (z0 % 2) == 0 && (nzb % 2) == 0;
     const int zs = nzb > 32 ? 64 : nzb > 16 ? 32 : nzb > 4 ? 16 : 4;  // slices per block row
     const dim3 blocks(nblk(cells, 64), (nzb + zs - 1) / zs);
-#define TOMO_GZ(ZLV, SPLV)                                                                     \
-  hipLaunchKernelGGL((gather_z_kernel<ZLV, SPLV>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, \
-                     idx, wts, lscale, gg.M, nl, nz, z0, nzb)
+#define TOMO_GZ(ZLV, SPLV)                                                                        \
+  hipLaunchKernelGGL((gather_z_kernel<ZLV, SPLV, false>), blocks, dim3(256), 0, st, ghat, grid,   \
+                     nullptr, row_ptr, idx, wts, lscale, gg.M, nl, nz, z0, nzb)
     if (two) {
       if (zs == 64) TOMO_GZ(32, 2);
       else if (zs == 32) TOMO_GZ(16, 2);
@@ -1032,6 +1044,32 @@ hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* ro
                        wts, lscale, gg.M, nl, nz, z0, nzb);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_gather_dual(const cpx<float>* ghat, cpx<float>* grid, cpx<float>* grid_ramp,
+                              const int* row_ptr, const int* idx, const float* wts,
+                              const float* lscale, const GridGeom& gg, int nz, int z0, int nzb,
+                              hipStream_t st) {
+  const idx_t cells = (idx_t)gg.M * gg.M;
+  const int nl = gg.n_det - 1;
+  if (nzb < 1 || nzb > 64) return hipErrorInvalidValue;
+  const bool two = nzb >= 8 && (nz % 2) == 0 && (z0 % 2) == 0 && (nzb % 2) == 0;
+  const int zs = nzb > 32 ? 64 : nzb > 16 ? 32 : nzb > 4 ? 16 : 4;
+  const dim3 blocks(nblk(cells, 64), (nzb + zs - 1) / zs);
+#define TOMO_GZ(ZLV, SPLV)                                                                        \
+  hipLaunchKernelGGL((gather_z_kernel<ZLV, SPLV, true>), blocks, dim3(256), 0, st, ghat, grid,    \
+                     grid_ramp, row_ptr, idx, wts, lscale, gg.M, nl, nz, z0, nzb)
+  if (two) {
+    if (zs == 64) TOMO_GZ(32, 2);
+    else if (zs == 32) TOMO_GZ(16, 2);
+    else TOMO_GZ(8, 2);
+  } else {
+    if (zs == 64) TOMO_GZ(64, 1);
+    else if (zs == 32) TOMO_GZ(32, 1);
+    else if (zs == 16) TOMO_GZ(16, 1);
+    else TOMO_GZ(4, 1);
+  }
+#undef TOMO_GZ
   return hipGetLastError();
 }
 hipError_t launch_deapod_table(float* inv, const GridGeom& gg, hipStream_t st) {

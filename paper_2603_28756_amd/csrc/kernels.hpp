@@ -212,6 +212,12 @@ hipError_t launch_psf_grid(const int* row_ptr, const double* wts, cpx<double>* g
 hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
                          const int* idx, const float* wts, const float* lscale,
                          const GridGeom& gg, int nz, int z0, int nzb, hipStream_t st);
+// Both grids of one list walk: grid (R* g) and grid_ramp (every sample weighted by lscale, the
+// ramp filter); the sums equal those of two launch_gather calls.  nzb 1..64.
+hipError_t launch_gather_dual(const cpx<float>* ghat, cpx<float>* grid, cpx<float>* grid_ramp,
+                              const int* row_ptr, const int* idx, const float* wts,
+                              const float* lscale, const GridGeom& gg, int nz, int z0, int nzb,
+                              hipStream_t st);
 hipError_t launch_deapod_table(float* inv, const GridGeom& gg, hipStream_t st);
 hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir,
                             const cpx<float>* tw, hipStream_t st);

@@ -227,7 +227,7 @@ void layout(tomo_plan p) {
   for (const Level& l : p->lv) {
     const size_t s1 = align_up((size_t)p->nz * l.n * (l.P / 2) * 8);
     const size_t hot = 2 * s1;
-    const size_t bp = (size_t)l.M * l.M * sizeof(cpx<float>);
+    const size_t bp = 2 * (size_t)l.M * l.M * sizeof(cpx<float>);  // R* g and FBP grids of a slice
     const size_t npts = (size_t)na * (l.nd - 1);
     scratch = std::max(scratch, std::max(hot, bp));
   }
@@ -421,6 +421,61 @@ tomo_status backproject_level(tomo_plan p, const Level& l, const float* sino, fl
   return s;
 }
 
+// Radial spectrum of level l's projections into ghat (and the ramp weights into rampf).
+tomo_status radial_spectrum(tomo_plan p, const Level& l, const float* sino) {
+  hipStream_t st = p->stream;
+  const GridGeom gg = bp_geom(p, l);
+  cpx<float>* ghat = p->at<cpx<float>>(p->off_ghat);
+  cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
+  cpx<float>* post = p->at<cpx<float>>(p->off_post);
+  HIPCHK(p, launch_radial_tables(tab, post, p->at<float>(p->off_rampf), gg, 0, st));
+  // the radial DFT by chirp-z (two FFTs of length L per row); the direct sum where L would
+  // exceed the largest transform
+  const int L = czt_length(l.nd);
+  if (L <= kMaxGrid)
+    HIPCHK(p, launch_radial_czt(sino, p->g.n_det, ghat, p->at<cpx<float>>(l.off_czc),
+                                p->at<cpx<float>>(l.off_czb), p->at<cpx<float>>(l.off_czf),
+                                p->tw32(L), gg, p->nz, st));
+  else
+    HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
+  return TOMO_OK;
+}
+
+// R* g (out_b) and the FBP (out_fbp) of level l from one radial spectrum and one walk of the
+// gridding lists per slice chunk (the scratch holds both grids of a chunk).
+tomo_status backproject_level_dual_impl(tomo_plan p, const Level& l, const float* sino,
+                                        float* out_b, float* out_fbp) {
+  hipStream_t st = p->stream;
+  tomo_status s = ensure_grids(p);
+  if (s == TOMO_OK) s = radial_spectrum(p, l, sino);
+  if (s != TOMO_OK) return s;
+  const GridGeom gg = bp_geom(p, l);
+  const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
+  int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / (2 * slice_grid));
+  if (chunk > 64) chunk = 64;
+  if (chunk < 1) return fail(p, TOMO_ERR_INTERNAL, "scratch too small for two grid slices");
+  cpx<float>* grid = p->at<cpx<float>>(p->off_scratch);
+  cpx<float>* grid2 = grid + (size_t)chunk * l.M * l.M;
+  for (int z0 = 0; z0 < p->nz; z0 += chunk) {
+    const int zc = std::min(chunk, p->nz - z0);
+    HIPCHK(p, launch_gather_dual(p->at<cpx<float>>(p->off_ghat), grid, grid2, p->at<int>(l.off_rowptr),
+                                 p->at<int>(l.off_cidx), p->at<float>(l.off_cw),
+                                 p->at<float>(p->off_rampf), gg, p->nz, z0, zc, st));
+    HIPCHK(p, launch_fft2d_crop_f32(grid, l.M, zc, p->tw32(l.M), out_b + (size_t)z0 * l.n * l.n,
+                                    p->at<float>(l.off_deapod), l.n, st));
+    HIPCHK(p, launch_fft2d_crop_f32(grid2, l.M, zc, p->tw32(l.M), out_fbp + (size_t)z0 * l.n * l.n,
+                                    p->at<float>(l.off_deapod), l.n, st));
+  }
+  return TOMO_OK;
+}
+tomo_status backproject_level_dual(tomo_plan p, const Level& l, const float* sino, float* out_b,
+                                   float* out_fbp) {
+  const int ti = tbegin(p, TOMO_T_BACKPROJECT);
+  const tomo_status s = backproject_level_dual_impl(p, l, sino, out_b, out_fbp);
+  tend(p, ti);
+  return s;
+}
+
 tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sino, float* out,
                                    int ramp, bool reuse) {
   hipStream_t st = p->stream;
@@ -429,20 +484,7 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
   const GridGeom gg = bp_geom(p, l);
   cpx<float>* ghat = p->at<cpx<float>>(p->off_ghat);
   float* rampf = p->at<float>(p->off_rampf);
-  if (!reuse) {
-    cpx<float>* tab = p->at<cpx<float>>(p->off_dfttab);
-    cpx<float>* post = p->at<cpx<float>>(p->off_post);
-    HIPCHK(p, launch_radial_tables(tab, post, rampf, gg, 0, st));
-    // the radial DFT by chirp-z (two FFTs of length L per row); the direct sum where L would
-    // exceed the largest transform
-    const int L = czt_length(l.nd);
-    if (L <= kMaxGrid)
-      HIPCHK(p, launch_radial_czt(sino, p->g.n_det, ghat, p->at<cpx<float>>(l.off_czc),
-                                  p->at<cpx<float>>(l.off_czb), p->at<cpx<float>>(l.off_czf),
-                                  p->tw32(L), gg, p->nz, st));
-    else
-      HIPCHK(p, launch_radial_dft(sino, p->g.n_det, ghat, tab, post, gg, p->nz, st));
-  }
+  if (!reuse && (s = radial_spectrum(p, l, sino)) != TOMO_OK) return s;
   const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
   int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / slice_grid);
   if (chunk < 1) return fail(p, TOMO_ERR_INTERNAL, "scratch too small for one grid slice");
@@ -1098,12 +1140,14 @@ tomo_status tomo_reconstruct(tomo_plan p, const float* sino, float* x,
     const Level& l = p->lv[li];
     const size_t vol = (size_t)p->nz * l.n * l.n;
     float* b = p->at<float>(l.off_b);
-    if ((s = backproject_level(p, l, sino, b, 0)) != TOMO_OK) return s;
+    const bool fbp = li == 0 && (opts->init == TOMO_INIT_FBP || opts->init == TOMO_INIT_LEARNED);
+    if (fbp) s = backproject_level_dual(p, l, sino, b, p->xbuf(cur));  // b and the FBP start
+    else s = backproject_level(p, l, sino, b, 0);
+    if (s != TOMO_OK) return s;
     HIPCHK(p, launch_sumsq_strided(sino, (idx_t)p->nz * p->g.n_angles, l.nd, l.stride,
                                    1.0 / l.stride, p->partials(), sc + SC_GG, st));
     if (li == 0) {
-      if (opts->init == TOMO_INIT_FBP || opts->init == TOMO_INIT_LEARNED) {
-        if ((s = backproject_level(p, l, sino, p->xbuf(cur), 1, true)) != TOMO_OK) return s;
+      if (fbp) {
         if (opts->init == TOMO_INIT_LEARNED) {
           learned_state = in_domain(p, l, net) ? TOMO_LEARNED_TESTED : TOMO_LEARNED_OUT_OF_DOMAIN;
           if (learned_state == TOMO_LEARNED_TESTED &&
