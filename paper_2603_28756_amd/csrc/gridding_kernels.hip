@@ -412,6 +412,15 @@ csr_fill_kernel(const int* __restrict__ row_ptr, int* __restrict__ idx, float* _
   });
 }
 
+// Ramp-filtered list weights (Sec. 2.2, the FBP start): out[k] = wts[k] rampf[l] for the
+// radial index l = idx[k] mod (n_det - 1) of the entry's sample.
+__global__ void csr_ramp_kernel(const int* __restrict__ idx, const float* __restrict__ wts,
+                                const float* __restrict__ rampf, idx_t nnz, int nl,
+                                float* __restrict__ out) {
+  const idx_t k = (idx_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < nnz) out[k] = wts[k] * rampf[idx[k] % nl];
+}
+
 // Exclusive scan of n ints (block-local scans of 4096 elements, then their sums).
 constexpr int SCAN_PER_BLOCK = 4096;
 __global__ void __launch_bounds__(1024)
@@ -473,14 +482,13 @@ __global__ void scan_add_kernel(int* __restrict__ out, const int* __restrict__ s
   if (i < n) out[i] += sums[i / SCAN_PER_BLOCK];
 }
 
-// H[z][cell] = sum over the cell's list of w * c[p][z0 + z] (times the per-l factor lscale[p mod
-// (nd-1)] when given), z < nzb; samples hold all slices contiguously.
+// H[z][cell] = sum over the cell's list of w * c[p][z0 + z], z < nzb (w: the list's plain or
+// ramp-weighted weights); samples hold all slices contiguously.
 template <int ZB>
 __global__ void __launch_bounds__(256)
 gather_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid,
               const int* __restrict__ row_ptr, const int* __restrict__ idx,
-              const float* __restrict__ wts, const float* __restrict__ lscale, int M, int nl,
-              int nz, int z0, int nzb) {
+              const float* __restrict__ wts, int M, int nz, int z0, int nzb) {
   const idx_t cell = (idx_t)blockIdx.x * 256 + threadIdx.x;
   if (cell >= (idx_t)M * M) return;
   float ar[ZB], ai[ZB];
@@ -489,8 +497,7 @@ gather_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid
   const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
   for (int k = k0; k < k1; ++k) {
     const int p = idx[k];
-    float w = wts[k];
-    if (lscale) w *= lscale[p % nl];
+    const float w = wts[k];
     const cpx<float>* c = vals + (idx_t)p * nz + z0;
 #pragma unroll
     for (int z = 0; z < ZB; ++z) {
@@ -512,14 +519,14 @@ gather_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid
 // slice's row of 64 cells is written contiguously.  The walk is bound by the latency of its
 // dependent loads (list bounds, then entries, then values), so more cells per wave step (two
 // slices per lane) means fewer rounds for the same sums.  Every sum runs in list order.
-// DUAL: one walk gives both the plain sums (grid, lscale unused) and the sums with each
-// sample weighted by lscale[l] (grid2): R* g and the ramp-filtered back-projection.
+// DUAL: one walk gives the sums with the list weights wts (grid) and with the second weights
+// wts2 (grid2): R* g and the ramp-filtered back-projection.
 template <int ZL, int SPL, bool DUAL>
 __global__ void __launch_bounds__(256)
 gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ grid,
                 cpx<float>* __restrict__ grid2, const int* __restrict__ row_ptr,
                 const int* __restrict__ idx, const float* __restrict__ wts,
-                const float* __restrict__ lscale, int M, int nl, int nz, int z0, int nzb) {
+                const float* __restrict__ wts2, int M, int nz, int z0, int nzb) {
   static_assert(SPL == 1 || SPL == 2 || SPL == 4, "slices per lane");
   constexpr int G = 64 / ZL;   // cells per wave step
   constexpr int CB = 64;       // cells per block
@@ -551,10 +558,7 @@ gather_z_kernel(const cpx<float>* __restrict__ vals, cpx<float>* __restrict__ gr
           const bool in = k + u < k1;
           pp[u] = in ? idx[k + u] : 0;
           w[0][u] = in ? wts[k + u] : 0.f;
-        }
-        if (DUAL || lscale) {
-#pragma unroll
-          for (int u = 0; u < U; ++u) w[NO - 1][u] = w[0][u] * lscale[pp[u] % nl];
+          if constexpr (DUAL) w[1][u] = in ? wts2[k + u] : 0.f;
         }
         constexpr int H = SPL == 1 ? 1 : SPL / 2;
         float4 v[U][H];
@@ -999,6 +1003,12 @@ hipError_t launch_psf_lists(const double* atab, const int2* g0, const double* wx
                      wy, gg.M, gg.n_det, gg.n_angles, gg.W);
   return hipGetLastError();
 }
+hipError_t launch_csr_ramp(const int* idx, const float* wts, const float* rampf, idx_t nnz,
+                           const GridGeom& gg, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(csr_ramp_kernel, dim3(nblk(nnz, 256)), dim3(256), 0, st, idx, wts, rampf, nnz,
+                     gg.n_det - 1, out);
+  return hipGetLastError();
+}
 hipError_t launch_psf_grid(const int* row_ptr, const double* wts, cpx<double>* grid,
                            const GridGeom& gg, hipStream_t st) {
   const idx_t cells = (idx_t)gg.M * gg.M;
@@ -1007,10 +1017,9 @@ hipError_t launch_psf_grid(const int* row_ptr, const double* wts, cpx<double>* g
   return hipGetLastError();
 }
 hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
-                         const int* idx, const float* wts, const float* lscale,
-                         const GridGeom& gg, int nz, int z0, int nzb, hipStream_t st) {
+                         const int* idx, const float* wts, const GridGeom& gg, int nz, int z0,
+                         int nzb, hipStream_t st) {
   const idx_t cells = (idx_t)gg.M * gg.M;
-  const int nl = gg.n_det - 1;
   if (nzb >= 3) {
     // two slices per lane where every 16-byte value load is aligned: nz, z0 and nzb even
     const bool two = nzb >= 8 && (nz % 2) == 0 && (z0 % 2) == 0 && (nzb % 2) == 0;
@@ -1018,7 +1027,7 @@ hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* ro
     const dim3 blocks(nblk(cells, 64), (nzb + zs - 1) / zs);
 #define TOMO_GZ(ZLV, SPLV)                                                                        \
   hipLaunchKernelGGL((gather_z_kernel<ZLV, SPLV, false>), blocks, dim3(256), 0, st, ghat, grid,   \
-                     nullptr, row_ptr, idx, wts, lscale, gg.M, nl, nz, z0, nzb)
+                     nullptr, row_ptr, idx, wts, nullptr, gg.M, nz, z0, nzb)
     if (two) {
       if (zs == 64) TOMO_GZ(32, 2);
       else if (zs == 32) TOMO_GZ(16, 2);
@@ -1035,30 +1044,29 @@ hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* ro
   const dim3 blocks(nblk(cells, 256));
   if (nzb <= 1)
     hipLaunchKernelGGL((gather_kernel<1>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx, wts,
-                       lscale, gg.M, nl, nz, z0, nzb);
+                       gg.M, nz, z0, nzb);
   else if (nzb <= 4)
     hipLaunchKernelGGL((gather_kernel<4>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx, wts,
-                       lscale, gg.M, nl, nz, z0, nzb);
+                       gg.M, nz, z0, nzb);
   else if (nzb <= 16)
     hipLaunchKernelGGL((gather_kernel<16>), blocks, dim3(256), 0, st, ghat, grid, row_ptr, idx,
-                       wts, lscale, gg.M, nl, nz, z0, nzb);
+                       wts, gg.M, nz, z0, nzb);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 hipError_t launch_gather_dual(const cpx<float>* ghat, cpx<float>* grid, cpx<float>* grid_ramp,
                               const int* row_ptr, const int* idx, const float* wts,
-                              const float* lscale, const GridGeom& gg, int nz, int z0, int nzb,
+                              const float* wts_ramp, const GridGeom& gg, int nz, int z0, int nzb,
                               hipStream_t st) {
   const idx_t cells = (idx_t)gg.M * gg.M;
-  const int nl = gg.n_det - 1;
   if (nzb < 1 || nzb > 64) return hipErrorInvalidValue;
   const bool two = nzb >= 8 && (nz % 2) == 0 && (z0 % 2) == 0 && (nzb % 2) == 0;
   const int zs = nzb > 32 ? 64 : nzb > 16 ? 32 : nzb > 4 ? 16 : 4;
   const dim3 blocks(nblk(cells, 64), (nzb + zs - 1) / zs);
 #define TOMO_GZ(ZLV, SPLV)                                                                        \
   hipLaunchKernelGGL((gather_z_kernel<ZLV, SPLV, true>), blocks, dim3(256), 0, st, ghat, grid,    \
-                     grid_ramp, row_ptr, idx, wts, lscale, gg.M, nl, nz, z0, nzb)
+                     grid_ramp, row_ptr, idx, wts, wts_ramp, gg.M, nz, z0, nzb)
   if (two) {
     if (zs == 64) TOMO_GZ(32, 2);
     else if (zs == 32) TOMO_GZ(16, 2);

@@ -210,13 +210,16 @@ hipError_t launch_psf_grid(const int* row_ptr, const double* wts, cpx<double>* g
                            const GridGeom& gg, hipStream_t st);
 // grid[z][cell] for slices z0 .. z0+nzb-1 (nzb <= 64) from samples [p][nz] complex64.
 hipError_t launch_gather(const cpx<float>* ghat, cpx<float>* grid, const int* row_ptr,
-                         const int* idx, const float* wts, const float* lscale,
-                         const GridGeom& gg, int nz, int z0, int nzb, hipStream_t st);
-// Both grids of one list walk: grid (R* g) and grid_ramp (every sample weighted by lscale, the
+                         const int* idx, const float* wts, const GridGeom& gg, int nz, int z0,
+                         int nzb, hipStream_t st);
+// out[k] = wts[k] rampf[idx[k] mod (n_det - 1)]: the lists' ramp-filtered weights.
+hipError_t launch_csr_ramp(const int* idx, const float* wts, const float* rampf, idx_t nnz,
+                           const GridGeom& gg, float* out, hipStream_t st);
+// Both grids of one list walk: grid (weights wts: R* g) and grid_ramp (weights wts_ramp: the
 // ramp filter); the sums equal those of two launch_gather calls.  nzb 1..64.
 hipError_t launch_gather_dual(const cpx<float>* ghat, cpx<float>* grid, cpx<float>* grid_ramp,
                               const int* row_ptr, const int* idx, const float* wts,
-                              const float* lscale, const GridGeom& gg, int nz, int z0, int nzb,
+                              const float* wts_ramp, const GridGeom& gg, int nz, int z0, int nzb,
                               hipStream_t st);
 hipError_t launch_deapod_table(float* inv, const GridGeom& gg, hipStream_t st);
 hipError_t launch_fft2d_f32(cpx<float>* data, int M, int batch, int dir,

@@ -50,6 +50,7 @@ struct Level {
   double L = 0.0, lambda = 0.0;
   size_t off_fk = 0, off_fkn = 0, off_b = 0;
   size_t off_rowptr = 0, off_cidx = 0, off_cw = 0, off_deapod = 0;  // gridding lists
+  size_t off_cwr = 0;  // the lists' ramp-filtered weights (FBP)
   size_t off_prow = 0, off_pw = 0;  // point-spread grid lists (row pointers, float64 weights)
   size_t off_czc = 0, off_czf = 0, off_czb = 0;  // radial chirp-z tables (chirp, factor, B)
   int v_fwd = 1, v_cc = 1, v_inv = 1;  // tile variants of passes R, C, R'
@@ -193,6 +194,7 @@ void layout(tomo_plan p) {
     l.off_rowptr = take((cells + 1) * sizeof(int));
     l.off_cidx = take(nnz * sizeof(int));
     l.off_cw = take(nnz * sizeof(float));
+    l.off_cwr = take(nnz * sizeof(float));
     l.off_deapod = take((size_t)l.n * sizeof(float));
     l.off_czc = take((size_t)l.nd * sizeof(cpx<float>));
     l.off_czf = take((size_t)l.nd * sizeof(cpx<float>));
@@ -395,6 +397,15 @@ tomo_status ensure_grids(tomo_plan p) {
                                p->at<int>(l.off_rowptr), p->at<int>(l.off_cidx),
                                p->at<float>(l.off_cw), p->at<int>(p->off_scan), st));
     HIPCHK(p, launch_deapod_table(p->at<float>(l.off_deapod), gg, st));
+    {
+      // ramp weights of the level (radial_tables also writes the level's DFT tables, which
+      // every back-projection rewrites before use)
+      const size_t nnz = (size_t)p->g.n_angles * (l.nd - 1) * p->g.kb_width * p->g.kb_width;
+      HIPCHK(p, launch_radial_tables(p->at<cpx<float>>(p->off_dfttab), p->at<cpx<float>>(p->off_post),
+                                     p->at<float>(p->off_rampf), gg, 0, st));
+      HIPCHK(p, launch_csr_ramp(p->at<int>(l.off_cidx), p->at<float>(l.off_cw),
+                                p->at<float>(p->off_rampf), (idx_t)nnz, gg, p->at<float>(l.off_cwr), st));
+    }
     if (czt_length(l.nd) <= kMaxGrid)
       HIPCHK(p, launch_czt_tables(p->at<cpx<float>>(l.off_czc), p->at<cpx<float>>(l.off_czf),
                                   p->at<cpx<float>>(l.off_czb), gg, st));
@@ -460,7 +471,7 @@ tomo_status backproject_level_dual_impl(tomo_plan p, const Level& l, const float
     const int zc = std::min(chunk, p->nz - z0);
     HIPCHK(p, launch_gather_dual(p->at<cpx<float>>(p->off_ghat), grid, grid2, p->at<int>(l.off_rowptr),
                                  p->at<int>(l.off_cidx), p->at<float>(l.off_cw),
-                                 p->at<float>(p->off_rampf), gg, p->nz, z0, zc, st));
+                                 p->at<float>(l.off_cwr), gg, p->nz, z0, zc, st));
     HIPCHK(p, launch_fft2d_crop_f32(grid, l.M, zc, p->tw32(l.M), out_b + (size_t)z0 * l.n * l.n,
                                     p->at<float>(l.off_deapod), l.n, st));
     HIPCHK(p, launch_fft2d_crop_f32(grid2, l.M, zc, p->tw32(l.M), out_fbp + (size_t)z0 * l.n * l.n,
@@ -483,7 +494,6 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
   if (s != TOMO_OK) return s;
   const GridGeom gg = bp_geom(p, l);
   cpx<float>* ghat = p->at<cpx<float>>(p->off_ghat);
-  float* rampf = p->at<float>(p->off_rampf);
   if (!reuse && (s = radial_spectrum(p, l, sino)) != TOMO_OK) return s;
   const size_t slice_grid = (size_t)l.M * l.M * sizeof(cpx<float>);
   int chunk = (int)std::min<size_t>((size_t)p->nz, p->scratch_bytes / slice_grid);
@@ -494,8 +504,8 @@ tomo_status backproject_level_impl(tomo_plan p, const Level& l, const float* sin
     for (int zb = 0; zb < zc; zb += 64) {
       const int nzb = std::min(64, zc - zb);
       HIPCHK(p, launch_gather(ghat, grid + (size_t)zb * l.M * l.M, p->at<int>(l.off_rowptr),
-                              p->at<int>(l.off_cidx), p->at<float>(l.off_cw),
-                              ramp ? rampf : nullptr, gg, p->nz, z0 + zb, nzb, st));
+                              p->at<int>(l.off_cidx), p->at<float>(ramp ? l.off_cwr : l.off_cw), gg,
+                              p->nz, z0 + zb, nzb, st));
     }
     HIPCHK(p, launch_fft2d_crop_f32(grid, l.M, zc, p->tw32(l.M), out + (size_t)z0 * l.n * l.n,
                                     p->at<float>(l.off_deapod), l.n, st));
