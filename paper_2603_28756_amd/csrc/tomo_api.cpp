@@ -229,7 +229,9 @@ void layout(tomo_plan p) {
   for (const Level& l : p->lv) {
     const size_t s1 = align_up((size_t)p->nz * l.n * (l.P / 2) * 8);
     const size_t hot = 2 * s1;
-    const size_t bp = 2 * (size_t)l.M * l.M * sizeof(cpx<float>);  // R* g and FBP grids of a slice
+    // R* g and FBP grids of up to 32 slices: the back-projection walks its lists once per
+    // chunk of slices, and 32 slices per walk read 256-byte lines per sample (16: 128 bytes)
+    const size_t bp = 2 * (size_t)std::min(p->nz, 32) * l.M * l.M * sizeof(cpx<float>);
     const size_t npts = (size_t)na * (l.nd - 1);
     scratch = std::max(scratch, std::max(hot, bp));
   }
