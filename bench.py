@@ -247,8 +247,9 @@ def cpu_measurements(workload: str) -> dict:
 
 
 def run_batch(args) -> int:
-    """256 independent uneven single-slice problems advanced together (one persistent launch
-    per iteration, graph-captured) against the same problems run one plan at a time.  The
+    """256 independent uneven single-slice problems advanced together (the autotuned batch
+    schedule: one persistent launch, or one launch per phase and size, per iteration,
+    graph-captured) against the same problems run one plan at a time.  The
     per-iteration time comes from two run lengths (3 and 33 iterations), so it excludes the
     per-problem FBP start and precompute.  One JSON line."""
     import numpy as np
@@ -305,8 +306,12 @@ def run_batch(args) -> int:
                                           if schedule["fused_prior"] else "pair-shared prior phase"),
                                 "autotune_iter_ms": schedule["iter_ms"],
                                 "starting_schedule_iter_ms": schedule["base_ms"], "autotune_s": tune_s,
-                                "launch": "one persistent launch per iteration (prior, R, C, R' items "
-                                          "of all problems from one queue), graph-captured"}},
+                                "launch": ("one launch per phase and transform size (prior; R, C, R' of "
+                                           "every problem), one tile per block, and a per-problem "
+                                           "finalize launch, graph-captured"
+                                           if schedule.get("phase_launches") else
+                                           "one persistent launch per iteration (prior, R, C, R' items "
+                                           "of all problems from one queue), graph-captured")}},
         "one_plan_at_a_time": {"ms_per_iteration": it_seq, "voxel_updates_per_s": vox / (it_seq * 1e-3)},
         "batching_speedup": it_seq / it_batch,
     }

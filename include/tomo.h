@@ -396,20 +396,28 @@ typedef struct {
                                            bytes moved); 26-neighbour problems keep the phase    */
   float iter_ms;                        /* out (autotune): one batched iteration, chosen schedule */
   float base_ms;                        /* out (autotune): the starting schedule above            */
+  int32_t phase_launches;               /* 0: one persistent launch per iteration whose blocks take
+                                           items from the phase-ordered queue and wait for the
+                                           items they depend on (default); 1: one launch per phase
+                                           and transform size, each block one tile (group is 1),
+                                           and a per-problem finalize launch: launch boundaries
+                                           order the phases                                      */
 } tomo_batch_schedule_t;
 /* Time batched iterations (reps launches after a warm-up; reps <= 0 means 5) with the prior
- * phase, 16 elements per thread and 8 tiles per item everywhere, then try the prior inside
- * pass R' (when a problem has the 8-neighbour prior), 2, 16, 32 or 64 tiles per item for all
- * sizes, per FFT size half or twice that, and per size 8 elements per thread, keeping each
- * change that makes the whole iteration at least 3% faster (Sec. 2.1's padded FFTs,
- * scheduled per size).
+ * phase, the persistent launch, 16 elements per thread and 8 tiles per item everywhere, then
+ * try the prior inside pass R' (when a problem has the 8-neighbour prior), one launch per
+ * phase (then the prior scheme once more), and for the persistent launch 1, 2, 8, 16, 32 or
+ * 64 tiles per item for all sizes and per FFT size half or twice that, then per size 8
+ * elements per thread, keeping each change that makes the whole iteration at least 3% faster
+ * (Sec. 2.1's padded FFTs, scheduled per size).
  * Computes missing PSF spectra; overwrites every problem's iterates, b and scalars (call it
  * before tomo_batch_reconstruct, which prepares them again).  Synchronises the batch stream.
  * out: nullable.  Errors: INVALID_ARG, NO_WORKSPACE, HIP, INTERNAL. */
 tomo_status tomo_batch_autotune(tomo_batch batch, int32_t reps, tomo_batch_schedule_t* out);
-/* Set (set != NULL: fused_prior and pad/elems pairs, sizes not listed keep their choice) and/or
- * read back (out != NULL) the schedule.  Errors: INVALID_ARG (a size not in the batch, elems not
- * 8 or 16, fused_prior not 0 or 1). */
+/* Set (set != NULL: fused_prior, phase_launches and pad/elems/group triples, sizes not listed
+ * keep their choice) and/or read back (out != NULL) the schedule.  Errors: INVALID_ARG (a size
+ * not in the batch, elems not 8 or 16, group outside 1..64, fused_prior or phase_launches not
+ * 0 or 1). */
 tomo_status tomo_batch_schedule(tomo_batch batch, const tomo_batch_schedule_t* set,
                                 tomo_batch_schedule_t* out);
 tomo_status tomo_batch_destroy(tomo_batch batch);  /* NULL ok */

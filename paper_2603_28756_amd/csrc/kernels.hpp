@@ -108,6 +108,12 @@ int batch_blocks_per_cu(bool fused);
 hipError_t launch_batch_iteration(bool fused, const BatchProb* probs, const int2* items, int n_items,
                                   int* ctl, int* cnt, int nprob, int ik, int ikm1, int inext,
                                   int grid, hipStream_t st);
+// The same iteration as one launch per (phase, transform size) segment of the work list
+// (host int4[nseg]: phase, P | EL << 16, first item, item count; phases in order) and a per-problem
+// finalize launch; no tile waits.
+hipError_t launch_batch_phases(bool fused, const BatchProb* probs, const int2* items,
+                               const int4* segs, int nseg, int nprob, int ik, int ikm1, int inext,
+                               hipStream_t st);
 hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st);
 
 // ---- start selection (learned start with FBP fallback) -----------------------------------

@@ -1000,7 +1000,7 @@ TOMO_DEV void bounded_wait(const int* ctr, int target, int* err) {
 constexpr int BP_SUB = 16;
 
 template <int NB, bool QUAD>
-__device__ __attribute__((noinline)) void batch_phase_prior(unsigned char* smem, int tile,
+TOMO_DEV void batch_phase_prior_in(unsigned char* smem, int tile,
                                                             const BatchProb* pb, int ik, int ikm1) {
   using SH = PriorShape<16>;
   const int N = pb->N;
@@ -1031,11 +1031,11 @@ TOMO_DEV void item_tiles(int item, int grp, int ntiles, int* t0, int* t1) {
   *t1 = min(ntiles, *t0 + grp);
 }
 
-template <int P, int EL>
-__device__ __attribute__((noinline)) void batch_phase_r(unsigned char* smem, int item,
+template <int P, int EL, bool ONE = false>
+TOMO_DEV void batch_phase_r_in(unsigned char* smem, int item,
                                                         const BatchProb* pb, int ik, int ikm1) {
-  int t0, t1;
-  item_tiles(item, pb->grp, pb->nR, &t0, &t1);
+  int t0 = item, t1 = item + 1;  // ONE: the item is one tile (no loop to hoist across)
+  if constexpr (!ONE) item_tiles(item, pb->grp, pb->nR, &t0, &t1);
   const float mu = (float)pb->scal[SC_MU];
   for (int tile = t0; tile < t1; ++tile) {
     if (tile > t0) __syncthreads();  // the previous tile's rows are read from LDS
@@ -1048,13 +1048,13 @@ __device__ __attribute__((noinline)) void batch_phase_r(unsigned char* smem, int
   }
 }
 
-template <int P, int EL>
-__device__ __attribute__((noinline)) void batch_phase_c(unsigned char* smem, int item,
+template <int P, int EL, bool ONE = false>
+TOMO_DEV void batch_phase_c_in(unsigned char* smem, int item,
                                                         const BatchProb* pb) {
   constexpr int TC = bt_tc<P, EL>();
   constexpr int ncol = (P / 2) / TC;
-  int t0, t1;
-  item_tiles(item, pb->grp, pb->nC, &t0, &t1);
+  int t0 = item, t1 = item + 1;  // ONE: the item is one tile (no loop to hoist across)
+  if constexpr (!ONE) item_tiles(item, pb->grp, pb->nC, &t0, &t1);
   for (int tile = t0; tile < t1; ++tile) {
     if (tile > t0) __syncthreads();
     const int z = tile / ncol;
@@ -1063,11 +1063,11 @@ __device__ __attribute__((noinline)) void batch_phase_c(unsigned char* smem, int
 }
 
 // pass R' of a step whose y and gp - b were written by the prior phase (x_{k-1} slot: y)
-template <int P, int EL>
-__device__ __attribute__((noinline)) void batch_phase_rp(unsigned char* smem, int item,
+template <int P, int EL, bool ONE = false>
+TOMO_DEV void batch_phase_rp_in(unsigned char* smem, int item,
                                                          const BatchProb* pb, int ik, int inext) {
-  int t0, t1;
-  item_tiles(item, pb->grp, pb->nRp, &t0, &t1);
+  int t0 = item, t1 = item + 1;  // ONE: the item is one tile (no loop to hoist across)
+  if constexpr (!ONE) item_tiles(item, pb->grp, pb->nRp, &t0, &t1);
   const float invL = (float)pb->scal[SC_INVL];
   for (int tile = t0; tile < t1; ++tile) {
     if (tile > t0) __syncthreads();
@@ -1079,12 +1079,12 @@ __device__ __attribute__((noinline)) void batch_phase_rp(unsigned char* smem, in
 
 // pass R' with the in-plane prior evaluated over a neighbour tile in its epilogue (each pair
 // from both of its voxels): the 8-neighbour problems of a batch scheduled without prior phase
-template <int P, int EL>
-__device__ __attribute__((noinline)) void batch_phase_rp_fused(unsigned char* smem, int item,
+template <int P, int EL, bool ONE = false>
+TOMO_DEV void batch_phase_rp_fused_in(unsigned char* smem, int item,
                                                                const BatchProb* pb, int ik, int ikm1,
                                                                int inext) {
-  int t0, t1;
-  item_tiles(item, pb->grp, pb->nRp, &t0, &t1);
+  int t0 = item, t1 = item + 1;  // ONE: the item is one tile (no loop to hoist across)
+  if constexpr (!ONE) item_tiles(item, pb->grp, pb->nRp, &t0, &t1);
   const float mu = (float)pb->scal[SC_MU];
   const float invL = (float)pb->scal[SC_INVL];
   for (int tile = t0; tile < t1; ++tile) {
@@ -1093,6 +1093,48 @@ __device__ __attribute__((noinline)) void batch_phase_rp_fused(unsigned char* sm
         smem, tile, pb->S2, pb->x[ik], pb->x[ikm1], pb->b, nullptr, pb->x[inext],
         pb->partials + (idx_t)tile * 4, mu, invL, pb->tw, pb->N, pb->nz, pb->pp);
   }
+}
+
+// Non-inlined entry points of the phase bodies for the persistent kernel, which may dispatch to
+// every phase and size: each body's registers are then allocated on their own.  The
+// per-phase kernels inline the bodies of their one phase instead.
+template <int NB, bool QUAD>
+__device__ __attribute__((noinline)) void batch_phase_prior(unsigned char* smem, int tile,
+                                                            const BatchProb* pb, int ik, int ikm1) {
+  batch_phase_prior_in<NB, QUAD>(smem, tile, pb, ik, ikm1);
+}
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_r(unsigned char* smem, int item,
+                                                        const BatchProb* pb, int ik, int ikm1) {
+  batch_phase_r_in<P, EL>(smem, item, pb, ik, ikm1);
+}
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_c(unsigned char* smem, int item,
+                                                        const BatchProb* pb) {
+  batch_phase_c_in<P, EL>(smem, item, pb);
+}
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_rp(unsigned char* smem, int item,
+                                                         const BatchProb* pb, int ik, int inext) {
+  batch_phase_rp_in<P, EL>(smem, item, pb, ik, inext);
+}
+template <int P, int EL>
+__device__ __attribute__((noinline)) void batch_phase_rp_fused(unsigned char* smem, int item,
+                                                               const BatchProb* pb, int ik, int ikm1,
+                                                               int inext) {
+  batch_phase_rp_fused_in<P, EL>(smem, item, pb, ik, ikm1, inext);
+}
+
+// One item of phase PH (1 R, 2 C, 3 R') of a problem with transform size P and EL elements
+// per thread, inlined; with one launch per phase an item is one tile (the work list is built
+// with one tile per item), so no tile loop keeps loop-invariant twiddles live.
+template <int PH, int P, int EL, bool FUSED>
+TOMO_DEV void batch_tile_inline(unsigned char* smem, int item, const BatchProb* pb, int ik,
+                                int ikm1, int inext) {
+  if constexpr (PH == 1) batch_phase_r_in<P, EL, true>(smem, item, pb, ik, ikm1);
+  else if constexpr (PH == 2) batch_phase_c_in<P, EL, true>(smem, item, pb);
+  else if (FUSED && pb->fused) batch_phase_rp_fused_in<P, EL, true>(smem, item, pb, ik, ikm1, inext);
+  else batch_phase_rp_in<P, EL, true>(smem, item, pb, ik, inext);
 }
 
 template <int P, int EL, bool FUSED>
@@ -1219,6 +1261,59 @@ batch_iter_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ 
       __threadfence();
     }
   }
+}
+
+// The same iteration as one launch per phase instead of one persistent launch: block b of
+// phase PH takes item b of that phase's part of the work list (all problems of the batch),
+// and the launch boundaries order the phases, so there are no tile waits, counters or
+// fences.  The same tile bodies write the same partial sums; batch_finalize_kernel then
+// runs each problem's float64 finalize (one block per problem).
+// LDS of one phase: the largest body it may run (every batch size, 8 or 16 elements).
+template <int PH, int P, int EL, bool FUSED>
+constexpr int batch_phase_lds_pe() {
+  if constexpr (PH == 1) return rows_fwd_lds<P, bt_pairs<P, EL>()>();
+  else if constexpr (PH == 2) return cols_conv_lds<P, bt_tc<P, EL>()>();
+  else if constexpr (FUSED) return cmax(RowsInvLds<P, bt_pairs<P, EL>(), 0, EL>::BYTES,
+                                        RowsInvLds<P, bt_pairs<P, EL>(), 8, EL>::BYTES);
+  else return RowsInvLds<P, bt_pairs<P, EL>(), 0, EL>::BYTES;
+}
+template <int PH, int P, bool FUSED>
+constexpr int batch_phase_lds_p() {
+  return cmax(batch_phase_lds_pe<PH, P, 8, FUSED>(), batch_phase_lds_pe<PH, P, 16, FUSED>());
+}
+template <int PH, int P, int EL, bool FUSED>
+constexpr int batch_phase_lds() {
+  if constexpr (PH == 0) return cmax((int)sizeof(PriorLds<26, 16>), (int)sizeof(PriorLds<8, 16>));
+  else return batch_phase_lds_pe<PH, P, EL, FUSED>();
+}
+
+// One launch covers the items of one phase and one transform size P with EL elements per
+// thread (the prior phase: every problem, P and EL unused), so that each kernel holds the
+// body of one schedule only.
+template <int PH, int P, int EL, bool FUSED>
+__global__ void __launch_bounds__(BT)
+batch_phase_kernel(const BatchProb* __restrict__ probs, const int2* __restrict__ items, int ik,
+                   int ikm1, int inext) {
+  __shared__ __align__(16) unsigned char smem[batch_phase_lds<PH, P, EL, FUSED>()];
+  const int2 d = items[blockIdx.x];
+  const int j = d.x & 0xffffff, tile = d.y;
+  const BatchProb& pb = probs[j];
+  if constexpr (PH == 0) {
+    if (pb.neighbours == 26) {
+      if (pb.pp.quadratic) batch_phase_prior_in<26, true>(smem, tile, &pb, ik, ikm1);
+      else batch_phase_prior_in<26, false>(smem, tile, &pb, ik, ikm1);
+    } else {
+      if (pb.pp.quadratic) batch_phase_prior_in<8, true>(smem, tile, &pb, ik, ikm1);
+      else batch_phase_prior_in<8, false>(smem, tile, &pb, ik, ikm1);
+    }
+  } else {
+    batch_tile_inline<PH, P, EL, FUSED>(smem, tile, &pb, ik, ikm1, inext);
+  }
+}
+
+__global__ void __launch_bounds__(BT) batch_finalize_kernel(const BatchProb* __restrict__ probs) {
+  __shared__ double sh[4 * BT];
+  batch_finalize(probs[blockIdx.x], sh);
 }
 
 __global__ void fill_int_kernel(int* x, idx_t n, int v) {
@@ -1435,6 +1530,51 @@ hipError_t launch_batch_iteration(bool fused, const BatchProb* probs, const int2
   else
     hipLaunchKernelGGL(batch_iter_kernel<false>, dim3(grid), dim3(BT), 0, st, probs, items, n_items,
                        ctl, cnt, nprob, ik, ikm1, inext);
+  return hipGetLastError();
+}
+
+template <int PH, int P, int EL>
+void batch_phase_launch(bool fused, const BatchProb* probs, const int2* items, int cnt, int ik,
+                        int ikm1, int inext, hipStream_t st) {
+  if (fused)
+    hipLaunchKernelGGL((batch_phase_kernel<PH, P, EL, true>), dim3((unsigned)cnt), dim3(BT), 0,
+                       st, probs, items, ik, ikm1, inext);
+  else
+    hipLaunchKernelGGL((batch_phase_kernel<PH, P, EL, false>), dim3((unsigned)cnt), dim3(BT), 0,
+                       st, probs, items, ik, ikm1, inext);
+}
+
+hipError_t launch_batch_phases(bool fused, const BatchProb* probs, const int2* items,
+                               const int4* segs, int nseg, int nprob, int ik, int ikm1, int inext,
+                               hipStream_t st) {
+  for (int k = 0; k < nseg; ++k) {
+    // y: the transform size and the elements per thread (P | EL << 16)
+    const int ph = segs[k].x, P = segs[k].y & 0xffff, el = segs[k].y >> 16;
+    const int off = segs[k].z, cnt = segs[k].w;
+    if (cnt <= 0) continue;
+    const int2* it = items + off;
+    if (ph == 0) {
+      batch_phase_launch<0, 0, 0>(fused, probs, it, cnt, ik, ikm1, inext, st);
+      continue;
+    }
+#define TOMO_PHPE(PHV, PV)                                                                      \
+  if (el == 8) batch_phase_launch<PHV, PV, 8>(fused, probs, it, cnt, ik, ikm1, inext, st);      \
+  else batch_phase_launch<PHV, PV, 16>(fused, probs, it, cnt, ik, ikm1, inext, st);
+#define TOMO_PHP(PHV)                                       \
+  switch (P) {                                              \
+    case 256: { TOMO_PHPE(PHV, 256) } break;                \
+    case 512: { TOMO_PHPE(PHV, 512) } break;                \
+    case 1024: { TOMO_PHPE(PHV, 1024) } break;              \
+    case 2048: { TOMO_PHPE(PHV, 2048) } break;              \
+    default: return hipErrorInvalidValue;                   \
+  }
+    if (ph == 1) { TOMO_PHP(1) }
+    else if (ph == 2) { TOMO_PHP(2) }
+    else { TOMO_PHP(3) }
+#undef TOMO_PHP
+#undef TOMO_PHPE
+  }
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(nprob), dim3(BT), 0, st, probs);
   return hipGetLastError();
 }
 

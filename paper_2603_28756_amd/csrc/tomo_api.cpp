@@ -1299,6 +1299,8 @@ struct tomo_batch_s {
   hipStream_t stream = nullptr;
   int device = 0, grid = 0, grid_fused = 0;
   bool fused = false;          // 8-neighbour problems take the prior inside pass R'
+  bool phases = false;         // one launch per phase and size (and a finalize launch)
+  std::vector<int4> segs;      // work-list segments of one phase and transform size
   std::vector<BatchProb> probs;
   std::vector<int2> items;
   std::vector<int> order;      // problems by decreasing FFT size (queue order within a phase)
@@ -1376,7 +1378,7 @@ void batch_build_items(tomo_batch b) {
     const size_t si = std::lower_bound(b->sizes.begin(), b->sizes.end(), d.P) - b->sizes.begin();
     d.el = b->size_el[si];
     d.fused = b->fused && d.neighbours == 8 ? 1 : 0;
-    d.grp = b->size_grp[si];
+    d.grp = b->phases ? 1 : b->size_grp[si];  // one launch per phase: one tile per item
     batch_tile_counts(d.N, d.P, d.nz, d.el, &d.nPr, &d.nR, &d.nC, &d.nRp);
     if (d.fused) d.nPr = 0;
     d.iR = (d.nR + d.grp - 1) / d.grp;
@@ -1384,11 +1386,16 @@ void batch_build_items(tomo_batch b) {
     d.iRp = (d.nRp + d.grp - 1) / d.grp;
   }
   b->items.clear();
+  b->segs.clear();
   for (int ph = 0; ph < 4; ++ph)
-    for (int j : b->order) {
+    for (int j : b->order) {  // decreasing transform size: each size is one segment
       const BatchProb& d = b->probs[j];
       const int cntp = ph == 0 ? d.nPr : ph == 1 ? d.iR : ph == 2 ? d.iC : d.iRp;
+      const int key = ph == 0 ? 0 : (d.P | (d.el << 16));
+      if (b->segs.empty() || b->segs.back().x != ph || b->segs.back().y != key)
+        b->segs.push_back(make_int4(ph, key, (int)b->items.size(), 0));
       for (int t = 0; t < cntp; ++t) b->items.push_back(make_int2(j | (ph << 24), t));
+      b->segs.back().w += cntp;
     }
 }
 
@@ -1464,15 +1471,22 @@ void batch_report(tomo_batch b, tomo_batch_schedule_t* out) {
   std::memset(out, 0, sizeof *out);
   out->n_sizes = (int32_t)b->sizes.size();
   out->fused_prior = b->fused ? 1 : 0;
+  out->phase_launches = b->phases ? 1 : 0;
   for (size_t i = 0; i < b->sizes.size() && i < TOMO_BATCH_MAX_SIZES; ++i) {
     out->pad[i] = b->sizes[i];
     out->elems[i] = b->size_el[i];
-    out->group[i] = b->size_grp[i];
+    out->group[i] = b->phases ? 1 : b->size_grp[i];
   }
 }
 
 tomo_status batch_launch(tomo_batch bt, int ik, int ikm1, int inext, hipStream_t st) {
   const int nprob = (int)bt->plans.size();
+  if (bt->phases) {
+    BHIPCHK(bt, launch_batch_phases(bt->fused, reinterpret_cast<const BatchProb*>(bt->ws + bt->off_probs),
+                                    reinterpret_cast<const int2*>(bt->ws + bt->off_items), bt->segs.data(),
+                                    (int)bt->segs.size(), nprob, ik, ikm1, inext, st));
+    return TOMO_OK;
+  }
   BHIPCHK(bt, launch_batch_iteration(bt->fused, reinterpret_cast<const BatchProb*>(bt->ws + bt->off_probs),
                                      reinterpret_cast<const int2*>(bt->ws + bt->off_items),
                                      (int)bt->items.size(), reinterpret_cast<int*>(bt->ws + bt->off_ctl),
@@ -1675,6 +1689,8 @@ tomo_status tomo_batch_schedule(tomo_batch b, const tomo_batch_schedule_t* set,
     if (b->ws) BHIPCHK(b, hipStreamSynchronize(b->stream));
     if (set->fused_prior != 0 && set->fused_prior != 1)
       return bfail(b, TOMO_ERR_INVALID_ARG, "fused_prior must be 0 or 1");
+    if (set->phase_launches != 0 && set->phase_launches != 1)
+      return bfail(b, TOMO_ERR_INVALID_ARG, "phase_launches must be 0 or 1");
     std::vector<int> el = b->size_el, grp = b->size_grp;
     for (int i = 0; i < set->n_sizes && i < TOMO_BATCH_MAX_SIZES; ++i) {
       const auto it = std::find(b->sizes.begin(), b->sizes.end(), set->pad[i]);
@@ -1689,6 +1705,7 @@ tomo_status tomo_batch_schedule(tomo_batch b, const tomo_batch_schedule_t* set,
     b->size_el = el;
     b->size_grp = grp;
     b->fused = set->fused_prior == 1;
+    b->phases = set->phase_launches == 1;
     batch_build_items(b);
     if (b->ws) {
       BHIPCHK(b, hipSetDevice(b->device));
@@ -1744,6 +1761,7 @@ tomo_status tomo_batch_autotune(tomo_batch b, int32_t reps, tomo_batch_schedule_
   b->size_el.assign(b->sizes.size(), 16);
   b->size_grp.assign(b->sizes.size(), kBatchDefaultGroup);
   b->fused = false;
+  b->phases = false;
   batch_build_items(b);
   s = batch_upload_items(b);
   if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &best);
@@ -1759,6 +1777,32 @@ tomo_status tomo_batch_autotune(tomo_batch b, int32_t reps, tomo_batch_schedule_
     if (s == TOMO_OK && t < 0.97f * best) best = t;
     else b->fused = false;
   }
+  // one launch per phase (one tile per block) instead of the persistent queue
+  if (s == TOMO_OK) {
+    const std::vector<int> prev = b->size_grp;
+    b->phases = true;
+    b->size_grp.assign(b->sizes.size(), 1);
+    batch_build_items(b);
+    float t = 0.f;
+    s = batch_upload_items(b);
+    if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &t);
+    if (s == TOMO_OK && t < 0.97f * best) {
+      best = t;
+    } else {
+      b->phases = false;
+      b->size_grp = prev;
+    }
+  }
+  // with one launch per phase, the prior scheme again
+  if (s == TOMO_OK && b->phases && any8) {
+    b->fused = !b->fused;
+    batch_build_items(b);
+    float t = 0.f;
+    s = batch_upload_items(b);
+    if (s == TOMO_OK) s = batch_time(b, reps, e0, e1, &t);
+    if (s == TOMO_OK && t < 0.97f * best) best = t;
+    else b->fused = !b->fused;
+  }
   // tiles per queue item: the same for every size first, then each size halved or doubled
   auto try_groups = [&](const std::vector<int>& g) {
     const std::vector<int> prev = b->size_grp;
@@ -1770,9 +1814,10 @@ tomo_status tomo_batch_autotune(tomo_batch b, int32_t reps, tomo_batch_schedule_
     if (s == TOMO_OK && t < 0.97f * best) best = t;
     else b->size_grp = prev;
   };
-  for (int g : {2, 8, 16, 32, 64})
-    if (s == TOMO_OK) try_groups(std::vector<int>(b->sizes.size(), g));
-  for (size_t i = 0; s == TOMO_OK && i < b->sizes.size(); ++i)
+  // (one launch per phase always takes one tile per item)
+  for (int g : {1, 2, 8, 16, 32, 64})
+    if (s == TOMO_OK && !b->phases) try_groups(std::vector<int>(b->sizes.size(), g));
+  for (size_t i = 0; s == TOMO_OK && !b->phases && i < b->sizes.size(); ++i)
     for (int f : {2, -2}) {
       std::vector<int> g = b->size_grp;
       g[i] = f > 0 ? g[i] * 2 : g[i] / 2;

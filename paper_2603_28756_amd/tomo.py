@@ -98,13 +98,15 @@ class BatchSchedule(ctypes.Structure):
     _fields_ = [("n_sizes", ctypes.c_int32), ("pad", ctypes.c_int32 * BATCH_MAX_SIZES),
                 ("elems", ctypes.c_int32 * BATCH_MAX_SIZES), ("group", ctypes.c_int32 * BATCH_MAX_SIZES),
                 ("fused_prior", ctypes.c_int32),
-                ("iter_ms", ctypes.c_float), ("base_ms", ctypes.c_float)]
+                ("iter_ms", ctypes.c_float), ("base_ms", ctypes.c_float),
+                ("phase_launches", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         k = self.n_sizes
         return {"sizes": {int(self.pad[i]): int(self.elems[i]) for i in range(k)},
                 "group": {int(self.pad[i]): int(self.group[i]) for i in range(k)},
                 "fused_prior": bool(self.fused_prior),
+                "phase_launches": bool(self.phase_launches),
                 "iter_ms": float(self.iter_ms), "base_ms": float(self.base_ms)}
 
 
@@ -521,13 +523,14 @@ class Batch:
         return out.as_dict()
 
     def schedule(self, set_to: Optional[dict] = None, fused_prior: bool = False,
-                 group: Optional[dict] = None) -> dict:
-        """Read (and with set_to = {pad: elems} first set, with the prior scheme and the tiles
-        per item {pad: group}, default 8) the schedule."""
+                 group: Optional[dict] = None, phase_launches: bool = False) -> dict:
+        """Read (and with set_to = {pad: elems} first set, with the prior scheme, the tiles per
+        item {pad: group}, default 8, and the launch scheme) the schedule."""
         st = None
         if set_to is not None:
             st = BatchSchedule()
             st.fused_prior = int(fused_prior)
+            st.phase_launches = int(phase_launches)
             st.n_sizes = len(set_to)
             for i, (p, e) in enumerate(sorted(set_to.items())):
                 st.pad[i], st.elems[i] = int(p), int(e)

@@ -94,6 +94,17 @@ def test_batch_schedules_and_autotune():
         assert batch.reconstruct(sinos, xs, iters)["wait_timeouts"] == 0
         for x, a in zip(xs, outs[16, True]):
             assert np.array_equal(to_np(x), a)
+    # one launch per phase runs the same tile bodies in the same order per problem, with the
+    # launch boundaries in place of the tile waits: bit-identical to the persistent launch
+    for fused in (False, True):
+        for grp in (1, 8):
+            sch = batch.schedule({p: 16 for p in pads}, fused_prior=fused, group={p: grp for p in pads},
+                                 phase_launches=True)
+            assert sch["phase_launches"]
+            xs = [torch.empty((1, it[0], it[0]), dtype=torch.float32, device=dev()) for it in items]
+            assert batch.reconstruct(sinos, xs, iters)["wait_timeouts"] == 0
+            for x, a in zip(xs, outs[16, fused]):
+                assert np.array_equal(to_np(x), a)
     mixed = {p: (8 if i % 2 else 16) for i, p in enumerate(pads)}
     assert batch.schedule(mixed, group={p: 1 + i for i, p in enumerate(pads)})["sizes"] == mixed
     tuned = batch.autotune(reps=3)
@@ -142,12 +153,16 @@ def test_batch_with_volumes_matches_single_plans():
     batch = tomo.Batch(plans)
     sinos = [to_dev(it[4]) for it in items]
     pads = sorted({p.level_dims(0)[2] for p in plans})
-    batch.schedule({p: 16 for p in pads}, fused_prior=False)
-    xs = [torch.empty((it[1], it[0], it[0]), dtype=torch.float32, device=dev()) for it in items]
-    st = batch.reconstruct(sinos, xs, iters)
-    assert st["wait_timeouts"] == 0 and st["n_nonfinite"] == 0
-    for (n, nz, nb, nd, sino, ang), x in zip(items, xs):
+    refs = []
+    for (n, nz, nb, nd, sino, ang) in items:
         single = make_plan(n, nz, ang, nd, neighbours=nb)
         xx = torch.empty((nz, n, n), dtype=torch.float32, device=dev())
         single.reconstruct(to_dev(sino), xx, [iters], init=tomo.INIT_FBP)
-        assert rel_l2(to_np(x), to_np(xx)) < 1e-6
+        refs.append(to_np(xx))
+    for phases in (False, True):
+        batch.schedule({p: 16 for p in pads}, fused_prior=False, phase_launches=phases)
+        xs = [torch.empty((it[1], it[0], it[0]), dtype=torch.float32, device=dev()) for it in items]
+        st = batch.reconstruct(sinos, xs, iters)
+        assert st["wait_timeouts"] == 0 and st["n_nonfinite"] == 0
+        for x, r in zip(xs, refs):
+            assert rel_l2(to_np(x), r) < 1e-6
