@@ -596,6 +596,9 @@ def main() -> int:
                          "counter runs use it to repeat the schedule a timed run chose")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--hbm-rates", action="store_true",
+                    help="only time plain streaming kernels (read, write, copy of 512 MiB) for "
+                         "the HBM rates this part reaches outside the path")
     ap.add_argument("--cpu-only", action="store_true",
                     help="only the host measurements (oracle baseline, direct vs Toeplitz); no GPU")
     args = ap.parse_args()
@@ -631,6 +634,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": 4 * n, "copy_calib_bytes_written": 4 * n}))
         return 0
+
+    if args.hbm_rates:
+        return run_hbm_rates(torch, dev)
 
     import synth
     from paper_2603_28756_amd import tomo
@@ -805,6 +811,39 @@ def main() -> int:
         out["cpu_direct_vs_toeplitz"] = cpu["cpu_direct_vs_toeplitz"]
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out))
+    return 0
+
+
+def run_hbm_rates(torch, dev) -> int:
+    """HBM rates of plain streaming kernels on 512 MiB buffers (twice the 256 MB Infinity Cache):
+    a sum (read only), a fill (write only) and an elementwise copy (256 MiB each way), timed
+    with events, best and median of 10 launches after 2 warm-ups.  They give the rates a
+    kernel with no arithmetic reaches, beside the 8 TB/s of the data sheet."""
+    nbytes = 512 * 1024 * 1024
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    half = nbytes // 8
+    acc = torch.empty((), dtype=torch.float32, device=dev)
+    cases = {
+        "read": (lambda: torch.sum(a, out=acc), nbytes),
+        "write": (lambda: b.fill_(1.0), nbytes),
+        "copy": (lambda: torch.mul(a[:half], 1.0, out=b[:half]), nbytes),
+    }
+    out = {"metric": "streaming HBM rate", "unit": "GB/s", "buffer_bytes": nbytes}
+    for name, (fn, moved) in cases.items():
+        ts = []
+        for i in range(12):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            if i >= 2:
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        out[name] = {"best_gbs": moved / ts[0] / 1e9, "median_gbs": moved / ts[len(ts) // 2] / 1e9,
+                     "bytes": moved, "frac_of_8tbs": moved / ts[0] / 1e9 / HBM_PEAK_GBS}
     print(json.dumps(out))
     return 0
 

@@ -43,9 +43,12 @@ TOMO_DEV f32x4 mfma(u16x8 a, u16x8 b, f32x4 c) {
 // 3x3 conv on 2D pixel tiles staged through LDS.  A block owns a tile 16 pixels wide and
 // 4*RPW rows high (wave w: rows w*RPW .. w*RPW+RPW-1) x BN output channels.  For each chunk
 // of 32 input channels it stages (a) the input tile with a one-pixel halo, 64 bytes per
-// pixel, and (b) the weights of all 9 taps for its BN channels, then every wave runs
-// 9 taps x RPW rows x BN/16 MFMAs reading both operands from LDS (each 16-pixel A fragment
-// and each 16-channel B fragment is one contiguous kilobyte: no bank conflicts).
+// pixel, and (b) the weights of all 9 taps for its BN channels; every staging load of a chunk
+// is issued before the first LDS store, so their latencies overlap.  Then every wave runs
+// 9 taps x RPW rows x BN/16 MFMAs reading both operands from LDS (each 16-pixel fragment and
+// each 16-channel weight fragment is one contiguous kilobyte).  The weights are the MFMA's
+// first operand, so a lane's accumulator holds 4 consecutive output channels of one pixel
+// and the results leave as 8-byte stores.
 template <int BN, int RPW>
 struct ConvTile {
   static constexpr int TW = 16, TH = 4 * RPW, HW_ = TW + 2, HH = TH + 2;
@@ -53,14 +56,30 @@ struct ConvTile {
   static constexpr int A_BYTES = A_PIX * 64;              // 32 bf16 channels per pixel
   static constexpr int B_BYTES = 9 * BN * 64;             // [tap][co][32 channels]
   static constexpr int BYTES = A_BYTES + B_BYTES;
+  static constexpr int A_EL = A_PIX * 4, B_EL = 9 * BN * 4;  // 16-byte staging elements
+  static constexpr int NA = (A_EL + 255) / 256, NB = (B_EL + 255) / 256;  // per thread
 };
+
+// generic pointer into shared memory -> LDS address space (the destination operand of
+// global_load_lds)
+TOMO_DEV __attribute__((address_space(3))) void* lds_ptr(uint16_t* p) {
+  return (__attribute__((address_space(3))) void*)(p);
+}
+
+TOMO_DEV void st4bf(uint16_t* p, const uint16_t (&v)[4]) {
+  *reinterpret_cast<uint2*>(p) = make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16),
+                                            (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+}
 
 // UPCAT: the input is the concatenation [up2(xu), x]: channels below cu are read from the
 // half-resolution tensor xu at (row/2, column/2), the others from x (channel c - cu).
 // POOL: also write the 2x2 average of the (bfloat16-rounded) output to pool (channel
-// stride ldp, half resolution); every 2x2 block lies in one lane (4 rows x 4 columns).
+// stride ldp, half resolution); a 2x2 block spans two rows of one lane and the lane pair
+// (2m, 2m+1).
 template <int BN, int RPW, bool RELU, bool BIAS, bool MASK, bool UPCAT, bool POOL>
-__global__ void __launch_bounds__(256)
+// waves per SIMD: what the LDS tile allows (4 blocks of BN = 32, 2 of BN = 64 per CU), 3 for
+// the concatenating form, which spills at 4
+__global__ void __launch_bounds__(256, BN == 32 ? (UPCAT ? 3 : 4) : 2)
 conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
                     const float* __restrict__ bias, uint16_t* __restrict__ y, int ldy,
                     const uint16_t* __restrict__ mask, int ldm, int cin, int H, int W, int ntx,
@@ -86,26 +105,45 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int c0 = 0; c0 < cin; c0 += 32) {
-    // stage the input halo tile: A_PIX pixels x 4 chunks of 8 channels
-    for (int e = t; e < T::A_PIX * 4; e += 256) {
-      const int pix = e >> 2, q = (e & 3) * 8;
-      const int hy = pix / T::HW_, hx = pix - hy * T::HW_;
-      const int gy = y0 + hy - 1, gx = x0 + hx - 1;
-      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        if (UPCAT && c0 < cu)
-          v = ld8(xu + (((size_t)blockIdx.y * (H / 2) + gy / 2) * (W / 2) + gx / 2) * ldu + c0 + q);
-        else
-          v = ld8(x + (img + (size_t)gy * W + gx) * ldx + c0 - (UPCAT ? cu : 0) + q);
+    // staging element e: input pixel e / 4 (halo tile, row-major) channels 8 (e % 4) .. +7,
+    // or weight row e / 4 = tap * BN + co, channels 8 (e % 4) .. +7; LDS byte offset 16 e.
+    // Elements t + 256 i of one wave are 64 consecutive 16-byte slots, so each goes straight
+    // from memory to LDS (global_load_lds_dwordx4: lane l of the wave writes its wave base
+    // + 16 l), with no registers in between.  A halo pixel outside the image loads a pixel
+    // inside it and is overwritten with zeros once the copies have landed.
+    bool zero_a[T::NA];
+#pragma unroll
+    for (int i = 0; i < T::NA; ++i) {
+      const int e = t + 256 * i;
+      zero_a[i] = false;
+      if (e < T::A_EL) {
+        const int pix = e >> 2, q = (e & 3) * 8;
+        const int hy = pix / T::HW_, hx = pix - hy * T::HW_;
+        int gy = y0 + hy - 1, gx = x0 + hx - 1;
+        zero_a[i] = !(gy >= 0 && gy < H && gx >= 0 && gx < W);
+        gy = min(max(gy, 0), H - 1);
+        gx = min(max(gx, 0), W - 1);
+        const uint16_t* src =
+            (UPCAT && c0 < cu)
+                ? xu + (((size_t)blockIdx.y * (H / 2) + gy / 2) * (W / 2) + gx / 2) * ldu + c0 + q
+                : x + (img + (size_t)gy * W + gx) * ldx + c0 - (UPCAT ? cu : 0) + q;
+        __builtin_amdgcn_global_load_lds(src, lds_ptr(sa + (256 * i + 64 * wave) * 8), 16, 0, 0);
       }
-      st8(sa + pix * 32 + q, v);
     }
-    // stage the weights of the 9 taps: [tap][co][32]
-    for (int e = t; e < 9 * BN * 4; e += 256) {
-      const int q = (e & 3) * 8, rest = e >> 2;
-      const int co = rest % BN, tap = rest / BN;
-      st8(sb + (tap * BN + co) * 32 + q, ld8(w + ((size_t)(co0 + co) * 9 + tap) * cin + c0 + q));
+#pragma unroll
+    for (int i = 0; i < T::NB; ++i) {
+      const int e = t + 256 * i;
+      if (e < T::B_EL) {
+        const int q = (e & 3) * 8, rest = e >> 2;
+        const int co = rest % BN, tap = rest / BN;
+        __builtin_amdgcn_global_load_lds(w + ((size_t)(co0 + co) * 9 + tap) * cin + c0 + q,
+                                         lds_ptr(sb + (256 * i + 64 * wave) * 8), 16, 0, 0);
+      }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the copies of this thread have landed in LDS
+#pragma unroll
+    for (int i = 0; i < T::NA; ++i)
+      if (zero_a[i]) st8(sa + (t + 256 * i) * 8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
     __syncthreads();
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
@@ -117,53 +155,61 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
       for (int r = 0; r < RPW; ++r) {
         const u16x8 a = ld8(sa + ((wave * RPW + r + ky) * T::HW_ + lc + kx) * 32 + kq);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[r][j] = mfma(a, b[j], acc[r][j]);
+        for (int j = 0; j < NJ; ++j) acc[r][j] = mfma(b[j], a, acc[r][j]);
       }
     }
     __syncthreads();
   }
-  // lane holds pixels x0 + 4*(lane>>4) + i of row y0 + wave*RPW + r, channel co0 + 16j + lc
+  // lane holds channels co0 + 16 j + cq + i (i = 0..3) of pixel x0 + lc in row
+  // y0 + wave * RPW + r
+  const int gx = x0 + lc, cq = 4 * (lane >> 4);
+  float bv[NJ][4];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bv[j][i] = BIAS ? bias[co0 + 16 * j + cq + i] : 0.f;
   uint16_t ob[RPW][NJ][4];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int gy = y0 + wave * RPW + r;
+    const bool ok = gy < H && gx < W;
+    const size_t pix = img + (size_t)gy * W + gx;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int co = co0 + 16 * j + lc;
-      const float bv = BIAS ? bias[co] : 0.f;
+      const int co = co0 + 16 * j + cq;
+      uint2 mk = make_uint2(0u, 0u);
+      if (MASK && ok) mk = *reinterpret_cast<const uint2*>(mask + pix * ldm + co);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gx = x0 + 4 * (lane >> 4) + i;
-        ob[r][j][i] = 0;
-        if (gy < H && gx < W) {
-          const size_t pix = img + (size_t)gy * W + gx;
-          float v = acc[r][j][i] + bv;
-          if (RELU) v = fmaxf(v, 0.f);
-          if (MASK && !(bf2f(mask[pix * ldm + co]) > 0.f)) v = 0.f;
-          ob[r][j][i] = f2bf(v);
-          y[pix * ldy + co] = ob[r][j][i];
+        float v = acc[r][j][i] + bv[j][i];
+        if (RELU) v = fmaxf(v, 0.f);
+        if (MASK) {
+          const uint32_t mw = (i < 2) ? mk.x : mk.y;
+          if (!(bf2f((uint16_t)(mw >> (16 * (i & 1)))) > 0.f)) v = 0.f;
         }
+        ob[r][j][i] = ok ? f2bf(v) : (uint16_t)0;
       }
+      if (ok) st4bf(y + pix * ldy + co, ob[r][j]);
     }
   }
   if constexpr (POOL) {
     const int h2 = H / 2, w2 = W / 2;
+    const int px2 = gx >> 1;
 #pragma unroll
     for (int r = 0; r < RPW; r += 2) {
       const int py = (y0 + wave * RPW + r) / 2;
-      if (py >= h2) continue;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const int co = co0 + 16 * j + lc;
+        uint16_t pv[4];
 #pragma unroll
-        for (int i = 0; i < 4; i += 2) {
-          const int px2 = (x0 + 4 * (lane >> 4) + i) / 2;
-          if (px2 < w2) {
-            const float sm = bf2f(ob[r][j][i]) + bf2f(ob[r][j][i + 1]) + bf2f(ob[r + 1][j][i]) +
-                             bf2f(ob[r + 1][j][i + 1]);
-            pool[(((size_t)blockIdx.y * h2 + py) * w2 + px2) * ldp + co] = f2bf(0.25f * sm);
-          }
+        for (int i = 0; i < 4; ++i) {
+          // ((top left + top right) + bottom left) + bottom right
+          const float a = bf2f(ob[r][j][i]), c = bf2f(ob[r + 1][j][i]);
+          const float an = __shfl_xor(a, 1), cn = __shfl_xor(c, 1);
+          pv[i] = f2bf(0.25f * (((a + an) + c) + cn));
         }
+        if (!(lane & 1) && py < h2 && px2 < w2)
+          st4bf(pool + (((size_t)blockIdx.y * h2 + py) * w2 + px2) * ldp + co0 + 16 * j + cq, pv);
       }
     }
   }
@@ -755,8 +801,9 @@ hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float
                       uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
                       int B, int H, int W, bool relu, hipStream_t st, const uint16_t* xu, int ldu,
                       int cu, uint16_t* pool, int ldp) {
-  if (cin % 32 || cout % 32 || ldx % 8 || ldy < cout || B < 1 || H < 1 || W < 1)
+  if (cin % 32 || cout % 32 || ldx % 8 || ldy % 8 || ldy < cout || B < 1 || H < 1 || W < 1)
     return hipErrorInvalidValue;
+  if (mask && (ldm % 8 || ldm < cout)) return hipErrorInvalidValue;
   if (xu && (cu % 32 || cu <= 0 || cu >= cin || ldu % 8 || H % 2 || W % 2)) return hipErrorInvalidValue;
   if (pool && (H % 2 || W % 2 || ldp < cout || ldp % 8 || !relu || !bias || mask))
     return hipErrorInvalidValue;
