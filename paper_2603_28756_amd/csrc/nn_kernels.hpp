@@ -16,11 +16,22 @@ namespace tomo {
 // 0..cu-1 come from xu (half resolution, channel stride ldu), the rest from x.  With
 // pool != NULL (ReLU form, even H and W) the 2x2 average of the output is also written to
 // pool (half resolution, channel stride ldp).
+// With head != NULL (ReLU form with bias, no concatenation or pooling, cout 32 or 64) the
+// output is not stored: the 1x1 head r = hb + sum_c hw[c] y[c] and x0 = fbp + s r are written
+// instead (r nullable), per pixel.
+struct NnHead {
+  const float* hw;
+  const float* hb;
+  const float* fbp;
+  float s;
+  float* r;
+  float* x0;
+};
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float* bias,
                       uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
                       int B, int H, int W, bool relu, hipStream_t st,
                       const uint16_t* xu = nullptr, int ldu = 0, int cu = 0,
-                      uint16_t* pool = nullptr, int ldp = 0);
+                      uint16_t* pool = nullptr, int ldp = 0, const NnHead* head = nullptr);
 
 struct WgradPlan {
   int ntn = 0, ntc = 0, nsplit = 0, px_per_split = 0;

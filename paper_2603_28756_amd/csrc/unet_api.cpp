@@ -234,6 +234,14 @@ tomo_status forward(tomo_unet u, const float* fbp, float* x0, int B, float s, bo
                          nullptr, 0, ca.cin, ca.cout, B, v.h, v.w, true, st, u->D(l + 1), cu, cu));
     }
     const auto& cb = cv[k + 1];
+    if (l == 0 && !keep_cat && (cb.cout == 32 || cb.cout == 64)) {
+      // inference: the last convolution writes the head's output instead of D_0
+      const NnHead hd{th + u->head_w, th + u->head_b, fbp, s, nullptr, x0};
+      NCHK(u, nn_conv3x3(u->at<uint16_t>(v.Da), v.c, u->at<uint16_t>(cb.wbf), th + cb.b, nullptr, 0,
+                         nullptr, 0, cb.cin, cb.cout, B, v.h, v.w, true, st, nullptr, 0, 0, nullptr, 0,
+                         &hd));
+      return TOMO_OK;
+    }
     NCHK(u, nn_conv3x3(u->at<uint16_t>(v.Da), v.c, u->at<uint16_t>(cb.wbf), th + cb.b,
                        u->at<uint16_t>(v.D), v.c, nullptr, 0, cb.cin, cb.cout, B, v.h, v.w, true, st));
   }

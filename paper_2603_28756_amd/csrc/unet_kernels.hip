@@ -76,15 +76,17 @@ TOMO_DEV void st4bf(uint16_t* p, const uint16_t (&v)[4]) {
 // POOL: also write the 2x2 average of the (bfloat16-rounded) output to pool (channel
 // stride ldp, half resolution); a 2x2 block spans two rows of one lane and the lane pair
 // (2m, 2m+1).
-template <int BN, int RPW, bool RELU, bool BIAS, bool MASK, bool UPCAT, bool POOL>
+// HEAD: the output is not stored; the 1x1 head over the block's BN (= all) channels is
+// written instead (r = hb + sum_c hw[c] y[c], x0 = fbp + s r).
+template <int BN, int RPW, bool RELU, bool BIAS, bool MASK, bool UPCAT, bool POOL, bool HEAD>
 // waves per SIMD: what the LDS tile allows (4 blocks of BN = 32, 2 of BN = 64 per CU), 3 for
-// the concatenating form, which spills at 4
-__global__ void __launch_bounds__(256, BN == 32 ? (UPCAT ? 3 : 4) : 2)
+// the concatenating and head forms, which spill at 4
+__global__ void __launch_bounds__(256, BN == 32 ? ((UPCAT || HEAD) ? 3 : 4) : 2)
 conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __restrict__ w,
                     const float* __restrict__ bias, uint16_t* __restrict__ y, int ldy,
                     const uint16_t* __restrict__ mask, int ldm, int cin, int H, int W, int ntx,
                     int nty, const uint16_t* __restrict__ xu, int ldu, int cu,
-                    uint16_t* __restrict__ pool, int ldp) {
+                    uint16_t* __restrict__ pool, int ldp, NnHead hd) {
   using T = ConvTile<BN, RPW>;
   constexpr int NJ = BN / 16;
   __shared__ __align__(16) unsigned char smem[T::BYTES];
@@ -104,6 +106,20 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
   for (int r = 0; r < RPW; ++r)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // HEAD: the FBP values and head weights of this lane, read before the convolution so that
+  // their latency is hidden behind it
+  float fbv[RPW], hwv[NJ][4];
+  if constexpr (HEAD) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int gy = y0 + wave * RPW + r, gx = x0 + lc;
+      fbv[r] = (gy < H && gx < W) ? hd.fbp[img + (size_t)gy * W + gx] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hwv[j][i] = hd.hw[16 * j + 4 * (lane >> 4) + i];
+  }
   for (int c0 = 0; c0 < cin; c0 += 32) {
     // staging element e: input pixel e / 4 (halo tile, row-major) channels 8 (e % 4) .. +7,
     // or weight row e / 4 = tap * BN + co, channels 8 (e % 4) .. +7; LDS byte offset 16 e.
@@ -168,6 +184,7 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int i = 0; i < 4; ++i) bv[j][i] = BIAS ? bias[co0 + 16 * j + cq + i] : 0.f;
+  const float hb = HEAD ? hd.hb[0] : 0.f;
   uint16_t ob[RPW][NJ][4];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
@@ -189,7 +206,22 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
         }
         ob[r][j][i] = ok ? f2bf(v) : (uint16_t)0;
       }
-      if (ok) st4bf(y + pix * ldy + co, ob[r][j]);
+      if (!HEAD && ok) st4bf(y + pix * ldy + co, ob[r][j]);
+    }
+    if constexpr (HEAD) {
+      // the pixel's channels lie in lanes lc, lc + 16, lc + 32, lc + 48
+      float part = 0.f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part = fmaf(hwv[j][i], bf2f(ob[r][j][i]), part);
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      if (lane < 16 && ok) {
+        const float a = hb + part;
+        if (hd.r) hd.r[pix] = a;
+        hd.x0[pix] = fbv[r] + hd.s * a;
+      }
     }
   }
   if constexpr (POOL) {
@@ -484,6 +516,60 @@ conv_in_kernel(const float* __restrict__ fbp, float inv_s, const float* __restri
       out[j] = f2bf(fmaxf(a, 0.f));
     }
     st8(y + (size_t)p * cout + c0, out);
+  }
+}
+
+// The same for a channel count fixed at compile time: weights and biases are read from LDS
+// as three 16-byte broadcast words per channel (48-byte rows); same products in the same
+// order (bias first, taps 0..8), so the same results.  The
+// block's 256 pixels are consecutive, so their outputs form one contiguous run of 512 CO
+// bytes: each thread puts its pixel's channels in LDS and the block then writes the run in
+// 16-byte pieces with consecutive lanes on consecutive pieces.
+template <int CO>
+__global__ void __launch_bounds__(256)
+conv_in_fixed_kernel(const float* __restrict__ fbp, float inv_s, const float* __restrict__ w,
+                     const float* __restrict__ bias, uint16_t* __restrict__ y, int H, int W,
+                     int npx) {
+  constexpr int NC = CO / 8;  // 16-byte pieces per pixel
+  __shared__ u16x8 so[256 * NC];
+  __shared__ float4 sf[CO * 3];  // [channel][9 taps, bias, 2 unused]: broadcast reads
+  for (int e = threadIdx.x; e < CO * 12; e += 256) {
+    const int ch = e / 12, k = e - ch * 12;
+    reinterpret_cast<float*>(sf)[e] = k < 9 ? w[ch * 9 + k] : (k == 9 ? bias[ch] : 0.f);
+  }
+  __syncthreads();
+  const int p0 = blockIdx.x * 256, p = p0 + threadIdx.x;
+  if (p < npx) {
+    const int HW = H * W, b = p / HW, rem = p - b * HW, r = rem / W, c = rem - r * W;
+    float u[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int yy = r + tap / 3 - 1, xx = c + tap % 3 - 1;
+      u[tap] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                   ? fbp[(size_t)b * HW + (size_t)yy * W + xx] * inv_s : 0.f;
+    }
+#pragma unroll
+    for (int c0 = 0; c0 < CO; c0 += 8) {
+      u16x8 out;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float4 wa = sf[(c0 + j) * 3], wb = sf[(c0 + j) * 3 + 1], wc = sf[(c0 + j) * 3 + 2];
+        const float wt[9] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w, wc.x};
+        float a = wc.y;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) a = fmaf(wt[tap], u[tap], a);
+        out[j] = f2bf(fmaxf(a, 0.f));
+      }
+      // piece index rotated by the pixel so that neighbouring lanes hit different banks
+      so[threadIdx.x * NC + ((c0 / 8 + threadIdx.x) % NC)] = out;
+    }
+  }
+  __syncthreads();
+  const int nval = min(256, npx - p0) * NC;
+#pragma unroll
+  for (int k0 = 0; k0 < 256 * NC; k0 += 256) {
+    const int k = k0 + threadIdx.x, px = k / NC, pc = k % NC;
+    if (k < nval) st8(y + ((size_t)p0 * NC + k) * 8, so[px * NC + ((pc + px) % NC)]);
   }
 }
 
@@ -800,7 +886,23 @@ unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float* bias,
                       uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
                       int B, int H, int W, bool relu, hipStream_t st, const uint16_t* xu, int ldu,
-                      int cu, uint16_t* pool, int ldp) {
+                      int cu, uint16_t* pool, int ldp, const NnHead* head) {
+  if (head) {
+    if (!relu || !bias || mask || xu || pool || (cout != 32 && cout != 64) || cin % 32 || ldx % 8 ||
+        B < 1 ||
+        H < 1 || W < 1 || !head->hw || !head->hb || !head->fbp || !head->x0)
+      return hipErrorInvalidValue;
+    const int ntx = (W + 15) / 16, nty = (H + 15) / 16;
+    if (cout == 64)
+      hipLaunchKernelGGL((conv3x3_tile_kernel<64, 4, true, true, false, false, false, true>),
+                         dim3(ntx * nty, B), dim3(256), 0, st, x, ldx, w, bias, nullptr, 0, nullptr,
+                         0, cin, H, W, ntx, nty, nullptr, 0, 0, nullptr, 0, *head);
+    else
+      hipLaunchKernelGGL((conv3x3_tile_kernel<32, 4, true, true, false, false, false, true>),
+                         dim3(ntx * nty, B), dim3(256), 0, st, x, ldx, w, bias, nullptr, 0, nullptr,
+                         0, cin, H, W, ntx, nty, nullptr, 0, 0, nullptr, 0, *head);
+    return hipGetLastError();
+  }
   if (cin % 32 || cout % 32 || ldx % 8 || ldy % 8 || ldy < cout || B < 1 || H < 1 || W < 1)
     return hipErrorInvalidValue;
   if (mask && (ldm % 8 || ldm < cout)) return hipErrorInvalidValue;
@@ -813,9 +915,9 @@ hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float
 #define CV(BN, RPW, R, BI, M, U, PO)                                                              \
   do {                                                                                            \
     const int nty = (H + 4 * RPW - 1) / (4 * RPW);                                                \
-    hipLaunchKernelGGL((conv3x3_tile_kernel<BN, RPW, R, BI, M, U, PO>),                            \
+    hipLaunchKernelGGL((conv3x3_tile_kernel<BN, RPW, R, BI, M, U, PO, false>),                     \
                        dim3(ntx * nty * (cout / BN), B), dim3(256), 0, st, x, ldx, w, bias, y, ldy, \
-                       mask, ldm, cin, H, W, ntx, nty, xu, ldu, cu, pool, ldp);                   \
+                       mask, ldm, cin, H, W, ntx, nty, xu, ldu, cu, pool, ldp, NnHead{});         \
   } while (0)
 #define CV_FORMS(BN, RPW)                                                        \
   if (relu && bi && !m && up && !pl) CV(BN, RPW, true, true, false, true, false); \
@@ -900,8 +1002,15 @@ hipError_t nn_conv_in(const float* fbp, float inv_s, const float* w, const float
                       uint16_t* y, int cout, int B, int H, int W, hipStream_t st) {
   if (cout % 8 || cout > CIN_MAXC) return hipErrorInvalidValue;
   const size_t n = (size_t)B * H * W;
-  hipLaunchKernelGGL(conv_in_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, fbp, inv_s, w,
-                     bias, y, cout, H, W, B * H * W);
+  if (cout == 32)
+    hipLaunchKernelGGL(conv_in_fixed_kernel<32>, dim3(blocks_for(n, 256)), dim3(256), 0, st, fbp,
+                       inv_s, w, bias, y, H, W, B * H * W);
+  else if (cout == 64)
+    hipLaunchKernelGGL(conv_in_fixed_kernel<64>, dim3(blocks_for(n, 256)), dim3(256), 0, st, fbp,
+                       inv_s, w, bias, y, H, W, B * H * W);
+  else
+    hipLaunchKernelGGL(conv_in_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, fbp, inv_s, w,
+                       bias, y, cout, H, W, B * H * W);
   return hipGetLastError();
 }
 
