@@ -826,7 +826,7 @@ def run_hbm_rates(torch, dev) -> int:
     half = nbytes // 8
     acc = torch.empty((), dtype=torch.float32, device=dev)
     cases = {
-        "read": (lambda: torch.sum(a, out=acc), nbytes),
+        "read": (lambda: torch.sum(a, dim=0, out=acc), nbytes),
         "write": (lambda: b.fill_(1.0), nbytes),
         "copy": (lambda: torch.mul(a[:half], 1.0, out=b[:half]), nbytes),
     }
