@@ -101,12 +101,15 @@ def _net_case(levels=3, H=48, W=40, B=2, seed=0, base=32):
     return arch, theta, fbp, target
 
 
-@pytest.mark.parametrize("levels,H,W", [(3, 48, 40), (4, 64, 72), (1, 16, 24)])
-def test_network_forward(levels, H, W):
+# 64 base channels: the 64-channel forms of the first layer and of the head-writing last
+# convolution
+@pytest.mark.parametrize("levels,H,W,base", [(3, 48, 40, 32), (4, 64, 72, 32), (1, 16, 24, 32),
+                                             (2, 40, 56, 64)])
+def test_network_forward(levels, H, W, base):
     from paper_2603_28756_amd import tomo
-    arch, theta, fbp, _ = _net_case(levels, H, W)
+    arch, theta, fbp, _ = _net_case(levels, H, W, base=base)
     s = 1.3
-    net = tomo.UNet(H, W, levels=levels, base=32, max_batch=3)
+    net = tomo.UNet(H, W, levels=levels, base=base, max_batch=3)
     assert net.n_params == arch.n_params()
     net.set_params(torch.as_tensor(theta, dtype=torch.float32))
     x0 = net.forward(torch.as_tensor(fbp, dtype=torch.float32, device=dev()).contiguous(), s)
