@@ -120,30 +120,34 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
 #pragma unroll
       for (int i = 0; i < 4; ++i) hwv[j][i] = hd.hw[16 * j + 4 * (lane >> 4) + i];
   }
-  for (int c0 = 0; c0 < cin; c0 += 32) {
-    // staging element e: input pixel e / 4 (halo tile, row-major) channels 8 (e % 4) .. +7,
-    // or weight row e / 4 = tap * BN + co, channels 8 (e % 4) .. +7; LDS byte offset 16 e.
-    // Elements t + 256 i of one wave are 64 consecutive 16-byte slots, so each goes straight
-    // from memory to LDS (global_load_lds_dwordx4: lane l of the wave writes its wave base
-    // + 16 l), with no registers in between.  A halo pixel outside the image loads a pixel
-    // inside it and is overwritten with zeros once the copies have landed.
-    bool zero_a[T::NA];
+  // staging element e: input pixel e / 4 (halo tile, row-major) channels 8 (e % 4) .. +7,
+  // or weight row e / 4 = tap * BN + co, channels 8 (e % 4) .. +7; LDS byte offset 16 e.
+  // Elements t + 256 i of one wave are 64 consecutive 16-byte slots, so each goes straight
+  // from memory to LDS (global_load_lds_dwordx4: lane l of the wave writes its wave base
+  // + 16 l), with no registers in between.  A halo pixel outside the image loads a pixel
+  // inside it and is overwritten with zeros once the copies have landed.
+  bool zero_a[T::NA];
+  int src_a[T::NA];  // clamped pixel of each element, as (row, column) packed
+#pragma unroll
+  for (int i = 0; i < T::NA; ++i) {
+    const int e = t + 256 * i;
+    const int pix = e >> 2;
+    const int hy = pix / T::HW_, hx = pix - hy * T::HW_;
+    const int gy = y0 + hy - 1, gx = x0 + hx - 1;
+    zero_a[i] = e < T::A_EL && !(gy >= 0 && gy < H && gx >= 0 && gx < W);
+    src_a[i] = (min(max(gy, 0), H - 1) << 16) | min(max(gx, 0), W - 1);
+  }
+  auto stage = [&](int c0, uint16_t* da, uint16_t* db) {
 #pragma unroll
     for (int i = 0; i < T::NA; ++i) {
       const int e = t + 256 * i;
-      zero_a[i] = false;
       if (e < T::A_EL) {
-        const int pix = e >> 2, q = (e & 3) * 8;
-        const int hy = pix / T::HW_, hx = pix - hy * T::HW_;
-        int gy = y0 + hy - 1, gx = x0 + hx - 1;
-        zero_a[i] = !(gy >= 0 && gy < H && gx >= 0 && gx < W);
-        gy = min(max(gy, 0), H - 1);
-        gx = min(max(gx, 0), W - 1);
+        const int q = (e & 3) * 8, gy = src_a[i] >> 16, gx = src_a[i] & 0xffff;
         const uint16_t* src =
             (UPCAT && c0 < cu)
                 ? xu + (((size_t)blockIdx.y * (H / 2) + gy / 2) * (W / 2) + gx / 2) * ldu + c0 + q
                 : x + (img + (size_t)gy * W + gx) * ldx + c0 - (UPCAT ? cu : 0) + q;
-        __builtin_amdgcn_global_load_lds(src, lds_ptr(sa + (256 * i + 64 * wave) * 8), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src, lds_ptr(da + (256 * i + 64 * wave) * 8), 16, 0, 0);
       }
     }
 #pragma unroll
@@ -153,27 +157,37 @@ conv3x3_tile_kernel(const uint16_t* __restrict__ x, int ldx, const uint16_t* __r
         const int q = (e & 3) * 8, rest = e >> 2;
         const int co = rest % BN, tap = rest / BN;
         __builtin_amdgcn_global_load_lds(w + ((size_t)(co0 + co) * 9 + tap) * cin + c0 + q,
-                                         lds_ptr(sb + (256 * i + 64 * wave) * 8), 16, 0, 0);
+                                         lds_ptr(db + (256 * i + 64 * wave) * 8), 16, 0, 0);
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // the copies of this thread have landed in LDS
+  };
+  // wait for this thread's copies, zero its out-of-image halo elements, publish the chunk
+  auto land = [&](uint16_t* da) {
+    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int i = 0; i < T::NA; ++i)
-      if (zero_a[i]) st8(sa + (t + 256 * i) * 8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+      if (zero_a[i]) st8(da + (t + 256 * i) * 8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
     __syncthreads();
+  };
+  auto compute = [&](const uint16_t* ca, const uint16_t* cb) {
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int ky = tap / 3, kx = tap % 3;
       u16x8 b[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) b[j] = ld8(sb + (tap * BN + j * 16 + lc) * 32 + kq);
+      for (int j = 0; j < NJ; ++j) b[j] = ld8(cb + (tap * BN + j * 16 + lc) * 32 + kq);
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
-        const u16x8 a = ld8(sa + ((wave * RPW + r + ky) * T::HW_ + lc + kx) * 32 + kq);
+        const u16x8 a = ld8(ca + ((wave * RPW + r + ky) * T::HW_ + lc + kx) * 32 + kq);
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[r][j] = mfma(b[j], a, acc[r][j]);
       }
     }
+  };
+  for (int c0 = 0; c0 < cin; c0 += 32) {
+    stage(c0, sa, sb);
+    land(sa);
+    compute(sa, sb);
     __syncthreads();
   }
   // lane holds channels co0 + 16 j + cq + i (i = 0..3) of pixel x0 + lc in row
