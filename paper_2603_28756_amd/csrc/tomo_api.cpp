@@ -54,6 +54,9 @@ struct Level {
   size_t off_prow = 0, off_pw = 0;  // point-spread grid lists (row pointers, float64 weights)
   size_t off_czc = 0, off_czf = 0, off_czb = 0;  // radial chirp-z tables (chirp, factor, B)
   int v_fwd = 1, v_cc = 1, v_inv = 1;  // tile variants of passes R, C, R'
+  // the level's PSF precompute as one graph, captured with tile variants psf_key
+  hipGraphExec_t psf_exec = nullptr;
+  int psf_key = -1;
   int chunks = 1;  // slice chunks that passes R, C, R' run through one after the other
 };
 
@@ -607,7 +610,7 @@ tomo_status toeplitz_passes(tomo_plan p, const Level& l, int mode, int nz, const
 // iteration, on the PSF stream with the PSF's own scratch, iterate and spectrum buffers (so
 // that it can run beside the back-projections of the plan's stream).  lambda, L and 1 / L
 // stay on the device (off_lvl); nothing here waits for the host.
-tomo_status psf_level(tomo_plan p, Level& l, int li) {
+tomo_status psf_level_launches(tomo_plan p, Level& l, int li) {
   hipStream_t st = p->fstream;
   const GridGeom gg = psf_geom(p, l);
   const PsfScratch ps = psf_scratch(p, l);
@@ -645,6 +648,54 @@ tomo_status psf_level(tomo_plan p, Level& l, int li) {
   // L = 1.01 lambda + 2 beta rho''(0) (a bound on the Hessian of the whole objective)
   HIPCHK(p, launch_lipschitz(sc, 1.01, 2.0 * p->g.beta * p->rho2_0,
                              p->at<double>(p->off_lvl) + 3 * (size_t)li, st));
+  return TOMO_OK;
+}
+
+void drop_psf_graphs(tomo_plan p) {
+  bool any = false;
+  for (auto& l : p->lv) any = any || l.psf_exec;
+  if (!any) return;
+  if (p->fstream) (void)hipStreamSynchronize(p->fstream);
+  for (auto& l : p->lv) {
+    if (l.psf_exec) (void)hipGraphExecDestroy(l.psf_exec);
+    l.psf_exec = nullptr;
+    l.psf_key = -1;
+  }
+}
+
+// The PSF precompute of level l on the PSF stream: its ~130 launches (spectrum, 30 power
+// iterations of four kernels each on one slice, step constant) are captured once into a
+// graph and replayed, so the host spends one launch on them instead of keeping the plan's
+// own stream waiting behind them.  Launched one by one when kernel timing is on or graphs
+// are off.  The graph holds the workspace pointers and the level's tile variants; it is
+// captured again when the tiles change and dropped with the workspace.
+tomo_status psf_level(tomo_plan p, Level& l, int li) {
+  if (!p->use_graphs || p->tmask != 0) return psf_level_launches(p, l, li);
+  const int key = l.v_fwd * 9 + l.v_cc * 3 + l.v_inv;
+  if (l.psf_exec && l.psf_key != key) {
+    HIPCHK(p, hipStreamSynchronize(p->fstream));
+    (void)hipGraphExecDestroy(l.psf_exec);
+    l.psf_exec = nullptr;
+  }
+  if (!l.psf_exec) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(p, hipStreamBeginCapture(p->fstream, hipStreamCaptureModeRelaxed));
+    const tomo_status s = psf_level_launches(p, l, li);
+    hipError_t e = hipStreamEndCapture(p->fstream, &graph);
+    if (s != TOMO_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(p, TOMO_ERR_HIP, "PSF graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&l.psf_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      l.psf_exec = nullptr;
+      return fail(p, TOMO_ERR_HIP, "PSF graph instantiate: %s", hipGetErrorString(e));
+    }
+    l.psf_key = key;
+  }
+  HIPCHK(p, hipGraphLaunch(l.psf_exec, p->fstream));
   return TOMO_OK;
 }
 
@@ -1000,6 +1051,7 @@ tomo_status tomo_plan_set_workspace(tomo_plan p, void* dev, size_t bytes) {
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);  // captured with the old pointers
   p->graphs.clear();
   if (p->fstream) HIPCHK(p, hipStreamSynchronize(p->fstream));  // a PSF precompute may still write
+  drop_psf_graphs(p);
   p->ws = static_cast<char*>(dev);
   p->ws_bytes = bytes;
   p->tables_ready = false;
@@ -2057,6 +2109,7 @@ tomo_status tomo_plan_destroy(tomo_plan p) {
   }
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  drop_psf_graphs(p);
   if (p->gstream) {
     (void)hipStreamSynchronize(p->gstream);
     (void)hipStreamDestroy(p->gstream);
