@@ -58,3 +58,29 @@ def test_gradient_and_normal_wait_for_the_precompute():
     plan.apply_normal(xd, out2)
     torch.cuda.synchronize()
     assert np.array_equal(to_np(out1), to_np(out2))
+
+
+def test_replayed_precompute_matches_direct_launches_and_follows_tile_changes():
+    """The precompute of a level is captured once into a graph and replayed; launched one by
+    one (kernel timing on), captured, replayed, and captured again after the tile variants
+    change, it gives the same spectrum, lambda and L bit for bit."""
+    from paper_2603_28756_amd import tomo
+    n, nz, nd = 128, 2, 182
+    _, ang, _, _ = problem(n, nz, 45, nd, seed=23)
+    plan = make_plan(n, nz, ang, nd)
+    plan.timing_enable(range(tomo.T_COUNT))  # direct launches
+    plan.precompute_psf()
+    fk0, L0, lam0 = plan.psf_info()
+    plan.timing_enable([])
+    runs = []
+    for _ in range(2):  # captured, then replayed
+        plan.precompute_psf()
+        runs.append(plan.psf_info())
+    sched = plan.tiles()
+    sched[0].update({"rows_fwd": 0, "cols_conv": 2, "rows_inv": 0})
+    plan.tiles(sched)
+    plan.precompute_psf()  # captured again with the new tiles
+    runs.append(plan.psf_info())
+    for fk, L, lam in runs:
+        assert np.array_equal(to_np(fk), to_np(fk0))
+        assert L == L0 and lam == lam0
