@@ -45,8 +45,8 @@ extern "C" {
 
 typedef struct tomo_unet_s* tomo_unet;
 
-/* Create a network for images of height x width (multiples of 2^(levels-1)) and batches
- * up to max_batch.  levels 1..6; base_channels a multiple of 32, at most 256, with
+/* Create a network for images of height x width (multiples of 2^(levels-1), at most 32767)
+ * and batches up to max_batch.  levels 1..6; base_channels a multiple of 32, at most 256, with
  * base_channels 2^(levels-1) <= 1024.  Errors: INVALID_ARG, NO_DEVICE. */
 tomo_status tomo_unet_create(int32_t levels, int32_t base_channels, int32_t max_batch,
                              int32_t height, int32_t width, void* hip_stream, tomo_unet* out);
@@ -93,7 +93,7 @@ const char* tomo_unet_last_error(tomo_unet net);
 
 /* Layer-level entry points (bfloat16 arrays as uint16_t; NHWC [batch][H][W][ld], the tensor
  * occupying channels 0..C-1 from the given pointer, 16-byte aligned; cin, cout multiples of
- * 32; ld multiples of 8).
+ * 32; ld multiples of 8; H and W at most 32767).
  * tomo_nn_conv3x3: y = relu(bias + conv(x, w)) (relu = 1, bias required), or
  * y = bias + conv(x, w) (bias nullable), optionally times (mask > 0) (mask: bfloat16 with
  * channel count cout and stride ldm; no bias then).  w: bfloat16 [cout][3][3][cin].

@@ -347,8 +347,8 @@ tomo_status tomo_unet_create(int32_t levels, int32_t base_channels, int32_t max_
   if (height < div || width < div || height % div || width % div)
     return nfail(nullptr, TOMO_ERR_INVALID_ARG, "image %dx%d must be a positive multiple of %d", height,
                  width, div);
-  if ((int64_t)max_batch * height * width > (int64_t)1 << 30)
-    return nfail(nullptr, TOMO_ERR_INVALID_ARG, "batch x image too large");
+  if ((int64_t)max_batch * height * width > (int64_t)1 << 30 || height > 32767 || width > 32767)
+    return nfail(nullptr, TOMO_ERR_INVALID_ARG, "batch x image too large (height, width <= 32767)");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return nfail(nullptr, TOMO_ERR_NO_DEVICE, "no HIP device");
@@ -466,7 +466,8 @@ tomo_status tomo_nn_conv3x3(const uint16_t* x, int32_t ldx, const uint16_t* w, c
                             void* hip_stream) {
   if (!x || !w || !y) return nfail(nullptr, TOMO_ERR_INVALID_ARG, "NULL array");
   if (cin % 32 || cout % 32 || cin < 32 || cout < 32 || ldx < cin || ldy < cout || ldx % 8 || ldy % 8 ||
-      (mask && (ldm < cout || ldm % 8)) || batch < 1 || height < 1 || width < 1)
+      (mask && (ldm < cout || ldm % 8)) || batch < 1 || height < 1 || width < 1 || height > 32767 ||
+      width > 32767)
     return nfail(nullptr, TOMO_ERR_INVALID_ARG, "unsupported shape");
   if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(w)) % 16)
     return nfail(nullptr, TOMO_ERR_INVALID_ARG, "x and w must be 16-byte aligned");

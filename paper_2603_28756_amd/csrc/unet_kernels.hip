@@ -901,10 +901,11 @@ hipError_t nn_conv3x3(const uint16_t* x, int ldx, const uint16_t* w, const float
                       uint16_t* y, int ldy, const uint16_t* mask, int ldm, int cin, int cout,
                       int B, int H, int W, bool relu, hipStream_t st, const uint16_t* xu, int ldu,
                       int cu, uint16_t* pool, int ldp, const NnHead* head) {
+  // the staging packs a clamped (row, column) into 15 bits each
+  if (H > 32767 || W > 32767) return hipErrorInvalidValue;
   if (head) {
     if (!relu || !bias || mask || xu || pool || (cout != 32 && cout != 64) || cin % 32 || ldx % 8 ||
-        B < 1 ||
-        H < 1 || W < 1 || !head->hw || !head->hb || !head->fbp || !head->x0)
+        B < 1 || H < 1 || W < 1 || !head->hw || !head->hb || !head->fbp || !head->x0)
       return hipErrorInvalidValue;
     const int ntx = (W + 15) / 16, nty = (H + 15) / 16;
     if (cout == 64)

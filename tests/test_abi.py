@@ -110,6 +110,7 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 @pytest.mark.parametrize("args", [
     (0, 32, 1, 64, 64), (7, 32, 1, 64, 64), (4, 16, 1, 64, 64), (4, 48, 1, 64, 64), (4, 32, 0, 64, 64),
     (4, 32, 1, 60, 64), (4, 32, 1, 64, 4), (6, 64, 1, 64, 64), (1, 288, 1, 64, 64),
+    (1, 32, 1, 32768, 8),
 ])
 def test_unet_create_rejects_bad_shapes(args):
     _, lib = _lib()
@@ -136,6 +137,8 @@ def test_nn_entry_points_validate_on_host():
     assert lib.tomo_nn_conv3x3(None, 32, p, None, p, 32, None, 0, 32, 32, 1, 4, 4, 0, None) == 1
     assert lib.tomo_nn_conv3x3(ctypes.c_void_p(258), 32, p, None, p, 32, None, 0, 32, 32, 1, 4, 4, 0, None) == 1
     assert lib.tomo_nn_conv3x3(p, 32, p, None, p, 32, None, 0, 32, 32, 1, 4, 4, 1, None) == 1  # ReLU needs bias
+    assert lib.tomo_nn_conv3x3(p, 32, p, None, p, 36, None, 0, 32, 32, 1, 4, 4, 0, None) == 1  # ld % 8
+    assert lib.tomo_nn_conv3x3(p, 32, p, None, p, 32, None, 0, 32, 32, 1, 32768, 4, 0, None) == 1  # H
     n = ctypes.c_size_t()
     assert lib.tomo_nn_wgrad_scratch(32, 64, 1000, ctypes.byref(n)) == 0 and n.value > 0
     assert lib.tomo_nn_wgrad_scratch(30, 64, 1000, ctypes.byref(n)) == 1
