@@ -24,6 +24,8 @@ when it matches the current kernel sources) over the wall time of the graph-repl
 iteration loop, against 8 TB/s; and the same for the compulsory 20.5 B/voxel and the
 three-pass 56 B/voxel model.  Precompute and iteration loop are also timed separately
 (median of 5).
+--hbm-rates: only the HBM rates plain streaming kernels reach on this part (a sum, a fill and
+an elementwise copy of 512 MiB), the practical ceiling beside the 8 TB/s the rooflines use.
 cpu_baseline: the FP64 oracle's own iteration (Toeplitz product by numpy FFTs, prior,
 update) on a 4-slice slab of the same volume, run in one process per host core (the box's
 CPU share) at once; plus the oracle's direct A^T(A x) against its Toeplitz product at
