@@ -83,33 +83,44 @@ __global__ __launch_bounds__(SO_NT) void slice_objective_kernel(
   if (threadIdx.x == 0) part[(idx_t)z * gridDim.x + blockIdx.x] = s;
 }
 
-// Block z decides for slice z (per_slice) or for the whole volume (every block takes the same
-// decision from the same fixed-order sums): the network's start xb is kept unless its
-// objective exceeds the FBP start's or is not finite; a kept slice is copied over xa.
-__global__ __launch_bounds__(SO_NT) void select_start_kernel(
+// Thread z decides for slice z (per_slice) or for the whole volume (every thread takes the
+// same decision from the same fixed-order sums): the network's start xb is kept unless its
+// objective exceeds the FBP start's or is not finite.
+__global__ __launch_bounds__(64) void start_choice_kernel(
     const double* __restrict__ pa, const double* __restrict__ pb, int nblk, int nz, int per_slice,
-    float* __restrict__ xa, const float* __restrict__ xb, int N, int32_t* __restrict__ choice,
-    int32_t* __restrict__ choice_user) {
-  __shared__ int keep;
-  const int z = blockIdx.x;
-  if (threadIdx.x == 0) {
-    const int z0 = per_slice ? z : 0, z1 = per_slice ? z + 1 : nz;
-    double fa = 0.0, fb = 0.0;
-    for (int zz = z0; zz < z1; ++zz)
-      for (int k = 0; k < nblk; ++k) {
-        fa += pa[(idx_t)zz * nblk + k];
-        fb += pb[(idx_t)zz * nblk + k];
-      }
-    keep = (isfinite(fb) && !(fb > fa)) ? 1 : 0;
-    choice[z] = keep;
-    if (choice_user) choice_user[z] = keep;
-  }
-  __syncthreads();
-  if (!keep) return;
+    int32_t* __restrict__ choice, int32_t* __restrict__ choice_user) {
+  const int z = blockIdx.x * 64 + threadIdx.x;
+  if (z >= nz) return;
+  const int z0 = per_slice ? z : 0, z1 = per_slice ? z + 1 : nz;
+  double fa = 0.0, fb = 0.0;
+  for (int zz = z0; zz < z1; ++zz)
+    for (int k = 0; k < nblk; ++k) {
+      fa += pa[(idx_t)zz * nblk + k];
+      fb += pb[(idx_t)zz * nblk + k];
+    }
+  const int keep = (isfinite(fb) && !(fb > fa)) ? 1 : 0;
+  choice[z] = keep;
+  if (choice_user) choice_user[z] = keep;
+}
+
+// A kept slice z (choice[z]) is copied from xb over xa with gridDim.x blocks per slice,
+// 16 bytes per access when every slice starts 16-byte aligned (N^2 % 4 == 0; the volumes
+// start 256-byte aligned), else 4.
+__global__ __launch_bounds__(SO_NT) void start_copy_kernel(float* __restrict__ xa,
+                                                           const float* __restrict__ xb, int N,
+                                                           const int32_t* __restrict__ choice) {
+  const int z = blockIdx.y;
+  if (!choice[z]) return;
   const idx_t plane = (idx_t)N * N;
   float* dst = xa + z * plane;
   const float* src = xb + z * plane;
-  for (idx_t i = threadIdx.x; i < plane; i += SO_NT) dst[i] = src[i];
+  const idx_t i0 = (idx_t)blockIdx.x * SO_NT + threadIdx.x, step = (idx_t)gridDim.x * SO_NT;
+  if (plane % 4 == 0) {
+    for (idx_t i = i0; i < plane / 4; i += step)
+      reinterpret_cast<float4*>(dst)[i] = reinterpret_cast<const float4*>(src)[i];
+  } else {
+    for (idx_t i = i0; i < plane; i += step) dst[i] = src[i];
+  }
 }
 
 }  // namespace
@@ -124,8 +135,9 @@ hipError_t launch_slice_objective(const float* x, const float* tx, const float* 
 hipError_t launch_select_start(const double* pa, const double* pb, int nz, int per_slice,
                                float* xa, const float* xb, int N, int32_t* choice,
                                int32_t* choice_user, hipStream_t st) {
-  hipLaunchKernelGGL(select_start_kernel, dim3(nz), dim3(SO_NT), 0, st, pa, pb, kObjBlocks, nz,
-                     per_slice, xa, xb, N, choice, choice_user);
+  hipLaunchKernelGGL(start_choice_kernel, dim3((nz + 63) / 64), dim3(64), 0, st, pa, pb, kObjBlocks,
+                     nz, per_slice, choice, choice_user);
+  hipLaunchKernelGGL(start_copy_kernel, dim3(64, nz), dim3(SO_NT), 0, st, xa, xb, N, choice);
   return hipGetLastError();
 }
 
