@@ -129,15 +129,19 @@ struct ObjParams {
   int quadratic;      // 1 when p == q
 };
 constexpr int kObjBlocks = 64;  // blocks per slice of the start objective
-// part [nz][kObjBlocks]: per-block float64 sums of 1/2 x T x - x b + beta (forward-pair rho).
-hipError_t launch_slice_objective(const float* x, const float* tx, const float* b, int N, int nz,
-                                  const ObjParams& op, double* part, hipStream_t st);
-// Per slice (per_slice = 1) or for the whole volume: keep xb where its objective (pb) does not
-// exceed xa's (pa) and is finite, copying it over xa; choice[z] (and choice_user[z], nullable)
-// receive 1 where xb was kept.
-hipError_t launch_select_start(const double* pa, const double* pb, int nz, int per_slice,
-                               float* xa, const float* xb, int N, int32_t* choice,
-                               int32_t* choice_user, hipStream_t st);
+// part [nz][kObjBlocks]: per-block float64 sums of F(xb) - F(xa), F(x) = 1/2 x T x - x b +
+// beta (forward-pair rho), from ts = T (xa + xb).
+hipError_t launch_slice_objective_diff(const float* xa, const float* xb, const float* ts,
+                                       const float* b, int N, int nz, const ObjParams& op,
+                                       double* part, hipStream_t st);
+// out[i] = a[i] + b[i], i < n
+hipError_t launch_add(const float* a, const float* b, float* out, idx_t n, hipStream_t st);
+// Per slice (per_slice = 1) or for the whole volume: keep xb where the objective difference
+// F(xb) - F(xa) (partials pd) is finite and not positive, copying it over xa; choice[z] (and
+// choice_user[z], nullable) receive 1 where xb was kept.
+hipError_t launch_select_start(const double* pd, int nz, int per_slice, float* xa,
+                               const float* xb, int N, int32_t* choice, int32_t* choice_user,
+                               hipStream_t st);
 
 // ---- direct (non-Toeplitz) forward projection ----------------------------------------------
 // grid[z][cell], slices z0 .. z0+nzb-1: deapodised image embedded at offset -N/2 (mod M).

@@ -215,7 +215,7 @@ void layout(tomo_plan p) {
   size_t maxprior = 1;
   for (const Level& l : p->lv) maxprior = std::max(maxprior, (size_t)prior_blocks(l.n, p->nz));
   p->off_ppartials = take(maxprior * 4 * sizeof(double));
-  p->off_objpart = take(2 * (size_t)p->nz * kObjBlocks * sizeof(double));
+  p->off_objpart = take((size_t)p->nz * kObjBlocks * sizeof(double));
   p->off_resid = take((size_t)p->nz * na * fin.nd * sizeof(float));
   p->off_rpart = take((size_t)radial_idft_blocks(fin.nd, p->nz * na) * sizeof(double));
   p->off_choice = take((size_t)p->nz * sizeof(int32_t));
@@ -835,18 +835,17 @@ tomo_status learned_start(tomo_plan p, const Level& l, const float* b, int cur, 
     HIPCHK(p, hipEventRecord(p->nev_join, net.stream));
     HIPCHK(p, hipStreamWaitEvent(st, p->nev_join, 0));
   }
-  double* pa = p->at<double>(p->off_objpart);
-  double* pb = pa + (size_t)p->nz * kObjBlocks;
-  const float* cand[2] = {xa, xb};
-  double* parts[2] = {pa, pb};
-  for (int k = 0; k < 2; ++k) {
-    HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, st));
-    int nb = 0;
-    tomo_status s = toeplitz_passes(p, l, MODE_POWER, p->nz, cand[k], cand[k], nullptr, ty, false, &nb);
-    if (s != TOMO_OK) return s;
-    HIPCHK(p, launch_slice_objective(cand[k], ty, b, l.n, p->nz, p->op, parts[k], st));
-  }
-  HIPCHK(p, launch_select_start(pa, pb, p->nz, p->g.neighbours == 8 ? 1 : 0, xa, xb, l.n,
+  // F(xb) - F(xa) from one Toeplitz product, T (xa + xb) (the third iterate buffer holds the
+  // sum), instead of one product per candidate
+  double* pd = p->at<double>(p->off_objpart);
+  float* sum = p->xbuf((cur + 2) % 3);
+  HIPCHK(p, launch_add(xa, xb, sum, (idx_t)p->nz * plane, st));
+  HIPCHK(p, launch_set_scalars(p->scal(), SC_PSCALE, 1, nullptr, 1.0, st));
+  int nb = 0;
+  tomo_status s = toeplitz_passes(p, l, MODE_POWER, p->nz, sum, sum, nullptr, ty, false, &nb);
+  if (s != TOMO_OK) return s;
+  HIPCHK(p, launch_slice_objective_diff(xa, xb, ty, b, l.n, p->nz, p->op, pd, st));
+  HIPCHK(p, launch_select_start(pd, p->nz, p->g.neighbours == 8 ? 1 : 0, xa, xb, l.n,
                                 p->at<int32_t>(p->off_choice), o->init_choice_dev, st));
   return TOMO_OK;
 }
