@@ -809,9 +809,10 @@ bool in_domain(tomo_plan p, const Level& l, const UnetView& v) {
 }
 
 // Learned start on level l: the FBP image in xbuf(cur) is mapped by the network into
-// xbuf(alt); both starts' float64 objectives (T x into the y volume) decide, per slice with the
-// 8-neighbour prior or for the whole volume with the 26-neighbour prior, which one xbuf(cur)
-// holds afterwards (FBP unless the network's objective is not larger).
+// xbuf(alt); the float64 difference of the two starts' objectives (from T of their sum, into
+// the y volume) decides, per slice with the 8-neighbour prior or for the whole volume with the
+// 26-neighbour prior, which one xbuf(cur) holds afterwards (FBP unless the network's objective
+// is not larger).
 tomo_status learned_start(tomo_plan p, const Level& l, const float* b, int cur, const UnetView& net,
                           const tomo_recon_opts_t* o) {
   hipStream_t st = p->stream;
