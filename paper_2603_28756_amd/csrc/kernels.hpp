@@ -43,9 +43,12 @@ void tile_shapes(int P, int v_fwd, int v_cc, int v_inv, int* fwd, int* cc, int* 
 
 // ---- hot path (float32 data, float64 reductions) --------------------------------------
 // Pass R: y = x_k + mu (x_k - x_{k-1}) (or scale * x_k in power mode) -> row R2C -> S1.
+// Power mode with pprev: scale = 1 / sqrt(sum of slot 0 of the nprev partial sums pprev[4 b])
+// (the previous power step's pass R'), else scal[SC_PSCALE].
 hipError_t launch_rows_fwd(int P, int v, int mode, const float* xk, const float* xkm1,
                            const double* scal, cpx<float>* S1, const cpx<float>* tw,
-                           int N, int nz, hipStream_t st);
+                           int N, int nz, hipStream_t st, const double* pprev = nullptr,
+                           int nprev = 0);
 // Pass C: column FFT, x FK, inverse column FFT, keep N rows: S1 -> S2.
 hipError_t launch_cols_conv(int P, int v, const cpx<float>* S1, cpx<float>* S2, const float* fk,
                             const float* fkn, const cpx<float>* tw, int N, int nz, hipStream_t st);

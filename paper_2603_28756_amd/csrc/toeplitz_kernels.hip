@@ -148,15 +148,37 @@ TOMO_DEV void rows_fwd_body(unsigned char* smem, int blk, const float* __restric
   }
 }
 
+// MODE_POWER with pprev: the scale is 1 / ||T v|| of the previous power step, formed by every
+// block from that step's pass R' partial sums (slot 0, nprev blocks) in one fixed order, in
+// place of a separate one-block reduction launch between the steps.
 template <int P, int PAIRS, int MODE>
 __global__ void __launch_bounds__(PAIRS * (P / kE))
 rows_fwd_kernel(const float* __restrict__ xk, const float* __restrict__ xkm1,
                 const double* __restrict__ scal, cpx<float>* __restrict__ S1,
-                const cpx<float>* __restrict__ tw, int N, int n_pairs) {
+                const cpx<float>* __restrict__ tw, int N, int n_pairs,
+                const double* __restrict__ pprev, int nprev) {
   __shared__ __align__(16) unsigned char smem[rows_fwd_lds<P, PAIRS>()];
   float mu = 0.f, s = 1.f;
-  if constexpr (MODE == MODE_POWER) s = (float)scal[SC_PSCALE];
-  else mu = (float)scal[SC_MU];
+  if constexpr (MODE == MODE_POWER) {
+    if (pprev) {
+      constexpr int NT = PAIRS * (P / kE);
+      __shared__ double red[NT];
+      double a = 0.0;
+      for (int b = threadIdx.x; b < nprev; b += NT) a += pprev[(idx_t)b * 4];
+      red[threadIdx.x] = a;
+      __syncthreads();
+      for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+      }
+      const double wn = sqrt(red[0]);
+      s = wn > 0.0 ? (float)(1.0 / wn) : 0.f;
+    } else {
+      s = (float)scal[SC_PSCALE];
+    }
+  } else {
+    mu = (float)scal[SC_MU];
+  }
   rows_fwd_body<P, PAIRS, MODE>(smem, blockIdx.x, xk, xkm1, mu, s, S1, tw, N, n_pairs);
 }
 
@@ -1368,29 +1390,31 @@ constexpr int inv_pairs_v(int P, int v) {
 
 template <int P, int V>
 hipError_t rows_fwd_pv(int mode, const float* xk, const float* xkm1, const double* scal,
-                       cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st) {
+                       cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st,
+                       const double* pprev, int nprev) {
   constexpr int PAIRS = fwd_pairs_v(P, V);
   constexpr int NT = PAIRS * fft::Plan<P, kE>::TPF;
   const int n_pairs = nz * (N / 2);
   const dim3 grid((n_pairs + PAIRS - 1) / PAIRS);
   if (mode == MODE_POWER)
     hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_POWER>), grid, dim3(NT), 0, st, xk, xkm1,
-                       scal, S1, tw, N, n_pairs);
+                       scal, S1, tw, N, n_pairs, pprev, nprev);
   else if (mode == MODE_FISTA_Y)
     hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_FISTA_Y>), grid, dim3(NT), 0, st, xk, xkm1,
-                       scal, S1, tw, N, n_pairs);
+                       scal, S1, tw, N, n_pairs, nullptr, 0);
   else
     hipLaunchKernelGGL((rows_fwd_kernel<P, PAIRS, MODE_FISTA>), grid, dim3(NT), 0, st, xk, xkm1,
-                       scal, S1, tw, N, n_pairs);
+                       scal, S1, tw, N, n_pairs, nullptr, 0);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t rows_fwd_p(int v, int mode, const float* xk, const float* xkm1, const double* scal,
-                      cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st) {
-  if (v == 0) return rows_fwd_pv<P, 0>(mode, xk, xkm1, scal, S1, tw, N, nz, st);
-  if (v == 2) return rows_fwd_pv<P, 2>(mode, xk, xkm1, scal, S1, tw, N, nz, st);
-  return rows_fwd_pv<P, 1>(mode, xk, xkm1, scal, S1, tw, N, nz, st);
+                      cpx<float>* S1, const cpx<float>* tw, int N, int nz, hipStream_t st,
+                      const double* pprev, int nprev) {
+  if (v == 0) return rows_fwd_pv<P, 0>(mode, xk, xkm1, scal, S1, tw, N, nz, st, pprev, nprev);
+  if (v == 2) return rows_fwd_pv<P, 2>(mode, xk, xkm1, scal, S1, tw, N, nz, st, pprev, nprev);
+  return rows_fwd_pv<P, 1>(mode, xk, xkm1, scal, S1, tw, N, nz, st, pprev, nprev);
 }
 
 template <int P, int V>
@@ -1599,8 +1623,9 @@ hipError_t launch_fill_int(int* x, idx_t n, int v, hipStream_t st) {
 
 hipError_t launch_rows_fwd(int P, int v, int mode, const float* xk, const float* xkm1,
                            const double* scal, cpx<float>* S1, const cpx<float>* tw, int N,
-                           int nz, hipStream_t st) {
-#define CALL(PP) rows_fwd_p<PP>(v, mode, xk, xkm1, scal, S1, tw, N, nz, st)
+                           int nz, hipStream_t st, const double* pprev, int nprev) {
+  if (pprev && (mode != MODE_POWER || nprev < 1)) return hipErrorInvalidValue;
+#define CALL(PP) rows_fwd_p<PP>(v, mode, xk, xkm1, scal, S1, tw, N, nz, st, pprev, nprev)
   TOMO_PSWITCH(CALL)
 #undef CALL
 }

@@ -636,15 +636,22 @@ tomo_status psf_level_launches(tomo_plan p, Level& l, int li) {
   HIPCHK(p, launch_fill(v, (idx_t)l.n * l.n, 1.0f, st));
   HIPCHK(p, launch_set_scalars(sc, SC_PSCALE, 1, nullptr, 1.0, st));
   HIPCHK(p, launch_set_scalars(sc, SC_VNORM, 1, nullptr, (double)l.n, st));
+  // each step after the first takes its scale 1 / ||T v|| from the previous step's pass R'
+  // partial sums inside pass R; one finalize after the last step gives lambda (the iterate
+  // then has unit norm)
+  int nb_prev = 0;
   for (int it = 0; it < kPowerIters; ++it) {
     int nb = 0;
-    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, MODE_POWER, v, v, sc, S1, p->tw32(l.P), l.n, 1, st));
+    HIPCHK(p, launch_rows_fwd(l.P, l.v_fwd, MODE_POWER, v, v, sc, S1, p->tw32(l.P), l.n, 1, st,
+                              it > 0 ? part : nullptr, nb_prev));
     HIPCHK(p, launch_cols_conv(l.P, l.v_cc, S1, S2, fk, fkn, p->tw32(l.P), l.n, 1, st));
     HIPCHK(p, launch_rows_inv(l.P, l.v_inv, MODE_POWER, p->g.neighbours, false, S2, v, v, nullptr,
                               nullptr, w, part, sc, p->tw32(l.P), l.n, 1, p->pp, &nb, st));
-    HIPCHK(p, launch_finalize(MODE_POWER, part, nb, nullptr, 0, sc, nullptr, nullptr, nullptr, st));
+    nb_prev = nb;
     std::swap(v, w);
   }
+  if (kPowerIters > 1) HIPCHK(p, launch_set_scalars(sc, SC_VNORM, 1, nullptr, 1.0, st));
+  HIPCHK(p, launch_finalize(MODE_POWER, part, nb_prev, nullptr, 0, sc, nullptr, nullptr, nullptr, st));
   // L = 1.01 lambda + 2 beta rho''(0) (a bound on the Hessian of the whole objective)
   HIPCHK(p, launch_lipschitz(sc, 1.01, 2.0 * p->g.beta * p->rho2_0,
                              p->at<double>(p->off_lvl) + 3 * (size_t)li, st));
